@@ -1,0 +1,377 @@
+"""Pins of the CPU oracle to facts that do not come from the oracle itself.
+
+Each ``pin_*`` function takes a loaded oracle library and raises
+``AssertionError`` (or ``oracle.OracleError``) when the oracle disagrees with:
+
+* closed forms on sequence-valued columns (counts and sums computed from
+  arithmetic series, not by re-running a filter);
+* the paper's worked compaction example of section 3.2;
+* exact special cases (projections whose result is exactly representable);
+* exact rational arithmetic (``fractions``) and ``decimal`` exponentials;
+* brute force on tiny inputs with a different algorithm (nested-loop joins).
+
+The functions are shared by ``test_oracle_pins.py`` (the real oracle) and
+``test_oracle_mutants.py`` (oracles with planted mistakes, which must fail at
+least one pin).
+"""
+from __future__ import annotations
+
+import decimal
+import os
+from fractions import Fraction
+
+import numpy as np
+
+import oracle
+from paper_2003_01178_amd import datagen
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+I32_MIN, I32_MAX = -(2 ** 31), 2 ** 31 - 1
+
+
+def read_fixture(name):
+    rows = {}
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            k, *v = line.split()
+            rows[k] = [int(x) for x in v]
+    return rows
+
+
+# ---------------------------------------------------------------- selection --
+def _perm_column(n, k):
+    """y[i] = k*i mod n: a permutation of 0..n-1 when gcd(k, n) = 1."""
+    return ((np.arange(n, dtype=np.int64) * k) % n).astype(np.int32)
+
+
+def pin_select_closed_form(lib):
+    n, k = 10007, 7919                       # both prime
+    y = _perm_column(n, k)
+    kinv = pow(k, -1, n)
+    for lo, hi in [(0, n - 1), (0, 0), (n - 1, n - 1), (17, 4093), (5000, 5001), (100, 99)]:
+        out = oracle.select(y, lo, hi, lib=lib).astype(np.int64)
+        cnt = max(0, hi - lo + 1)
+        assert out.size == cnt, (lo, hi, out.size, cnt)
+        if cnt:
+            assert int(out.sum()) == (lo + hi) * cnt // 2
+            sq = (hi * (hi + 1) * (2 * hi + 1) - (lo - 1) * lo * (2 * lo - 1)) // 6
+            assert int((out * out).sum()) == sq
+            # values are reported in input order: their positions v*k^-1 mod n increase
+            pos = (out * kinv) % n
+            assert np.all(np.diff(pos) > 0)
+
+
+def pin_select_extremes(lib):
+    y = np.array([I32_MIN, -1, 0, 1, I32_MAX, I32_MIN, I32_MAX], dtype=np.int32)
+    assert list(oracle.select(y, I32_MIN, I32_MAX, lib=lib)) == list(y)
+    assert list(oracle.select(y, I32_MIN, I32_MIN, lib=lib)) == [I32_MIN, I32_MIN]
+    assert list(oracle.select(y, I32_MAX, I32_MAX, lib=lib)) == [I32_MAX, I32_MAX]
+    assert oracle.select(y, 2, -2, lib=lib).size == 0
+    assert oracle.select(y[:0], I32_MIN, I32_MAX, lib=lib).size == 0
+    # the selectivity encoding of the Q3 micro-benchmark: sigma 0 keeps nothing, 1 keeps all
+    col = np.array([0, 1, 2 ** 30, I32_MAX], dtype=np.int32)
+    assert oracle.select(col, *datagen.select_threshold_range(0.0), lib=lib).size == 0
+    assert oracle.select(col, *datagen.select_threshold_range(1.0), lib=lib).size == 4
+    assert oracle.select(col, *datagen.select_threshold_range(0.5), lib=lib).size == 2
+
+
+def pin_select_tile_example(lib):
+    fx = read_fixture("tile_example.txt")
+    y = np.array(fx["input"], dtype=np.int32)
+    t = fx["threads"][0]
+    # the fixture itself agrees with the counts and offsets the paper prints
+    counts = [sum(1 for i in range(th, y.size, t) if y[i] > fx["predicate_gt"][0]) for th in range(t)]
+    assert counts == fx["counts"]
+    assert [sum(counts[:i]) for i in range(t)] == fx["offsets"]
+    out = oracle.select(y, fx["predicate_gt"][0] + 1, I32_MAX, lib=lib)
+    assert out.size == fx["total"][0]
+    assert sorted(out.tolist()) == sorted(fx["thread_major_output"])
+
+
+def pin_select_bruteforce(lib):
+    rng = np.random.default_rng(7)
+    for n in (0, 1, 5, 63, 64, 65, 1000):
+        y = rng.integers(-50, 50, size=n, dtype=np.int32)
+        lo, hi = sorted(int(v) for v in rng.integers(-60, 60, size=2))
+        want = []
+        for v in y.tolist():
+            if lo <= v <= hi:
+                want.append(v)
+        assert oracle.select(y, lo, hi, lib=lib).tolist() == want
+
+
+# --------------------------------------------------------------- projection --
+def pin_project_exact(lib):
+    """x = i * 2^-20 -> 2*x1 + 3*x2 = (2*i1 + 3*i2) * 2^-20, exact in float32."""
+    rng = np.random.default_rng(11)
+    i1 = rng.integers(0, 2 ** 20, size=4096)
+    i2 = rng.integers(0, 2 ** 20, size=4096)
+    x1 = (i1 / 2 ** 20).astype(np.float32)
+    x2 = (i2 / 2 ** 20).astype(np.float32)
+    out = oracle.project(x1, x2, 2.0, 3.0, lib=lib)
+    want = np.array([(2 * a + 3 * b) / 2 ** 20 for a, b in zip(i1.tolist(), i2.tolist())],
+                    dtype=np.float32)
+    assert np.array_equal(out, want)
+    assert np.array_equal(oracle.project(x1, x2, 1.0, 0.0, lib=lib), x1)
+    assert np.array_equal(oracle.project(x1, x2, 0.0, 1.0, lib=lib), x2)
+    assert not np.any(oracle.project(x1, x2, 0.0, 0.0, lib=lib))
+
+
+def pin_project_rational(lib):
+    """Against exact rational arithmetic: within half an ulp of float32 (plus double rounding)."""
+    x1, x2 = datagen.project_columns(2000, workload=99)
+    for a, b in [(2.0, 3.0), (-1.5, 0.25), (3.0, -2.0)]:
+        out = oracle.project(x1, x2, a, b, lib=lib)
+        for k in range(x1.size):
+            exact = Fraction(a) * Fraction(float(x1[k])) + Fraction(b) * Fraction(float(x2[k]))
+            err = abs(Fraction(float(out[k])) - exact)
+            assert err <= abs(exact) * Fraction(1, 2 ** 24) * Fraction(1001, 1000) + Fraction(1, 2 ** 149), \
+                (a, b, k, float(out[k]), float(exact))
+
+
+def pin_project_sigmoid(lib):
+    """sigmoid(0) = 1/2 exactly, symmetry, and decimal-module reference values."""
+    z = np.zeros(3, dtype=np.float32)
+    assert np.all(oracle.project_sigmoid(z, z, 2.0, 3.0, lib=lib) == np.float32(0.5))
+    decimal.getcontext().prec = 40
+    x1 = np.array([0.25, 0.5, 1.0, 0.125, 0.75], dtype=np.float32)
+    x2 = np.array([0.5, 0.125, 0.0, 0.875, 1.0], dtype=np.float32)
+    out = oracle.project_sigmoid(x1, x2, 2.0, -3.0, lib=lib)
+    neg = oracle.project_sigmoid(x1, x2, -2.0, 3.0, lib=lib)
+    for k in range(x1.size):
+        t = decimal.Decimal(2) * decimal.Decimal(float(x1[k])) - 3 * decimal.Decimal(float(x2[k]))
+        ref = 1 / (1 + (-t).exp())
+        assert abs(decimal.Decimal(float(out[k])) - ref) <= ref * decimal.Decimal(2) ** -23
+        assert abs(float(out[k]) + float(neg[k]) - 1.0) <= 2 ** -23
+
+
+# --------------------------------------------------------------------- join --
+def _series(q, d, r):
+    return q * d * (d - 1) // 2 + r * (r - 1) // 2
+
+
+def pin_join_closed_form(lib):
+    """Keys a shuffled 0..D-1 with payload = key; fk[i] = i mod D."""
+    rng = np.random.default_rng(3)
+    for d, n in [(1, 10), (7, 100), (64, 1000), (1000, 12345)]:
+        key = rng.permutation(d).astype(np.int32)
+        fk = (np.arange(n) % d).astype(np.int32)
+        q, r = divmod(n, d)
+        assert oracle.join_sum(key, key, fk, lib=lib) == (_series(q, d, r), n)
+        # Q4 form SUM(A.v + B.v) with a probe payload of 1 per row
+        assert oracle.join_sum(key, key, fk, pval=np.ones(n, np.int32), lib=lib) == (_series(q, d, r) + n, n)
+        # sparse keys (bisection path): key*1000003 with payload = key
+        sp = (key.astype(np.int64) * 1000003 - 2 ** 30).astype(np.int32)
+        fsp = (fk.astype(np.int64) * 1000003 - 2 ** 30).astype(np.int32)
+        assert oracle.join_sum(sp, key, fsp, lib=lib) == (_series(q, d, r), n)
+        # build filter keeping keys = 0 mod 5: the matched keys are 0, 5, 10, ...
+        filt = (key % 5).astype(np.int32)
+        want_s = sum(i % d for i in range(n) if (i % d) % 5 == 0)
+        want_m = sum(1 for i in range(n) if (i % d) % 5 == 0)
+        assert oracle.join_sum(key, key, fk, bfilter=filt, flo=0, fhi=0, lib=lib) == (want_s, want_m)
+        assert oracle.join_sum(sp, key, fsp, bfilter=filt, flo=0, fhi=0, lib=lib) == (want_s, want_m)
+
+
+def pin_join_misses_and_width(lib):
+    key = np.arange(16, dtype=np.int32)
+    assert oracle.join_sum(key, key, np.arange(16, 40, dtype=np.int32), lib=lib) == (0, 0)
+    assert oracle.join_sum(key, key, np.array([-1, I32_MIN, I32_MAX], np.int32), lib=lib) == (0, 0)
+    big = np.full(4, I32_MAX, dtype=np.int32)
+    fk = np.array([0, 1, 2, 3] * 5, dtype=np.int32)
+    assert oracle.join_sum(np.arange(4, dtype=np.int32), big, fk, lib=lib) == (20 * I32_MAX, 20)
+    negv = np.full(4, -7, dtype=np.int32)
+    assert oracle.join_sum(np.arange(4, dtype=np.int32), negv, fk, lib=lib) == (-140, 20)
+    assert oracle.join_sum(key, None, np.arange(8, dtype=np.int32), lib=lib) == (0, 8)
+    try:
+        oracle.join_sum(np.array([1, 2, 1], np.int32), None, fk, lib=lib)
+    except oracle.OracleError as e:
+        assert e.code == oracle.EDUPKEY
+    else:
+        raise AssertionError("duplicate build key accepted")
+
+
+def pin_join_bruteforce(lib):
+    rng = np.random.default_rng(5)
+    for trial in range(20):
+        d = int(rng.integers(1, 64))
+        key = rng.choice(np.arange(-200, 200), size=d, replace=False).astype(np.int32)
+        val = rng.integers(-1000, 1000, size=d, dtype=np.int32)
+        filt = rng.integers(0, 4, size=d, dtype=np.int32)
+        n = int(rng.integers(0, 2000))
+        fk = rng.integers(-250, 250, size=n, dtype=np.int32)
+        pv = rng.integers(-1000, 1000, size=n, dtype=np.int32)
+        s = m = 0
+        for i in range(n):
+            for r in range(d):
+                if key[r] == fk[i] and 1 <= filt[r] <= 2:
+                    s += int(val[r]) + int(pv[i])
+                    m += 1
+        assert oracle.join_sum(key, val, fk, pval=pv, bfilter=filt, flo=1, fhi=2, lib=lib) == (s, m)
+
+
+# ------------------------------------------------------------------ group-by --
+def pin_groupby_closed_form(lib):
+    for G, n in [(1, 100), (7, 1000), (1000, 123457)]:
+        g = (np.arange(n) % G).astype(np.int32)
+        v = np.arange(n, dtype=np.int32)
+        sums = oracle.groupby(g, v, G, lib=lib)
+        q, r = divmod(n, G)
+        for grp in range(G):
+            c = q + (1 if grp < r else 0)
+            assert int(sums[grp]) == c * grp + G * c * (c - 1) // 2
+        assert int(sums.sum()) == n * (n - 1) // 2
+    try:
+        oracle.groupby(np.array([0, 3], np.int32), np.array([1, 1], np.int32), 3, lib=lib)
+    except oracle.OracleError as e:
+        assert e.code == oracle.ERANGE
+    else:
+        raise AssertionError("group index outside the array accepted")
+
+
+def pin_groupby_bruteforce(lib):
+    rng = np.random.default_rng(9)
+    g = rng.integers(0, 13, size=777, dtype=np.int32)
+    v = rng.integers(I32_MIN, I32_MAX, size=777, dtype=np.int32, endpoint=True)
+    want = [0] * 13
+    for a, b in zip(g.tolist(), v.tolist()):
+        want[a] += b
+    assert oracle.groupby(g, v, 13, lib=lib).tolist() == want
+
+
+# ------------------------------------------------------------- star queries --
+def q11_factorial():
+    """Every (day, quantity, discount) combination once; price = 90000 + day."""
+    keys, _ = datagen.day_keys()
+    day = np.repeat(np.arange(datagen.N_DAYS), 50 * 11)
+    qty = np.tile(np.repeat(np.arange(1, 51), 11), datagen.N_DAYS)
+    disc = np.tile(np.arange(0, 11), datagen.N_DAYS * 50)
+    return [keys[day].astype(np.int32), disc.astype(np.int32), qty.astype(np.int32),
+            (90_000 + day).astype(np.int32)]
+
+
+def pin_star_q11_factorial(lib):
+    cols = q11_factorial()
+    assert cols[0].size == 1_405_800
+    preds = [(0, *datagen.q11_year_range(1994)), (1, 1, 3), (2, I32_MIN, 24)]
+    # 1994 is day 731 .. 1095 counted from 1992-01-01 (1992 has 366 days, 1993 365)
+    day_sum = sum(90_000 + d for d in range(731, 1096))
+    out, surv = oracle.star(cols, 1, preds=preds, agg=oracle.AGG_SUM_PRODUCT, agg_cols=(3, 1),
+                            lib=lib, return_survivors=True)
+    assert surv == 365 * 24 * 3
+    assert int(out[0]) == 24 * (1 + 2 + 3) * day_sum
+    cnt = oracle.star(cols, 1, preds=preds, agg=oracle.AGG_COUNT, lib=lib)
+    assert int(cnt[0]) == 26_280
+    dif = oracle.star(cols, 1, preds=preds, agg=oracle.AGG_SUM_DIFF, agg_cols=(3, 1), lib=lib)
+    assert int(dif[0]) == 24 * 3 * day_sum - 365 * 24 * (1 + 2 + 3)
+    s = oracle.star(cols, 1, preds=preds, agg=oracle.AGG_SUM, agg_cols=(3, 0), lib=lib)
+    assert int(s[0]) == 24 * 3 * day_sum
+
+
+def _small_dims(rng):
+    """Four tiny dimensions shaped like the star schema (keys, filter, group)."""
+    keys, years = datagen.day_keys(60 + 366)          # spans 1992 and 1993
+    sel = np.concatenate([rng.choice(366, size=5, replace=False),
+                          366 + rng.choice(60, size=4, replace=False)])
+    rng.shuffle(sel)
+
+    def attrs(n, hi):
+        # filter attribute in 0..2 with every value present at least once
+        f = np.concatenate([np.arange(3), rng.integers(0, 3, n - 3)])
+        return rng.permutation(f).astype(np.int32), rng.integers(0, hi, n).astype(np.int32)
+
+    f1, _ = attrs(9, 4)
+    d1 = dict(key=keys[sel], filter=f1, group=years[sel])
+    d2 = dict(zip(("filter", "group"), attrs(5, 4)), key=rng.permutation(5).astype(np.int32))
+    d3 = dict(zip(("filter", "group"), attrs(6, 4)), key=rng.permutation(6).astype(np.int32))
+    d4 = dict(zip(("filter", "group"), attrs(4, 4)), key=rng.permutation(4).astype(np.int32))
+    return [d1, d2, d3, d4]
+
+
+def pin_star_factorial(lib):
+    """Fact rows enumerate every foreign-key combination once (plus misses):
+    per group, COUNT = product of per-dimension filtered counts."""
+    rng = np.random.default_rng(21)
+    dims = _small_dims(rng)
+    c = [1, 0, 2, 1]
+    fk_vals = [np.concatenate([d["key"], [np.int32(-5)]]) for d in dims]   # one missing key each
+    grids = np.meshgrid(*[np.arange(v.size) for v in fk_vals], indexing="ij")
+    cols = [fk_vals[j][grids[j].ravel()].astype(np.int32) for j in range(4)]
+    m1 = cols[3].copy()                                  # measure = fk4 value
+    m1[cols[3] < 0] = 0
+    cols.append(m1.astype(np.int32))
+    joins = [dict(fk_col=j, key=dims[j]["key"], filter=dims[j]["filter"], flo=c[j], fhi=c[j]) for j in range(4)]
+    joins[0].update(group=dims[0]["group"], base=1992, stride=4)
+    joins[2].update(group=dims[2]["group"], base=0, stride=1)
+    G = 2 * 4
+    cnt = oracle.star(cols, G, joins=joins, agg=oracle.AGG_COUNT, lib=lib)
+    s = oracle.star(cols, G, joins=joins, agg=oracle.AGG_SUM, agg_cols=(4, 0), lib=lib)
+    keep = [dims[j]["filter"] == c[j] for j in range(4)]
+    n2, n4 = int(keep[1].sum()), int(keep[3].sum())
+    s4 = int(dims[3]["key"][keep[3]].sum())
+    for y in range(2):
+        n1 = int((keep[0] & (dims[0]["group"] == 1992 + y)).sum())
+        for g3 in range(4):
+            n3 = int((keep[2] & (dims[2]["group"] == g3)).sum())
+            assert int(cnt[y * 4 + g3]) == n1 * n2 * n3 * n4
+            assert int(s[y * 4 + g3]) == n1 * n2 * n3 * s4
+    assert np.count_nonzero(cnt) >= 2, "degenerate fixture: too few populated groups"
+    # the dense index ignores attributes of joins that carry no group role
+    assert int(cnt.sum()) == int(keep[0].sum()) * n2 * int(keep[2].sum()) * n4
+
+
+def pin_star_bruteforce(lib):
+    """Nested-loop joins over every (fact, dimension) pair on tiny random tables."""
+    rng = np.random.default_rng(33)
+    nonempty = 0
+    for trial in range(8):
+        dims = _small_dims(rng)
+        n = 1500
+        cols = [rng.choice(np.concatenate([d["key"], [np.int32(-1), np.int32(999)]]), size=n).astype(np.int32)
+                for d in dims]
+        cols.append(rng.integers(-1000, 1000, size=n, dtype=np.int32))
+        cols.append(rng.integers(-1000, 1000, size=n, dtype=np.int32))
+        c = [int(v) for v in rng.integers(0, 3, size=4)]
+        w = [int(v) for v in rng.integers(0, 2, size=4)]    # filter window [c, c + w]
+        plo, phi = sorted(int(v) for v in rng.integers(-1000, 1000, size=2))
+        agg = int(rng.integers(0, 4))
+        order = rng.permutation(4)
+        joins = []
+        for j in order:
+            jj = dict(fk_col=int(j), key=dims[j]["key"], filter=dims[j]["filter"], flo=c[j], fhi=c[j] + w[j])
+            if j == 0:
+                jj.update(group=dims[0]["group"], base=1992, stride=4)
+            if j == 2:
+                jj.update(group=dims[2]["group"], base=0, stride=1)
+            joins.append(jj)
+        got = oracle.star(cols, 8, preds=[(5, plo, phi)], joins=joins, agg=agg, agg_cols=(4, 5), lib=lib)
+        want = [0] * 8
+        for i in range(n):
+            if not (plo <= cols[5][i] <= phi):
+                continue
+            rows = []
+            for j in range(4):
+                hit = [r for r in range(dims[j]["key"].size) if dims[j]["key"][r] == cols[j][i]]
+                if len(hit) != 1 or not (c[j] <= dims[j]["filter"][hit[0]] <= c[j] + w[j]):
+                    rows = None
+                    break
+                rows.append(hit[0])
+            if rows is None:
+                continue
+            g = (int(dims[0]["group"][rows[0]]) - 1992) * 4 + int(dims[2]["group"][rows[2]])
+            a, b = int(cols[4][i]), int(cols[5][i])
+            want[g] += [a, a * b, a - b, 1][agg]
+        assert got.tolist() == want, (trial, got.tolist(), want)
+        nonempty += sum(1 for v in want if v)
+    assert nonempty >= 10, "degenerate fixtures: too few populated groups"
+
+
+ALL_PINS = [
+    pin_select_closed_form, pin_select_extremes, pin_select_tile_example, pin_select_bruteforce,
+    pin_project_exact, pin_project_rational, pin_project_sigmoid,
+    pin_join_closed_form, pin_join_misses_and_width, pin_join_bruteforce,
+    pin_groupby_closed_form, pin_groupby_bruteforce,
+    pin_star_q11_factorial, pin_star_factorial, pin_star_bruteforce,
+]
