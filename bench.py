@@ -1,0 +1,331 @@
+#!/usr/bin/env python3
+"""Benchmark of the fused star query (and the operator micro-benchmarks).
+
+Default workload: a 120,000,000-row fact table (four int32 foreign keys, two
+int32 measures) joined to four dimensions of 2,556 / 40,000 / 200,000 /
+600,000 rows, each filtered to about 1/25 of its rows, grouped by
+(year, dim3.group) into 7,000 int64 sums.  One step = the four filtered
+dimension builds plus the fused probe/aggregate kernel, on resident data.
+
+Prints one JSON line.  ``roofline`` refers to the fused star kernel: its
+algorithmic bytes (fact-column cache lines the selective loads must touch, at
+the HBM fetch granularity) over its average duration measured with HIP events
+on the launch stream.  ``cpu_baseline`` is the plain CPU oracle timed on the
+host (single thread) over repeated passes of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0
+FETCH_BYTES = int(os.environ.get("CRYSTAL_FETCH_BYTES", "64"))   # HBM fetch granularity model
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=5)
+    p.add_argument("--workload", default="star", choices=["star", "q11", "select", "project", "join"])
+    p.add_argument("--rows", type=int, default=0, help="override the fact/column length")
+    p.add_argument("--sigma", type=float, default=0.5, help="select selectivity")
+    p.add_argument("--dim", type=int, default=1 << 20, help="join build size D")
+    p.add_argument("--kind", default="linear", choices=["linear", "direct"])
+    p.add_argument("--order", default="1,0,2,3", help="star join order")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-seconds", type=float, default=12.0)
+    p.add_argument("--tune", default="", help="kernel block,ipt,grid_per_cu override, e.g. 256,16,0")
+    return p.parse_args()
+
+
+def host_info():
+    model = platform.processor()
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
+def lines_touched(mask: np.ndarray, item_bytes: int = 4, line: int = FETCH_BYTES) -> int:
+    """Number of `line`-byte lines of a column holding at least one live item."""
+    per = line // item_bytes
+    n = mask.size
+    pad = (-n) % per
+    if pad:
+        mask = np.concatenate([mask, np.zeros(pad, dtype=bool)])
+    return int(mask.reshape(-1, per).any(axis=1).sum())
+
+
+def star_algorithmic_bytes(t, order, line=FETCH_BYTES):
+    """Bytes the selective scan must fetch: column s is read at the lines that
+    hold an item still alive before step s; the measure at the survivors."""
+    alive = np.ones(t.n, dtype=bool)
+    total = 0
+    for j in order:
+        d = t.dims[j]
+        total += lines_touched(alive, line=line) * line
+        kmin = int(d.key.min())
+        keep = np.zeros(int(d.key.max()) - kmin + 1, dtype=bool)
+        keep[d.key[d.filter == t.consts[j]] - kmin] = True
+        fk = t.fk[j]
+        ok = (fk >= kmin) & (fk - kmin < keep.size)
+        hit = np.zeros(t.n, dtype=bool)
+        hit[ok] = keep[fk[ok] - kmin]
+        alive &= hit
+    total += lines_touched(alive, line=line) * line          # m1 of the survivors
+    return total, int(alive.sum())
+
+
+class Timer:
+    """HIP events around one call on the current stream, averaged."""
+
+    def __init__(self, torch):
+        self.torch = torch
+        self.pairs = []
+
+    def run(self, fn):
+        s = self.torch.cuda.Event(enable_timing=True)
+        e = self.torch.cuda.Event(enable_timing=True)
+        s.record()
+        r = fn()
+        e.record()
+        self.pairs.append((s, e))
+        return r
+
+    def mean_ms(self):
+        return float(np.mean([s.elapsed_time(e) for s, e in self.pairs])) if self.pairs else 0.0
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "requested_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+    from paper_2003_01178_amd import crystal as cx
+    from paper_2003_01178_amd import datagen, queries
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(3)
+    cx.load()
+    kernel_id = {"star": cx.K_STAR, "q11": cx.K_STAR, "select": cx.K_SELECT,
+                 "project": cx.K_PROJECT, "join": cx.K_HT_PROBE}[args.workload]
+    if args.tune:
+        b, i, g = (int(x) for x in args.tune.split(","))
+        cx.tune_set(kernel_id, b, i, g)
+    model, ncpu = host_info()
+    print(f"# host: {model}, {ncpu} logical CPUs; device: {torch.cuda.get_device_name(0)}",
+          file=sys.stderr, flush=True)
+
+    W, K = args.warmup, args.steps
+    result = {"n_gpus": 1, "steps": K, "warmup": W, "higher_is_better": True, "scaling": "weak",
+              "vs_baseline": None, "data": "synthetic"}
+    roof = {"bound": "hbm", "peak": HBM_PEAK_GBS, "unit": "GB/s", "traffic": None,
+            "fetch_bytes_model": FETCH_BYTES}
+    cpu = None
+
+    if args.workload == "star":
+        n = args.rows or 120_000_000
+        order = tuple(int(x) for x in args.order.split(","))
+        t0 = time.time()
+        t = datagen.star_tables(n=n, workload=3)
+        print(f"# generated {n} fact rows in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+        s = queries.StarSchema(t)
+        plan = s.plan(order)
+        out = torch.empty(queries.STAR_GROUPS, dtype=torch.int64, device="cuda")
+        status = cx.new_status()
+
+        def step(timer=None):
+            s.build()
+            if timer is None:
+                plan.run(out=out, status=status)
+            else:
+                timer.run(lambda: plan.run(out=out, status=status))
+
+        for _ in range(W):
+            step()
+        torch.cuda.synchronize()
+        timer = Timer(torch)
+        t0 = time.perf_counter()
+        for _ in range(K):
+            step(timer)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        cx.check_status(status)
+        cx.check_status(s.status)
+        kern_ms = timer.mean_ms()
+        alg_bytes, survivors = star_algorithmic_bytes(t, order)
+        gpu_out = out.cpu().numpy()
+        result.update(metric="fact rows/s & % HBM peak (fused star query); served queries/s + p99 latency",
+                      value=n * K / elapsed, unit="rows/s", ms_per_step=elapsed / K * 1e3, dtype="int32",
+                      config={"workload": "fused star query: fact 120M rows x (4 int32 FKs + 2 int32 "
+                                          "measures), 4 dims (2556/40000/200000/600000 rows) filtered "
+                                          "to ~1/25 each, group by (year, dim3.group) -> 7000 int64",
+                              "fact_rows": n, "join_order": list(order), "survivors": survivors,
+                              "tile": list(cx.tune_get(cx.K_STAR, n)),
+                              "step": "4 filtered dimension builds + fused probe/aggregate kernel"})
+        roof.update(kernel="crystal::star_kernel", achieved=alg_bytes / (kern_ms * 1e-3) / 1e9,
+                    algorithmic_bytes=alg_bytes, bytes_per_row=alg_bytes / n, kernel_ms=kern_ms,
+                    kernel_rows_per_s=n / (kern_ms * 1e-3))
+        if not args.no_cpu_baseline:
+            import oracle
+            from_cols = [*t.fk, t.m1, t.m2]
+            joins = []
+            for j, d in enumerate(t.dims):
+                jj = dict(fk_col=j, key=d.key, filter=d.filter, flo=t.consts[j], fhi=t.consts[j])
+                if j == 0:
+                    jj.update(group=d.year, base=datagen.FIRST_YEAR, stride=queries.GROUPS_PER_YEAR)
+                if j == 2:
+                    jj.update(group=d.group, base=0, stride=1)
+                joins.append(jj)
+            passes, c0 = 0, time.perf_counter()
+            while True:
+                want = oracle.star(from_cols, queries.STAR_GROUPS, joins=joins, agg=oracle.AGG_SUM,
+                                   agg_cols=(4, 0))
+                passes += 1
+                if time.perf_counter() - c0 >= args.cpu_seconds or passes >= 20:
+                    break
+            cdt = time.perf_counter() - c0
+            cpu = {"value": n * passes / cdt, "unit": "rows/s", "cores": 1, "kind": "oracle",
+                   "sample": f"{passes} full pass(es) over the {n}-row fact table, single thread",
+                   "host": model}
+            result["exact_vs_oracle"] = bool(np.array_equal(gpu_out, want))
+        result["paper_context"] = ("SSB q2.1 (3 joins, 120M rows) on V100: 3.86 ms = 3.1e10 rows/s; "
+                                   "GPU/CPU 25x on SSB (different hardware and workload)")
+
+    elif args.workload == "q11":
+        n = args.rows or 6_000_000
+        f = datagen.q11_fact(n, workload=0)
+        cols = [queries.to_dev(c) for c in (f.datekey, f.discount, f.quantity, f.price)]
+        plan = queries.Q11Plan(*cols)
+        out = torch.empty(1, dtype=torch.int64, device="cuda")
+        status = cx.new_status()
+        for _ in range(W):
+            plan.run(out=out, status=status)
+        torch.cuda.synchronize()
+        timer = Timer(torch)
+        t0 = time.perf_counter()
+        for _ in range(K):
+            timer.run(lambda: plan.run(out=out, status=status))
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        kern_ms = timer.mean_ms()
+        lo, hi = datagen.q11_year_range(1994)
+        m = (f.datekey >= lo) & (f.datekey <= hi)
+        b = lines_touched(np.ones(n, bool)) * FETCH_BYTES + lines_touched(m) * FETCH_BYTES
+        m &= (f.discount >= 1) & (f.discount <= 3)
+        b += lines_touched(m) * FETCH_BYTES
+        m &= f.quantity <= 24
+        b += lines_touched(m) * FETCH_BYTES * 2          # price and the discount re-read
+        result.update(metric="fact rows/s (SSB Q1.1-shaped selection-scan-aggregate)", value=n * K / elapsed,
+                      unit="rows/s", ms_per_step=elapsed / K * 1e3, dtype="int32",
+                      config={"workload": "Q1.1 shape: 6M rows, 3 range predicates, SUM(price*disc)",
+                              "fact_rows": n})
+        roof.update(kernel="crystal::star_kernel", achieved=b / (kern_ms * 1e-3) / 1e9, algorithmic_bytes=b,
+                    kernel_ms=kern_ms)
+
+    elif args.workload == "select":
+        n = args.rows or (1 << 29)
+        y = datagen.select_column(n)
+        x = queries.to_dev(y)
+        lo, hi = datagen.select_threshold_range(args.sigma)
+        outb = torch.empty(n, dtype=torch.int32, device="cuda")
+        cnt = torch.empty(1, dtype=torch.int64, device="cuda")
+        for _ in range(W):
+            cx.select(x, lo, hi, out=outb, count=cnt)
+        torch.cuda.synchronize()
+        timer = Timer(torch)
+        t0 = time.perf_counter()
+        for _ in range(K):
+            timer.run(lambda: cx.select(x, lo, hi, out=outb, count=cnt))
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        c = int(cnt.item())
+        kern_ms = timer.mean_ms()
+        b = 4 * n + 4 * c
+        result.update(metric="rows/s (selection, compacted output)", value=n * K / elapsed, unit="rows/s",
+                      ms_per_step=elapsed / K * 1e3, dtype="int32",
+                      config={"workload": f"select y < v on 2^29 int32, sigma={args.sigma}", "rows": n,
+                              "matches": c, "tile": list(cx.tune_get(cx.K_SELECT, n))})
+        roof.update(kernel="crystal::select_kernel", achieved=b / (kern_ms * 1e-3) / 1e9, algorithmic_bytes=b,
+                    kernel_ms=kern_ms)
+
+    elif args.workload == "project":
+        n = args.rows or (1 << 29)
+        x1h, x2h = datagen.project_columns(n)
+        x1, x2 = queries.to_dev(x1h), queries.to_dev(x2h)
+        outp = torch.empty(n, dtype=torch.float32, device="cuda")
+        for _ in range(W):
+            cx.project(x1, x2, 2.0, 3.0, out=outp)
+        torch.cuda.synchronize()
+        timer = Timer(torch)
+        t0 = time.perf_counter()
+        for _ in range(K):
+            timer.run(lambda: cx.project(x1, x2, 2.0, 3.0, out=outp))
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        kern_ms = timer.mean_ms()
+        b = 12 * n
+        result.update(metric="rows/s (projection 2*x1 + 3*x2)", value=n * K / elapsed, unit="rows/s",
+                      ms_per_step=elapsed / K * 1e3, dtype="f32",
+                      config={"workload": "project 2*x1+3*x2 on 2^29 fp32", "rows": n,
+                              "tile": list(cx.tune_get(cx.K_PROJECT, n))})
+        roof.update(kernel="crystal::project_kernel", achieved=b / (kern_ms * 1e-3) / 1e9, algorithmic_bytes=b,
+                    kernel_ms=kern_ms)
+
+    elif args.workload == "join":
+        n = args.rows or (1 << 28)
+        d = args.dim
+        jt = datagen.join_tables(d, n_probe=n)
+        kind = cx.HT_LINEAR if args.kind == "linear" else cx.HT_DIRECT
+        ht = cx.HashTable(kind, d, 0, d - 1)
+        keys, vals, fk = queries.to_dev(jt.dim_key), queries.to_dev(jt.dim_val), queries.to_dev(jt.fk)
+        st = ht.build(keys, vals)
+        res = torch.empty(2, dtype=torch.int64, device="cuda")
+        for _ in range(W):
+            ht.probe(fk, out=res)
+        torch.cuda.synchronize()
+        cx.check_status(st)
+        timer = Timer(torch)
+        t0 = time.perf_counter()
+        for _ in range(K):
+            timer.run(lambda: ht.probe(fk, out=res))
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        kern_ms = timer.mean_ms()
+        in_cache = ht.nbytes <= 4 * 2 ** 20
+        b = 4 * n + (0 if in_cache else n * FETCH_BYTES)
+        result.update(metric="probes/s (hash join probe + sum)", value=n * K / elapsed, unit="probes/s",
+                      ms_per_step=elapsed / K * 1e3, dtype="int32",
+                      config={"workload": f"join probe: D={d} ({args.kind}, table {ht.nbytes} B), 2^28 probes",
+                              "probes": n, "table_bytes": ht.nbytes, "tile": list(cx.tune_get(cx.K_HT_PROBE, n))})
+        roof.update(kernel="crystal::ht_probe_kernel", achieved=b / (kern_ms * 1e-3) / 1e9, algorithmic_bytes=b,
+                    kernel_ms=kern_ms)
+
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    result["roofline"] = roof
+    if cpu is not None:
+        result["cpu_baseline"] = cpu
+    order = ["metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better",
+             "scaling", "vs_baseline", "dtype", "data", "config", "roofline", "cpu_baseline"]
+    line = {k: result[k] for k in order if k in result}
+    line.update({k: v for k, v in result.items() if k not in line})
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

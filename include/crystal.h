@@ -1,0 +1,266 @@
+/*
+ * crystal.h -- C ABI of a tile-based fused query library for AMD MI355X (gfx950).
+ *
+ * The library implements the tile-based execution model of Shanbhag, Madden
+ * and Yu, "A Study of the Fundamental Performance Characteristics of GPUs and
+ * CPUs for Database Analytics" (SIGMOD 2020), section 3.2: a workgroup is the
+ * unit of execution and processes a tile of BLOCK x IPT items held in
+ * registers, so one kernel per query runs selection, projection, hash-join
+ * probes and aggregation with no intermediate result written to memory.
+ *
+ * Conventions shared by every call:
+ *  - Column, table and output pointers are DEVICE pointers owned by the caller.
+ *    The library never allocates or frees device memory.
+ *  - Column pointers must be 16-byte aligned (the kernels issue 128-bit loads);
+ *    a misaligned pointer is rejected with CRYSTAL_EINVAL.
+ *  - Every call is asynchronous on `stream` (a hipStream_t passed as void*;
+ *    NULL means the default stream).  Host-detectable argument errors are
+ *    returned synchronously and nothing is launched.
+ *  - Outputs are overwritten: the library clears them on the stream first.
+ *  - Device-detectable errors (duplicate key, full table, key or group index
+ *    out of range) are recorded in a caller-provided device int32 `status`
+ *    word with a compare-and-swap from 0, so the first error sticks.  The
+ *    library never clears `status`; the caller zeroes it and reads it after
+ *    synchronising the stream.
+ *  - Functions are reentrant.  The only global state is the tile-size tuning
+ *    table (crystal_tune_*), which calls read and tuning calls write; do not
+ *    tune while other threads launch.
+ */
+#ifndef CRYSTAL_H
+#define CRYSTAL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum crystal_status {
+    CRYSTAL_OK = 0,
+    CRYSTAL_EINVAL = 1,   /* bad argument (null, negative size, misaligned, bad plan)   */
+    CRYSTAL_ESCRATCH = 2, /* caller-provided scratch or slot memory too small           */
+    CRYSTAL_EFULL = 3,    /* hash table has no free slot (device status)                */
+    CRYSTAL_EDUPKEY = 4,  /* duplicate build key (device status)                        */
+    CRYSTAL_EHIP = 5,     /* HIP runtime or launch error                                */
+    CRYSTAL_EBUSY = 6,    /* shared-scan batch or server has no free slot               */
+    CRYSTAL_ERANGE = 7    /* key outside a direct table, or group index outside the
+                             dense group array (device status); the row is skipped     */
+} crystal_status;
+
+/* Inclusive int32 range lo <= x <= hi.  lo > hi is the empty range. */
+typedef struct crystal_range {
+    int32_t lo;
+    int32_t hi;
+} crystal_range;
+
+/* Human-readable name of a status code.  Never NULL. */
+const char *crystal_status_string(int32_t status);
+
+/* ABI version of this header (incremented on any layout change). */
+#define CRYSTAL_ABI_VERSION 1
+int32_t crystal_abi_version(void);
+
+/* sizeof of the ABI structs as compiled into the library, so a binding can
+ * check its own layout: 0 crystal_range, 1 crystal_ht, 2 crystal_pred,
+ * 3 crystal_join, 4 crystal_star_query.  Returns 0 for any other value. */
+size_t crystal_struct_size(int32_t which);
+
+/* ------------------------------------------------------------------------ */
+/* Selection -- section 4.2, query Q3 (and section 3.2, query Q0):           */
+/*   SELECT y FROM R WHERE pred.lo <= y <= pred.hi                           */
+/* One kernel: BlockLoad, BlockPred, BlockScan, one 64-bit atomic per tile   */
+/* on *out_count to reserve the tile's output range, BlockShuffle through    */
+/* LDS, BlockStore (coalesced).                                              */
+/*   in        device, n int32 values                                        */
+/*   out       device, capacity for every match (n values always suffice)    */
+/*   out_count device int64; cleared, then the number of matches             */
+/* Output order: the qualifying values of a tile are contiguous, grouped by  */
+/* thread as in the section 3.2 example; tiles follow the order in which    */
+/* their atomic reservations completed, which varies between runs.  The     */
+/* multiset of values and the count are exact.                              */
+/* ------------------------------------------------------------------------ */
+crystal_status crystal_select(const int32_t *in, int64_t n, crystal_range pred,
+                              int32_t *out, int64_t *out_count, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Projection -- section 4.1, query Q1:  SELECT a*x1 + b*x2 FROM R          */
+/* fp32, each product and the sum rounded to nearest-even, no fused          */
+/* multiply-add.  x1, x2, out: device, n floats.                             */
+/* ------------------------------------------------------------------------ */
+crystal_status crystal_project(const float *x1, const float *x2, int64_t n,
+                               float a, float b, float *out, void *stream);
+
+/* Section 4.1, query Q2:  SELECT sigmoid(a*x1 + b*x2) FROM R, with
+ * sigmoid(t) = 1 / (1 + e^-t) evaluated in fp32 with the device expf. */
+crystal_status crystal_project_sigmoid(const float *x1, const float *x2, int64_t n,
+                                       float a, float b, float *out, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Hash tables -- section 4.3 (build and probe phases, linear probing) and   */
+/* section 5.3 (perfect hashing of dense dimension keys).                    */
+/*                                                                          */
+/* CRYSTAL_HT_LINEAR: open addressing with linear probing.  capacity is the  */
+/*   smallest power of two >= max(64, 2 * n_keys) (at most 50% fill); each   */
+/*   slot is 8 bytes {int32 key, int32 payload}; the empty key is INT32_MIN, */
+/*   which therefore cannot be inserted.  Slot of key k: multiplicative      */
+/*   hashing, (k * 2654435761 mod 2^32) >> (32 - log2 capacity), then the    */
+/*   following slots in order.                                               */
+/* CRYSTAL_HT_DIRECT: one entry per key in [key_min, key_max] (perfect       */
+/*   hashing): a presence bitmap of ceil(span/32) 32-bit words padded to a   */
+/*   multiple of 64 words, followed by span int32 payloads if has_payload.   */
+/* ------------------------------------------------------------------------ */
+enum { CRYSTAL_HT_LINEAR = 0, CRYSTAL_HT_DIRECT = 1 };
+
+typedef struct crystal_ht {
+    void *mem;             /* device memory of crystal_ht_bytes() bytes (caller-owned) */
+    int64_t capacity;      /* LINEAR: number of slots; DIRECT: key span                 */
+    int32_t kind;          /* CRYSTAL_HT_LINEAR or CRYSTAL_HT_DIRECT                    */
+    int32_t key_min;       /* DIRECT: key stored in entry 0                             */
+    int32_t has_payload;   /* 0: keys only (a probe sums 0 per match)                   */
+    int32_t log2_capacity; /* LINEAR: log2(capacity)                                    */
+} crystal_ht;
+
+/* Host only: fill the descriptor for a table that will hold up to n_keys keys
+ * (LINEAR) or every key of [key_min, key_max] (DIRECT); sets mem = NULL. */
+crystal_status crystal_ht_init(crystal_ht *ht, int32_t kind, int64_t n_keys,
+                               int32_t key_min, int32_t key_max, int32_t has_payload);
+/* Device bytes the described table needs (0 for an invalid descriptor). */
+size_t crystal_ht_bytes(const crystal_ht *ht);
+
+/* Build phase: clear the table, then insert (keys[i], payload[i]) for every
+ * row i < n whose filter_col[i] lies in `filter` (all rows when filter_col is
+ * NULL).  payload may be NULL only for a table without payload.  Duplicate
+ * keys set CRYSTAL_EDUPKEY, a full LINEAR table CRYSTAL_EFULL, a key outside a
+ * DIRECT table's span CRYSTAL_ERANGE, the empty key CRYSTAL_EINVAL, in
+ * *status.  One thread per row; a 64-bit compare-and-swap claims a slot. */
+crystal_status crystal_ht_build(const crystal_ht *ht, const int32_t *keys,
+                                const int32_t *payload, const int32_t *filter_col,
+                                crystal_range filter, int64_t n, int32_t *status,
+                                void *stream);
+
+/* Probe phase of query Q4 (section 4.3):
+ *   SELECT SUM(A.v + B.v) FROM A, B WHERE A.k = B.k
+ * with A the built table and B the probe rows (fk[i], probe_payload[i]).
+ *   *out_sum     device int64: sum of the table payload of every match, plus
+ *                probe_payload[i] when probe_payload is not NULL (wraps mod 2^64)
+ *   *out_matches device int64: number of probe rows that found their key
+ * Tables that fit the workgroup's LDS are staged there once per workgroup. */
+crystal_status crystal_ht_probe(const crystal_ht *ht, const int32_t *fk,
+                                const int32_t *probe_payload, int64_t n,
+                                int64_t *out_sum, int64_t *out_matches, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Dense group-by aggregate (the aggregation table of section 5.3 in the     */
+/* dense form small group keys allow):  sums[group[i]] += value[i]  (int64). */
+/* Rows whose group lies outside [0, n_groups) are skipped and set           */
+/* CRYSTAL_ERANGE in *status.  sums: device, n_groups int64, overwritten.     */
+/* ------------------------------------------------------------------------ */
+crystal_status crystal_groupby_agg(const int32_t *group, const int32_t *value, int64_t n,
+                                   int64_t n_groups, int64_t *sums, int32_t *status,
+                                   void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Fused star query -- section 3.1 (SSB Q1.1) and section 5.3 (SSB Q2.1):   */
+/*   SELECT agg FROM fact, dim_1..dim_J                                      */
+/*   WHERE fact predicates AND fact.fk_j = dim_j.key AND dimension filters  */
+/*   GROUP BY dense index                                                    */
+/* One kernel.  Per tile: BlockLoad of the first column, then, in plan      */
+/* order, each fact predicate and each join reads its column with           */
+/* BlockLoadSel (only items still alive), probes (BlockProbeHT) and clears  */
+/* the items that fail; the survivors' group index and measure are formed   */
+/* and added (BlockAggregate for a single group, global 64-bit atomics per  */
+/* survivor otherwise).                                                      */
+/*                                                                          */
+/* Payload fields: a join may read two fields from the 32-bit payload of    */
+/* the matched entry, field = (uint32(payload) >> shift) & (2^bits - 1), or */
+/* the whole payload as a signed int32 when bits == 32.                     */
+/*   filter_bits > 0: keep the row only if the field lies in `filter`       */
+/*                    (dimension predicate evaluated at probe time);        */
+/*   group_bits  > 0: group += (field - group_base) * group_stride.          */
+/* A table built with a filter (crystal_ht_build) needs no filter field.     */
+/* ------------------------------------------------------------------------ */
+#define CRYSTAL_MAX_COLS 16
+#define CRYSTAL_MAX_PREDS 4
+#define CRYSTAL_MAX_JOINS 4
+
+typedef enum crystal_agg {
+    CRYSTAL_AGG_SUM = 0,         /* SUM(col0)                                  */
+    CRYSTAL_AGG_SUM_PRODUCT = 1, /* SUM(col0 * col1), product in int64         */
+    CRYSTAL_AGG_SUM_DIFF = 2,    /* SUM(col0 - col1)                           */
+    CRYSTAL_AGG_COUNT = 3        /* COUNT(*)                                   */
+} crystal_agg;
+
+typedef struct crystal_pred {
+    int32_t col;          /* fact column index                              */
+    crystal_range range;  /* keep lo <= fact[col] <= hi                     */
+} crystal_pred;
+
+typedef struct crystal_join {
+    crystal_ht ht;        /* built dimension table                          */
+    int32_t fk_col;       /* fact column holding the foreign key            */
+    int32_t filter_bits;  /* 0: no dimension predicate on the payload       */
+    int32_t filter_shift;
+    crystal_range filter;
+    int32_t group_bits;   /* 0: no contribution to the group index          */
+    int32_t group_shift;
+    int32_t group_base;
+    int32_t reserved;
+    int64_t group_stride;
+} crystal_join;
+
+typedef struct crystal_star_query {
+    const int32_t *cols[CRYSTAL_MAX_COLS]; /* fact columns (device)          */
+    int64_t n_rows;
+    int32_t n_cols;
+    int32_t n_preds;
+    crystal_pred preds[CRYSTAL_MAX_PREDS]; /* evaluated first, in order      */
+    int32_t n_joins;
+    int32_t agg;                           /* crystal_agg                    */
+    int32_t agg_col0;
+    int32_t agg_col1;
+    int64_t n_groups;                      /* >= 1; 1 means a scalar result  */
+    crystal_join joins[CRYSTAL_MAX_JOINS]; /* evaluated after the predicates */
+} crystal_star_query;
+
+/* Run one query.  out: device, n_groups int64, overwritten.  The plan needs
+ * at least one predicate or join (the first one's column is read in full). */
+crystal_status crystal_run_star_query(const crystal_star_query *q, int64_t *out,
+                                      int32_t *status, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Tile-size tuning (section 3.3: the tile is BLOCK threads x IPT items per */
+/* thread; the best shape depends on the kernel and the input).  The table  */
+/* maps (kernel, size bucket = floor(log2 n)) to a compiled variant.  A     */
+/* grid_per_cu of 0 launches one workgroup per tile; k > 0 launches k       */
+/* workgroups per compute unit that stride over the tiles.                  */
+/* ------------------------------------------------------------------------ */
+enum {
+    CRYSTAL_K_SELECT = 0,
+    CRYSTAL_K_PROJECT = 1,
+    CRYSTAL_K_HT_PROBE = 2,
+    CRYSTAL_K_GROUPBY = 3,
+    CRYSTAL_K_STAR = 4,
+    CRYSTAL_K_SHARED_SCAN = 5,
+    CRYSTAL_K_COUNT = 6
+};
+
+/* Number of compiled (block, ipt) variants of `kernel`; fills up to `max`. */
+int32_t crystal_tune_variants(int32_t kernel, int32_t *blocks, int32_t *ipts, int32_t max);
+/* Set the variant for sizes in bucket [bucket_lo, bucket_hi] (-1, -1: all). */
+crystal_status crystal_tune_set(int32_t kernel, int32_t bucket_lo, int32_t bucket_hi,
+                                int32_t block, int32_t ipt, int32_t grid_per_cu);
+/* Variant that a call of `kernel` on n items would use. */
+crystal_status crystal_tune_get(int32_t kernel, int64_t n, int32_t *block, int32_t *ipt,
+                                int32_t *grid_per_cu);
+/* Restore the built-in defaults. */
+void crystal_tune_reset(void);
+/* Text cache: one line "kernel bucket_lo bucket_hi block ipt grid_per_cu". */
+crystal_status crystal_tune_load(const char *path);
+crystal_status crystal_tune_save(const char *path);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CRYSTAL_H */

@@ -1,0 +1,318 @@
+"""Thin ctypes binding over ``libcrystal.so`` (declared in ``include/crystal.h``).
+
+Argument marshalling only: torch tensors supply device memory and
+``torch.cuda`` streams, every computation runs in the library's HIP kernels.
+The binding raises ``ImportError`` when the library is missing and cannot be
+built, and never falls back to CPU code.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcrystal.so")
+
+OK, EINVAL, ESCRATCH, EFULL, EDUPKEY, EHIP, EBUSY, ERANGE = range(8)
+HT_LINEAR, HT_DIRECT = 0, 1
+AGG_SUM, AGG_SUM_PRODUCT, AGG_SUM_DIFF, AGG_COUNT = 0, 1, 2, 3
+K_SELECT, K_PROJECT, K_HT_PROBE, K_GROUPBY, K_STAR, K_SHARED_SCAN = range(6)
+MAX_COLS, MAX_PREDS, MAX_JOINS = 16, 4, 4
+I32_MIN, I32_MAX = -(2 ** 31), 2 ** 31 - 1
+
+c_i32, c_i64, c_vp, c_f32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p, ctypes.c_float
+
+
+class Range(ctypes.Structure):
+    _fields_ = [("lo", c_i32), ("hi", c_i32)]
+
+
+class HT(ctypes.Structure):
+    _fields_ = [("mem", c_vp), ("capacity", c_i64), ("kind", c_i32), ("key_min", c_i32),
+                ("has_payload", c_i32), ("log2_capacity", c_i32)]
+
+
+class Pred(ctypes.Structure):
+    _fields_ = [("col", c_i32), ("range", Range)]
+
+
+class Join(ctypes.Structure):
+    _fields_ = [("ht", HT), ("fk_col", c_i32), ("filter_bits", c_i32), ("filter_shift", c_i32),
+                ("filter", Range), ("group_bits", c_i32), ("group_shift", c_i32),
+                ("group_base", c_i32), ("reserved", c_i32), ("group_stride", c_i64)]
+
+
+class StarQueryC(ctypes.Structure):
+    _fields_ = [("cols", c_vp * MAX_COLS), ("n_rows", c_i64), ("n_cols", c_i32), ("n_preds", c_i32),
+                ("preds", Pred * MAX_PREDS), ("n_joins", c_i32), ("agg", c_i32), ("agg_col0", c_i32),
+                ("agg_col1", c_i32), ("n_groups", c_i64), ("joins", Join * MAX_JOINS)]
+
+
+class CrystalError(RuntimeError):
+    def __init__(self, code, what=""):
+        super().__init__(f"{what}: {status_string(code)} ({code})" if what else status_string(code))
+        self.code = code
+
+
+_lib = None
+
+
+def _declare(lib):
+    P = ctypes.POINTER
+    sig = {
+        "crystal_status_string": (ctypes.c_char_p, [c_i32]),
+        "crystal_abi_version": (c_i32, []),
+        "crystal_struct_size": (ctypes.c_size_t, [c_i32]),
+        "crystal_select": (c_i32, [c_vp, c_i64, Range, c_vp, c_vp, c_vp]),
+        "crystal_project": (c_i32, [c_vp, c_vp, c_i64, c_f32, c_f32, c_vp, c_vp]),
+        "crystal_project_sigmoid": (c_i32, [c_vp, c_vp, c_i64, c_f32, c_f32, c_vp, c_vp]),
+        "crystal_ht_init": (c_i32, [P(HT), c_i32, c_i64, c_i32, c_i32, c_i32]),
+        "crystal_ht_bytes": (ctypes.c_size_t, [P(HT)]),
+        "crystal_ht_build": (c_i32, [P(HT), c_vp, c_vp, c_vp, Range, c_i64, c_vp, c_vp]),
+        "crystal_ht_probe": (c_i32, [P(HT), c_vp, c_vp, c_i64, c_vp, c_vp, c_vp]),
+        "crystal_groupby_agg": (c_i32, [c_vp, c_vp, c_i64, c_i64, c_vp, c_vp, c_vp]),
+        "crystal_run_star_query": (c_i32, [P(StarQueryC), c_vp, c_vp, c_vp]),
+        "crystal_tune_variants": (c_i32, [c_i32, P(c_i32), P(c_i32), c_i32]),
+        "crystal_tune_set": (c_i32, [c_i32, c_i32, c_i32, c_i32, c_i32, c_i32]),
+        "crystal_tune_get": (c_i32, [c_i32, c_i64, P(c_i32), P(c_i32), P(c_i32)]),
+        "crystal_tune_reset": (None, []),
+        "crystal_tune_load": (c_i32, [ctypes.c_char_p]),
+        "crystal_tune_save": (c_i32, [ctypes.c_char_p]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+def load(path: str = LIB_PATH):
+    """Load the HIP library; build it only when no built library exists."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        try:
+            from . import build as _build
+            _build.build()
+        except Exception as e:  # pragma: no cover - depends on the toolchain
+            raise ImportError(f"libcrystal.so is missing and could not be built: {e}") from e
+    lib = _declare(ctypes.CDLL(path))
+    for which, ty in enumerate((Range, HT, Pred, Join, StarQueryC)):
+        if lib.crystal_struct_size(which) != ctypes.sizeof(ty):
+            raise ImportError(f"ABI layout mismatch for {ty.__name__}")
+    _lib = lib
+    tune_file = os.environ.get("CRYSTAL_TUNE_FILE", os.path.join(_HERE, "tune", "gfx950.txt"))
+    if os.path.exists(tune_file):
+        lib.crystal_tune_load(tune_file.encode())
+    return lib
+
+
+def status_string(code: int) -> str:
+    return load().crystal_status_string(int(code)).decode()
+
+
+def _check(rc, what):
+    if rc != OK:
+        raise CrystalError(rc, what)
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return c_vp(stream.cuda_stream)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return c_vp(t.data_ptr())
+
+
+def _col(t, dtype=torch.int32):
+    if t.dtype != dtype:
+        raise TypeError(f"expected {dtype}, got {t.dtype}")
+    return _ptr(t)
+
+
+def new_status(device="cuda"):
+    return torch.zeros(1, dtype=torch.int32, device=device)
+
+
+def check_status(status):
+    """Raise if a device status word holds an error (synchronises)."""
+    code = int(status.item())
+    if code != OK:
+        raise CrystalError(code, "device status")
+
+
+# ------------------------------------------------------------------ calls --
+def select(x, lo, hi, out=None, count=None, stream=None):
+    """Section 4.2 Q3: values of x with lo <= x <= hi -> (out[:count], count tensor)."""
+    lib = load()
+    n = x.numel()
+    out = torch.empty(max(n, 1), dtype=torch.int32, device=x.device) if out is None else out
+    count = torch.empty(1, dtype=torch.int64, device=x.device) if count is None else count
+    _check(lib.crystal_select(_col(x), n, Range(int(lo), int(hi)), _ptr(out), _ptr(count),
+                              _stream(stream)), "crystal_select")
+    return out, count
+
+
+def project(x1, x2, a, b, out=None, sigmoid=False, stream=None):
+    """Section 4.1 Q1 (or Q2 with sigmoid=True): a*x1 + b*x2 in fp32."""
+    lib = load()
+    n = x1.numel()
+    if x2.numel() != n:
+        raise ValueError("x1 and x2 differ in length")
+    out = torch.empty_like(x1) if out is None else out
+    fn = lib.crystal_project_sigmoid if sigmoid else lib.crystal_project
+    _check(fn(_col(x1, torch.float32), _col(x2, torch.float32), n, float(a), float(b),
+              _col(out, torch.float32), _stream(stream)), "crystal_project")
+    return out
+
+
+class HashTable:
+    """A dimension hash table in caller-owned (torch) device memory."""
+
+    def __init__(self, kind, n_keys=0, key_min=0, key_max=0, has_payload=True, device="cuda"):
+        lib = load()
+        self.desc = HT()
+        _check(lib.crystal_ht_init(ctypes.byref(self.desc), int(kind), int(n_keys), int(key_min),
+                                   int(key_max), 1 if has_payload else 0), "crystal_ht_init")
+        nbytes = lib.crystal_ht_bytes(ctypes.byref(self.desc))
+        self.mem = torch.empty(max(16, nbytes), dtype=torch.uint8, device=device)
+        self.desc.mem = self.mem.data_ptr()
+        self.nbytes = nbytes
+
+    @property
+    def kind(self):
+        return self.desc.kind
+
+    def build(self, keys, payload=None, filter_col=None, filter=(I32_MIN, I32_MAX), status=None,
+              stream=None):
+        lib = load()
+        for extra in (payload, filter_col):
+            if extra is not None and extra.numel() != keys.numel():
+                raise ValueError("build columns differ in length")
+        status = new_status(keys.device) if status is None else status
+        _check(lib.crystal_ht_build(ctypes.byref(self.desc), _col(keys),
+                                    _col(payload) if payload is not None else None,
+                                    _col(filter_col) if filter_col is not None else None,
+                                    Range(int(filter[0]), int(filter[1])), keys.numel(),
+                                    _ptr(status), _stream(stream)), "crystal_ht_build")
+        return status
+
+    def probe(self, fk, probe_payload=None, out=None, stream=None):
+        """Q4 probe: device int64[2] = (sum, matches)."""
+        lib = load()
+        if probe_payload is not None and probe_payload.numel() != fk.numel():
+            raise ValueError("probe payload and keys differ in length")
+        out = torch.empty(2, dtype=torch.int64, device=fk.device) if out is None else out
+        base = out.data_ptr()
+        _check(lib.crystal_ht_probe(ctypes.byref(self.desc), _col(fk),
+                                    _col(probe_payload) if probe_payload is not None else None,
+                                    fk.numel(), c_vp(base), c_vp(base + 8), _stream(stream)),
+               "crystal_ht_probe")
+        return out
+
+
+def groupby_agg(group, value, n_groups, out=None, status=None, stream=None):
+    lib = load()
+    if value.numel() != group.numel():
+        raise ValueError("group and value columns differ in length")
+    out = torch.empty(int(n_groups), dtype=torch.int64, device=group.device) if out is None else out
+    status = new_status(group.device) if status is None else status
+    _check(lib.crystal_groupby_agg(_col(group), _col(value), group.numel(), int(n_groups), _ptr(out),
+                                   _ptr(status), _stream(stream)), "crystal_groupby_agg")
+    return out, status
+
+
+class StarQuery:
+    """Plan of a fused star query (marshalled once into the C struct).
+
+    cols: list of int32 device tensors (the fact columns).
+    preds: list of (col, lo, hi).
+    joins: list of dicts: ``table`` (HashTable), ``fk_col``, optional
+        ``filter`` = (bits, shift, lo, hi), optional ``group`` = (bits, shift,
+        base, stride).
+    """
+
+    def __init__(self, cols, n_groups=1, preds=(), joins=(), agg=AGG_SUM, agg_cols=(0, 0)):
+        if len(cols) > MAX_COLS or len(preds) > MAX_PREDS or len(joins) > MAX_JOINS:
+            raise ValueError("plan exceeds the ABI limits")
+        n = cols[0].numel() if cols else 0
+        for c in cols:
+            if c.dtype != torch.int32 or c.numel() != n or not c.is_cuda:
+                raise ValueError("fact columns must be int32 device tensors of equal length")
+        self.cols, self.joins = list(cols), list(joins)   # keep the memory alive
+        q = StarQueryC()
+        for i, c in enumerate(cols):
+            q.cols[i] = c.data_ptr()
+        q.n_rows, q.n_cols, q.n_preds, q.n_joins = n, len(cols), len(preds), len(joins)
+        for i, (col, lo, hi) in enumerate(preds):
+            q.preds[i] = Pred(int(col), Range(int(lo), int(hi)))
+        for i, j in enumerate(joins):
+            cj = Join()
+            cj.ht = j["table"].desc
+            cj.fk_col = int(j["fk_col"])
+            if j.get("filter") is not None:
+                bits, shift, lo, hi = j["filter"]
+                cj.filter_bits, cj.filter_shift, cj.filter = int(bits), int(shift), Range(int(lo), int(hi))
+            if j.get("group") is not None:
+                bits, shift, base, stride = j["group"]
+                cj.group_bits, cj.group_shift = int(bits), int(shift)
+                cj.group_base, cj.group_stride = int(base), int(stride)
+            q.joins[i] = cj
+        q.agg, q.agg_col0, q.agg_col1 = int(agg), int(agg_cols[0]), int(agg_cols[1])
+        q.n_groups = int(n_groups)
+        self.c = q
+        self.n_groups = int(n_groups)
+        self.n_rows = n
+
+    def run(self, out=None, status=None, stream=None):
+        lib = load()
+        dev = self.cols[0].device if self.cols else "cuda"
+        out = torch.empty(self.n_groups, dtype=torch.int64, device=dev) if out is None else out
+        status = new_status(dev) if status is None else status
+        _check(lib.crystal_run_star_query(ctypes.byref(self.c), _ptr(out), _ptr(status), _stream(stream)),
+               "crystal_run_star_query")
+        return out, status
+
+
+# ----------------------------------------------------------------- tuning --
+def tune_variants(kernel):
+    lib = load()
+    n = lib.crystal_tune_variants(int(kernel), None, None, 0)
+    b, i = (c_i32 * n)(), (c_i32 * n)()
+    lib.crystal_tune_variants(int(kernel), b, i, n)
+    return list(zip(list(b), list(i)))
+
+
+def tune_set(kernel, block, ipt, grid_per_cu=0, bucket_lo=-1, bucket_hi=-1):
+    _check(load().crystal_tune_set(int(kernel), int(bucket_lo), int(bucket_hi), int(block), int(ipt),
+                                   int(grid_per_cu)), "crystal_tune_set")
+
+
+def tune_get(kernel, n):
+    b, i, g = c_i32(), c_i32(), c_i32()
+    _check(load().crystal_tune_get(int(kernel), int(n), ctypes.byref(b), ctypes.byref(i), ctypes.byref(g)),
+           "crystal_tune_get")
+    return b.value, i.value, g.value
+
+
+def tune_reset():
+    load().crystal_tune_reset()
+
+
+def tune_load(path):
+    _check(load().crystal_tune_load(str(path).encode()), "crystal_tune_load")
+
+
+def tune_save(path):
+    _check(load().crystal_tune_save(str(path).encode()), "crystal_tune_save")

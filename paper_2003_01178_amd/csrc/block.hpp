@@ -1,0 +1,281 @@
+// Block-wide functions of the tile-based execution model (section 3.3,
+// Table "List of block-wide functions"), rebuilt for CDNA4 wave64.
+//
+// A tile is BLOCK threads x IPT items.  Items live in registers.  A thread
+// holds CHUNKS = IPT / VEC vectors of VEC consecutive items (VEC = 4 when
+// IPT >= 4, so every vector is one 128-bit load).  Item (c, e) of thread t
+// sits at tile offset (c * BLOCK + t) * VEC + e: for a fixed chunk c the
+// workgroup's loads cover BLOCK * VEC * 4 contiguous bytes, so each wave's
+// load instruction reads 1 KiB of consecutive memory.
+//
+// Per-item flags are a bitmask in one register (bit c * VEC + e), which is
+// what BlockPred produces and BlockLoadSel consumes.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace crystal {
+
+constexpr int kWave = 64;
+constexpr int32_t kEmptyKey = INT32_MIN;
+
+typedef int32_t v2i __attribute__((ext_vector_type(2)));
+typedef int32_t v4i __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+template <int N> struct VecOf;
+template <> struct VecOf<1> { typedef int32_t type; };
+template <> struct VecOf<2> { typedef v2i type; };
+template <> struct VecOf<4> { typedef v4i type; };
+
+template <int BLOCK, int IPT>
+struct TileShape {
+    static_assert(BLOCK % kWave == 0, "workgroups are whole waves");
+    static_assert(IPT == 1 || IPT == 2 || IPT % 4 == 0, "IPT is 1, 2 or a multiple of 4");
+    static_assert(IPT <= 32, "the per-item mask is one 32-bit register");
+    static constexpr int VEC = IPT >= 4 ? 4 : IPT;
+    static constexpr int CHUNKS = IPT / VEC;
+    static constexpr int ITEMS = BLOCK * IPT;
+    static constexpr int WAVES = BLOCK / kWave;
+    static constexpr uint32_t VMASK = (1u << VEC) - 1u;
+    static constexpr uint32_t ALL = IPT == 32 ? 0xffffffffu : ((1u << IPT) - 1u);
+    // bits needed for a per-thread count 0..IPT
+    static constexpr int CBITS = IPT < 2 ? 1 : IPT < 4 ? 2 : IPT < 8 ? 3 : IPT < 16 ? 4 : IPT < 32 ? 5 : 6;
+
+    __device__ static __forceinline__ int64_t index(int64_t base, int c, int e) {
+        return base + ((int64_t)c * BLOCK + (int64_t)threadIdx.x) * VEC + e;
+    }
+};
+
+// ---------------------------------------------------------------- lanes ----
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
+// number of set bits of m in lanes below the calling lane (v_mbcnt)
+__device__ __forceinline__ uint32_t count_below(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ __forceinline__ uint32_t lane_id() { return count_below(~0ull); }
+
+// ---------------------------------------------------------- BlockLoad ------
+// Valid-item mask of a tile that starts at `base` in a column of n items.
+template <int BLOCK, int IPT>
+__device__ __forceinline__ uint32_t valid_mask(int64_t base, int64_t n) {
+    using T = TileShape<BLOCK, IPT>;
+    if (base + T::ITEMS <= n) return T::ALL;
+    uint32_t m = 0;
+#pragma unroll
+    for (int c = 0; c < T::CHUNKS; ++c)
+#pragma unroll
+        for (int e = 0; e < T::VEC; ++e)
+            if (T::index(base, c, e) < n) m |= 1u << (c * T::VEC + e);
+    return m;
+}
+
+template <int VEC, bool NT>
+__device__ __forceinline__ void load_vec(const int32_t *__restrict__ p, int32_t *dst) {
+    typedef typename VecOf<VEC>::type V;
+    V v;
+    if (NT)
+        v = __builtin_nontemporal_load(reinterpret_cast<const V *>(p));
+    else
+        v = *reinterpret_cast<const V *>(p);
+    if constexpr (VEC == 1) {
+        dst[0] = v;
+    } else {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) dst[e] = v[e];
+    }
+}
+
+// BlockLoad: the whole tile (full tiles with vector loads, the tail item by item).
+template <int BLOCK, int IPT, bool NT>
+__device__ __forceinline__ void block_load(const int32_t *__restrict__ col, int64_t base,
+                                           int64_t n, int32_t (&v)[IPT]) {
+    using T = TileShape<BLOCK, IPT>;
+    if (base + T::ITEMS <= n) {
+#pragma unroll
+        for (int c = 0; c < T::CHUNKS; ++c)
+            load_vec<T::VEC, NT>(col + T::index(base, c, 0), &v[c * T::VEC]);
+    } else {
+#pragma unroll
+        for (int c = 0; c < T::CHUNKS; ++c)
+#pragma unroll
+            for (int e = 0; e < T::VEC; ++e) {
+                int64_t i = T::index(base, c, e);
+                v[c * T::VEC + e] = i < n ? col[i] : 0;
+            }
+    }
+}
+
+// BlockLoadSel: only the vectors that hold at least one flagged item are read
+// (a 128-bit load touches the same cache line as any single item in it).
+template <int BLOCK, int IPT, bool NT>
+__device__ __forceinline__ void block_load_sel(const int32_t *__restrict__ col, int64_t base,
+                                               int64_t n, uint32_t flags, int32_t (&v)[IPT]) {
+    using T = TileShape<BLOCK, IPT>;
+    const bool full = base + T::ITEMS <= n;
+#pragma unroll
+    for (int c = 0; c < T::CHUNKS; ++c) {
+        uint32_t m = (flags >> (c * T::VEC)) & T::VMASK;
+        if (!m) continue;
+        if (full) {
+            load_vec<T::VEC, NT>(col + T::index(base, c, 0), &v[c * T::VEC]);
+        } else {
+#pragma unroll
+            for (int e = 0; e < T::VEC; ++e)
+                if (m & (1u << e)) v[c * T::VEC + e] = col[T::index(base, c, e)];
+        }
+    }
+}
+
+// ---------------------------------------------------------- BlockPred ------
+__device__ __forceinline__ bool in_range(int32_t x, int32_t lo, int32_t hi) {
+    return x >= lo && x <= hi;
+}
+
+template <int IPT>
+__device__ __forceinline__ uint32_t block_pred_range(const int32_t (&v)[IPT], uint32_t flags,
+                                                     int32_t lo, int32_t hi) {
+    uint32_t m = 0;
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) m |= (uint32_t)in_range(v[k], lo, hi) << k;
+    return flags & m;
+}
+
+// ---------------------------------------------------------- BlockScan ------
+// Exclusive prefix over the wave of small per-lane values x < 2^BITS: one
+// ballot per bit, and the lanes below each lane counted with v_mbcnt.
+template <int BITS>
+__device__ __forceinline__ uint32_t wave_exclusive_scan_small(uint32_t x, uint32_t &wave_total) {
+    uint32_t pre = 0, tot = 0;
+#pragma unroll
+    for (int b = 0; b < BITS; ++b) {
+        uint64_t m = ballot((x >> b) & 1u);
+        pre += count_below(m) << b;
+        tot += (uint32_t)__popcll(m) << b;
+    }
+    wave_total = tot;
+    return pre;
+}
+
+// Workgroup exclusive prefix of per-thread counts (all threads must call).
+// lds_waves holds one word per wave; the caller syncs before reusing it.
+template <int BLOCK, int BITS>
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t x, uint32_t *lds_waves,
+                                                         uint32_t &block_total) {
+    constexpr int W = BLOCK / kWave;
+    uint32_t wave_total;
+    uint32_t pre = wave_exclusive_scan_small<BITS>(x, wave_total);
+    const int w = threadIdx.x / kWave;
+    if (W == 1) {
+        block_total = wave_total;
+        return pre;
+    }
+    if (lane_id() == 0) lds_waves[w] = wave_total;
+    __syncthreads();
+    uint32_t before = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < W; ++i) {
+        uint32_t t = lds_waves[i];
+        before += i < w ? t : 0u;
+        tot += t;
+    }
+    block_total = tot;
+    return before + pre;
+}
+
+// ----------------------------------------------------- BlockAggregate ------
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t x) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        uint32_t lo = __shfl_xor((uint32_t)x, o);
+        uint32_t hi = __shfl_xor((uint32_t)(x >> 32), o);
+        x += ((uint64_t)hi << 32) | lo;
+    }
+    return x;
+}
+
+// Hierarchical reduction; the result is valid in thread 0.
+template <int BLOCK>
+__device__ __forceinline__ uint64_t block_sum_u64(uint64_t x, uint64_t *lds_waves) {
+    constexpr int W = BLOCK / kWave;
+    x = wave_sum_u64(x);
+    if (W == 1) return x;
+    if (lane_id() == 0) lds_waves[threadIdx.x / kWave] = x;
+    __syncthreads();
+    uint64_t t = 0;
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int i = 0; i < W; ++i) t += lds_waves[i];
+    return t;
+}
+
+// ------------------------------------------------------------- atomics -----
+__device__ __forceinline__ uint64_t atomic_add_u64(uint64_t *p, uint64_t v) {
+    return atomicAdd(reinterpret_cast<unsigned long long *>(p), (unsigned long long)v);
+}
+
+__device__ __forceinline__ void set_status(int32_t *status, int32_t code) {
+    if (status) atomicCAS(status, 0, code);
+}
+
+// --------------------------------------------------------- hash tables -----
+struct DevTable {
+    const uint32_t *bitmap;   // DIRECT presence bits
+    const int32_t *payload;   // DIRECT payloads (or null)
+    const v2i *slots;         // LINEAR {key, payload}
+    int64_t span;             // DIRECT key span
+    uint32_t mask;            // LINEAR capacity - 1
+    int32_t key_min;          // DIRECT
+    int32_t kind;             // 0 LINEAR, 1 DIRECT
+    int32_t shift;            // LINEAR 32 - log2 capacity
+    int32_t has_payload;
+    int32_t pad;
+};
+
+__device__ __forceinline__ uint32_t hash_slot(int32_t k, int32_t shift) {
+    return ((uint32_t)k * 2654435761u) >> shift;
+}
+
+// BlockProbeHT for one item: returns whether key k is present and its payload.
+__device__ __forceinline__ bool probe_direct(const DevTable &t, int32_t k, int32_t &payload,
+                                             bool want_payload) {
+    uint32_t off = (uint32_t)k - (uint32_t)t.key_min;
+    if ((int64_t)off >= t.span) return false;
+    bool hit = (t.bitmap[off >> 5] >> (off & 31u)) & 1u;
+    if (hit && want_payload) payload = t.payload[off];
+    return hit;
+}
+
+__device__ __forceinline__ bool probe_linear(const v2i *__restrict__ slots, uint32_t mask,
+                                             int32_t shift, int32_t k, int32_t &payload) {
+    uint32_t s = hash_slot(k, shift);
+    for (uint32_t step = 0; step <= mask; ++step) {
+        v2i e = slots[s];
+        if (e.x == k) {
+            payload = e.y;
+            return true;
+        }
+        if (e.x == kEmptyKey) return false;
+        s = (s + 1u) & mask;
+    }
+    return false;
+}
+
+__device__ __forceinline__ bool probe_table(const DevTable &t, int32_t k, int32_t &payload,
+                                            bool want_payload) {
+    if (t.kind == 1) return probe_direct(t, k, payload, want_payload);
+    if (k == kEmptyKey) return false;
+    return probe_linear(t.slots, t.mask, t.shift, k, payload);
+}
+
+// Payload field extraction: bits == 32 takes the payload as a signed int32.
+__device__ __forceinline__ int32_t payload_field(int32_t payload, int32_t shift, uint32_t mask,
+                                                 int32_t bits) {
+    return bits >= 32 ? payload : (int32_t)(((uint32_t)payload >> shift) & mask);
+}
+
+}  // namespace crystal

@@ -1,0 +1,404 @@
+// C ABI entry points: argument validation, plan translation, tuning table.
+// Every compute step runs in the kernels of scan_ops.hip, hash_ops.hip and
+// star.hip; this file only checks arguments and launches them.
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <mutex>
+#include <vector>
+
+#include "block.hpp"
+#include "internal.hpp"
+#include "variants.hpp"
+
+namespace crystal {
+
+// ------------------------------------------------------------ device info --
+static int g_cu[64];
+static int64_t g_lds[64];
+
+static int cur_device() {
+    int d = 0;
+    if (hipGetDevice(&d) != hipSuccess || d < 0 || d >= 64) d = 0;
+    return d;
+}
+
+int device_cu_count() {
+    const int d = cur_device();
+    if (!g_cu[d]) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, d) != hipSuccess || v <= 0)
+            v = 256;
+        g_cu[d] = v;
+    }
+    return g_cu[d];
+}
+
+int64_t device_lds_per_block() {
+    const int d = cur_device();
+    if (!g_lds[d]) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, d) != hipSuccess || v <= 0)
+            v = 65536;
+        g_lds[d] = v;
+    }
+    return g_lds[d];
+}
+
+// ----------------------------------------------------------------- tuning --
+struct TuneEntry {
+    int kernel, blo, bhi;
+    LaunchCfg cfg;
+};
+
+static std::mutex g_tune_mu;
+static std::vector<TuneEntry> g_tune;
+
+static LaunchCfg default_cfg(int kernel) {
+    switch (kernel) {
+    case CRYSTAL_K_SELECT: return {256, 16, 0};
+    case CRYSTAL_K_PROJECT: return {256, 16, 0};
+    case CRYSTAL_K_HT_PROBE: return {256, 16, 8};
+    case CRYSTAL_K_GROUPBY: return {256, 16, 0};
+    case CRYSTAL_K_STAR: return {256, 16, 0};
+    case CRYSTAL_K_SHARED_SCAN: return {256, 16, 4};
+    default: return {256, 16, 0};
+    }
+}
+
+static int size_bucket(int64_t n) {
+    int b = 0;
+    while (b < 62 && (int64_t(1) << (b + 1)) <= n) ++b;
+    return b;
+}
+
+LaunchCfg tune_lookup(int kernel, int64_t n) {
+    const int b = size_bucket(n);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (auto it = g_tune.rbegin(); it != g_tune.rend(); ++it)
+        if (it->kernel == kernel && b >= it->blo && b <= it->bhi) return it->cfg;
+    return default_cfg(kernel);
+}
+
+static bool variant_exists(int kernel, int block, int ipt) {
+    const int key = CRYSTAL_VARIANT_KEY(block, ipt);
+    if (kernel == CRYSTAL_K_SELECT) {
+        switch (key) {
+#define X(B, I) case CRYSTAL_VARIANT_KEY(B, I): return true;
+            CRYSTAL_VARIANTS_ALL(X)
+#undef X
+        default: return false;
+        }
+    }
+    switch (key) {
+#define X(B, I) case CRYSTAL_VARIANT_KEY(B, I): return true;
+        CRYSTAL_VARIANTS_VEC(X)
+#undef X
+    default: return false;
+    }
+}
+
+static hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+// ------------------------------------------------------- plan translation --
+static uint32_t field_mask(int bits) { return bits >= 32 ? 0xffffffffu : ((1u << bits) - 1u); }
+
+static bool ht_valid(const crystal_ht &ht) {
+    if (!ht.mem || !aligned16(ht.mem) || ht.capacity <= 0) return false;
+    if (ht.kind == CRYSTAL_HT_LINEAR)
+        return ht.log2_capacity >= 6 && ht.log2_capacity <= 31 &&
+               ht.capacity == (int64_t(1) << ht.log2_capacity);
+    if (ht.kind == CRYSTAL_HT_DIRECT) return ht.capacity <= (int64_t(1) << 32);
+    return false;
+}
+
+static int64_t bitmap_words(int64_t span) { return ((span + 31) / 32 + 63) / 64 * 64; }
+
+crystal_status star_plan_to_dev(const crystal_star_query &q, StarPlanDev &d) {
+    memset(&d, 0, sizeof(d));
+    if (q.n_rows < 0 || q.n_cols < 0 || q.n_cols > CRYSTAL_MAX_COLS || q.n_preds < 0 ||
+        q.n_preds > CRYSTAL_MAX_PREDS || q.n_joins < 0 || q.n_joins > CRYSTAL_MAX_JOINS ||
+        q.n_groups < 1 || q.n_groups > INT32_MAX || q.agg < 0 || q.agg > CRYSTAL_AGG_COUNT)
+        return CRYSTAL_EINVAL;
+    // a plan over zero rows may carry null column pointers (nothing is read)
+    auto col_ok = [&](int c) {
+        return c >= 0 && c < q.n_cols && (q.n_rows == 0 || (q.cols[c] && aligned16(q.cols[c])));
+    };
+    for (int c = 0; c < q.n_cols; ++c) {
+        if (q.cols[c] && !aligned16(q.cols[c])) return CRYSTAL_EINVAL;
+        d.cols[c] = q.cols[c];
+    }
+    d.n_rows = q.n_rows;
+    d.n_groups = q.n_groups;
+    d.n_preds = q.n_preds;
+    d.n_joins = q.n_joins;
+    for (int i = 0; i < q.n_preds; ++i) {
+        if (!col_ok(q.preds[i].col)) return CRYSTAL_EINVAL;
+        d.pred_col[i] = q.preds[i].col;
+        d.pred_lo[i] = q.preds[i].range.lo;
+        d.pred_hi[i] = q.preds[i].range.hi;
+    }
+    d.agg = q.agg;
+    d.agg_col0 = q.agg_col0;
+    d.agg_col1 = q.agg_col1;
+    if (q.agg != CRYSTAL_AGG_COUNT && !col_ok(q.agg_col0)) return CRYSTAL_EINVAL;
+    if ((q.agg == CRYSTAL_AGG_SUM_PRODUCT || q.agg == CRYSTAL_AGG_SUM_DIFF) && !col_ok(q.agg_col1))
+        return CRYSTAL_EINVAL;
+    bool any_group = false;
+    for (int i = 0; i < q.n_joins; ++i) {
+        const crystal_join &j = q.joins[i];
+        StarJoinDev &o = d.joins[i];
+        if (!ht_valid(j.ht) || !col_ok(j.fk_col)) return CRYSTAL_EINVAL;
+        if (j.filter_bits < 0 || j.filter_bits > 32 || j.group_bits < 0 || j.group_bits > 32)
+            return CRYSTAL_EINVAL;
+        if (j.filter_shift < 0 || j.filter_shift > 31 || j.group_shift < 0 || j.group_shift > 31)
+            return CRYSTAL_EINVAL;
+        if ((j.filter_bits > 0 || j.group_bits > 0) && !j.ht.has_payload) return CRYSTAL_EINVAL;
+        o.kind = j.ht.kind;
+        o.has_payload = j.ht.has_payload;
+        if (j.ht.kind == CRYSTAL_HT_DIRECT) {
+            o.bitmap = (const uint32_t *)j.ht.mem;
+            o.payload = j.ht.has_payload ? (const int32_t *)j.ht.mem + bitmap_words(j.ht.capacity) : nullptr;
+            o.span = j.ht.capacity;
+            o.key_min = j.ht.key_min;
+        } else {
+            o.slots = j.ht.mem;
+            o.mask = (uint32_t)(j.ht.capacity - 1);
+            o.shift = 32 - j.ht.log2_capacity;
+        }
+        o.fk_col = j.fk_col;
+        o.f_bits = j.filter_bits;
+        o.f_shift = j.filter_shift;
+        o.f_mask = field_mask(j.filter_bits);
+        o.f_lo = j.filter.lo;
+        o.f_hi = j.filter.hi;
+        o.g_bits = j.group_bits;
+        o.g_shift = j.group_shift;
+        o.g_mask = field_mask(j.group_bits);
+        o.g_base = j.group_base;
+        o.g_stride = j.group_stride;
+        if (j.group_bits > 0) any_group = true;
+    }
+    d.scalar = (q.n_groups == 1 && !any_group) ? 1 : 0;
+    return CRYSTAL_OK;
+}
+
+}  // namespace crystal
+
+using namespace crystal;
+
+extern "C" {
+
+const char *crystal_status_string(int32_t s) {
+    switch (s) {
+    case CRYSTAL_OK: return "ok";
+    case CRYSTAL_EINVAL: return "invalid argument";
+    case CRYSTAL_ESCRATCH: return "scratch or slot memory too small";
+    case CRYSTAL_EFULL: return "hash table full";
+    case CRYSTAL_EDUPKEY: return "duplicate build key";
+    case CRYSTAL_EHIP: return "HIP runtime error";
+    case CRYSTAL_EBUSY: return "no free slot";
+    case CRYSTAL_ERANGE: return "key or group index out of range";
+    default: return "unknown status";
+    }
+}
+
+int32_t crystal_abi_version(void) { return CRYSTAL_ABI_VERSION; }
+
+size_t crystal_struct_size(int32_t which) {
+    switch (which) {
+    case 0: return sizeof(crystal_range);
+    case 1: return sizeof(crystal_ht);
+    case 2: return sizeof(crystal_pred);
+    case 3: return sizeof(crystal_join);
+    case 4: return sizeof(crystal_star_query);
+    default: return 0;
+    }
+}
+
+crystal_status crystal_select(const int32_t *in, int64_t n, crystal_range pred, int32_t *out,
+                              int64_t *out_count, void *stream) {
+    if (n < 0 || !out_count || (n > 0 && (!in || !out || !aligned16(in))))
+        return CRYSTAL_EINVAL;
+    hipStream_t s = as_stream(stream);
+    hipError_t e = fill_u64((uint64_t *)out_count, 1, 0ull, s);
+    if (e != hipSuccess) return CRYSTAL_EHIP;
+    if (n == 0 || pred.lo > pred.hi) return CRYSTAL_OK;
+    return from_hip(launch_select(tune_lookup(CRYSTAL_K_SELECT, n), in, n, pred.lo, pred.hi, out,
+                                  (uint64_t *)out_count, s));
+}
+
+static crystal_status project_common(const float *x1, const float *x2, int64_t n, float a, float b,
+                                     float *out, void *stream, bool sigmoid) {
+    if (n < 0 || (n > 0 && (!x1 || !x2 || !out || !aligned16(x1) || !aligned16(x2) || !aligned16(out))))
+        return CRYSTAL_EINVAL;
+    if (n == 0) return CRYSTAL_OK;
+    return from_hip(launch_project(tune_lookup(CRYSTAL_K_PROJECT, n), x1, x2, n, a, b, out, sigmoid,
+                                   as_stream(stream)));
+}
+
+crystal_status crystal_project(const float *x1, const float *x2, int64_t n, float a, float b,
+                               float *out, void *stream) {
+    return project_common(x1, x2, n, a, b, out, stream, false);
+}
+
+crystal_status crystal_project_sigmoid(const float *x1, const float *x2, int64_t n, float a, float b,
+                                       float *out, void *stream) {
+    return project_common(x1, x2, n, a, b, out, stream, true);
+}
+
+crystal_status crystal_ht_init(crystal_ht *ht, int32_t kind, int64_t n_keys, int32_t key_min,
+                               int32_t key_max, int32_t has_payload) {
+    if (!ht || n_keys < 0) return CRYSTAL_EINVAL;
+    memset(ht, 0, sizeof(*ht));
+    ht->kind = kind;
+    ht->has_payload = has_payload ? 1 : 0;
+    if (kind == CRYSTAL_HT_LINEAR) {
+        int l = 6;
+        while ((int64_t(1) << l) < 2 * n_keys) ++l;
+        if (l > 31) return CRYSTAL_EINVAL;
+        ht->log2_capacity = l;
+        ht->capacity = int64_t(1) << l;
+        return CRYSTAL_OK;
+    }
+    if (kind == CRYSTAL_HT_DIRECT) {
+        if (key_max < key_min) return CRYSTAL_EINVAL;
+        ht->key_min = key_min;
+        ht->capacity = (int64_t)key_max - (int64_t)key_min + 1;
+        return CRYSTAL_OK;
+    }
+    return CRYSTAL_EINVAL;
+}
+
+size_t crystal_ht_bytes(const crystal_ht *ht) {
+    if (!ht || ht->capacity <= 0) return 0;
+    if (ht->kind == CRYSTAL_HT_LINEAR) return (size_t)ht->capacity * 8;
+    if (ht->kind == CRYSTAL_HT_DIRECT)
+        return (size_t)bitmap_words(ht->capacity) * 4 + (ht->has_payload ? (size_t)ht->capacity * 4 : 0);
+    return 0;
+}
+
+crystal_status crystal_ht_build(const crystal_ht *ht, const int32_t *keys, const int32_t *payload,
+                                const int32_t *filter_col, crystal_range filter, int64_t n,
+                                int32_t *status, void *stream) {
+    if (!ht || !ht_valid(*ht) || n < 0 || !status || (n > 0 && !keys) ||
+        (ht->has_payload && n > 0 && !payload))
+        return CRYSTAL_EINVAL;
+    return from_hip(launch_ht_build(*ht, keys, ht->has_payload ? payload : nullptr, filter_col,
+                                    filter.lo, filter.hi, n, status, as_stream(stream)));
+}
+
+crystal_status crystal_ht_probe(const crystal_ht *ht, const int32_t *fk, const int32_t *probe_payload,
+                                int64_t n, int64_t *out_sum, int64_t *out_matches, void *stream) {
+    if (!ht || !ht_valid(*ht) || n < 0 || !out_sum || !out_matches || (n > 0 && (!fk || !aligned16(fk))) ||
+        (probe_payload && !aligned16(probe_payload)))
+        return CRYSTAL_EINVAL;
+    return from_hip(launch_ht_probe(tune_lookup(CRYSTAL_K_HT_PROBE, n), *ht, fk, probe_payload, n,
+                                    (uint64_t *)out_sum, (uint64_t *)out_matches, as_stream(stream)));
+}
+
+crystal_status crystal_groupby_agg(const int32_t *group, const int32_t *value, int64_t n,
+                                   int64_t n_groups, int64_t *sums, int32_t *status, void *stream) {
+    if (n < 0 || n_groups < 1 || !sums || !status ||
+        (n > 0 && (!group || !value || !aligned16(group) || !aligned16(value))))
+        return CRYSTAL_EINVAL;
+    return from_hip(launch_groupby(tune_lookup(CRYSTAL_K_GROUPBY, n), group, value, n, n_groups,
+                                   (uint64_t *)sums, status, as_stream(stream)));
+}
+
+crystal_status crystal_run_star_query(const crystal_star_query *q, int64_t *out, int32_t *status,
+                                      void *stream) {
+    if (!q || !out || !status) return CRYSTAL_EINVAL;
+    StarPlanDev d;
+    crystal_status st = star_plan_to_dev(*q, d);
+    if (st != CRYSTAL_OK) return st;
+    return from_hip(launch_star(tune_lookup(CRYSTAL_K_STAR, q->n_rows), d, (uint64_t *)out, status,
+                                as_stream(stream)));
+}
+
+// ----------------------------------------------------------------- tuning --
+int32_t crystal_tune_variants(int32_t kernel, int32_t *blocks, int32_t *ipts, int32_t max) {
+    if (kernel < 0 || kernel >= CRYSTAL_K_COUNT) return 0;
+    int32_t n = 0;
+    auto add = [&](int b, int i) {
+        if (blocks && ipts && n < max) {
+            blocks[n] = b;
+            ipts[n] = i;
+        }
+        ++n;
+    };
+    if (kernel == CRYSTAL_K_SELECT) {
+#define X(B, I) add(B, I);
+        CRYSTAL_VARIANTS_ALL(X)
+#undef X
+    } else {
+#define X(B, I) add(B, I);
+        CRYSTAL_VARIANTS_VEC(X)
+#undef X
+    }
+    return n;
+}
+
+crystal_status crystal_tune_set(int32_t kernel, int32_t bucket_lo, int32_t bucket_hi, int32_t block,
+                                int32_t ipt, int32_t grid_per_cu) {
+    if (kernel < 0 || kernel >= CRYSTAL_K_COUNT || !variant_exists(kernel, block, ipt) || grid_per_cu < 0 ||
+        grid_per_cu > 64)
+        return CRYSTAL_EINVAL;
+    if (bucket_lo < 0 && bucket_hi < 0) {
+        bucket_lo = 0;
+        bucket_hi = 63;
+    }
+    if (bucket_lo < 0 || bucket_hi < bucket_lo) return CRYSTAL_EINVAL;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.push_back({kernel, bucket_lo, bucket_hi, {block, ipt, grid_per_cu}});
+    return CRYSTAL_OK;
+}
+
+crystal_status crystal_tune_get(int32_t kernel, int64_t n, int32_t *block, int32_t *ipt,
+                                int32_t *grid_per_cu) {
+    if (kernel < 0 || kernel >= CRYSTAL_K_COUNT || !block || !ipt || !grid_per_cu) return CRYSTAL_EINVAL;
+    LaunchCfg c = tune_lookup(kernel, n);
+    *block = c.block;
+    *ipt = c.ipt;
+    *grid_per_cu = c.grid_per_cu;
+    return CRYSTAL_OK;
+}
+
+void crystal_tune_reset(void) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.clear();
+}
+
+crystal_status crystal_tune_load(const char *path) {
+    if (!path) return CRYSTAL_EINVAL;
+    FILE *f = fopen(path, "r");
+    if (!f) return CRYSTAL_EINVAL;
+    char line[256];
+    crystal_status st = CRYSTAL_OK;
+    while (fgets(line, sizeof line, f)) {
+        if (line[0] == '#' || line[0] == '\n') continue;
+        int k, lo, hi, b, i, g;
+        if (sscanf(line, "%d %d %d %d %d %d", &k, &lo, &hi, &b, &i, &g) != 6) {
+            st = CRYSTAL_EINVAL;
+            continue;
+        }
+        if (crystal_tune_set(k, lo, hi, b, i, g) != CRYSTAL_OK) st = CRYSTAL_EINVAL;
+    }
+    fclose(f);
+    return st;
+}
+
+crystal_status crystal_tune_save(const char *path) {
+    if (!path) return CRYSTAL_EINVAL;
+    FILE *f = fopen(path, "w");
+    if (!f) return CRYSTAL_EINVAL;
+    fprintf(f, "# kernel bucket_lo bucket_hi block ipt grid_per_cu\n");
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const auto &t : g_tune)
+        fprintf(f, "%d %d %d %d %d %d\n", t.kernel, t.blo, t.bhi, t.cfg.block, t.cfg.ipt, t.cfg.grid_per_cu);
+    fclose(f);
+    return CRYSTAL_OK;
+}
+
+}  // extern "C"

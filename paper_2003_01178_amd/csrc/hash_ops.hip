@@ -1,0 +1,299 @@
+// Hash-join build and probe (section 4.3; perfect hashing of section 5.3)
+// and the dense group-by aggregate.
+#include "block.hpp"
+#include "internal.hpp"
+#include "variants.hpp"
+
+namespace crystal {
+
+static constexpr uint64_t kEmptySlot = (uint64_t)(uint32_t)kEmptyKey;  // {EMPTY, 0}
+
+static inline int64_t direct_bitmap_words(int64_t span) {
+    int64_t w = (span + 31) / 32;
+    return (w + 63) / 64 * 64;
+}
+
+static DevTable to_dev(const crystal_ht &ht) {
+    DevTable t = {};
+    t.kind = ht.kind;
+    t.has_payload = ht.has_payload;
+    if (ht.kind == CRYSTAL_HT_DIRECT) {
+        t.bitmap = (const uint32_t *)ht.mem;
+        t.payload = ht.has_payload ? (const int32_t *)ht.mem + direct_bitmap_words(ht.capacity)
+                                   : nullptr;
+        t.span = ht.capacity;
+        t.key_min = ht.key_min;
+    } else {
+        t.slots = (const v2i *)ht.mem;
+        t.mask = (uint32_t)(ht.capacity - 1);
+        t.shift = 32 - ht.log2_capacity;
+    }
+    return t;
+}
+
+hipError_t launch_ht_clear(const crystal_ht &ht, hipStream_t s) {
+    if (ht.kind == CRYSTAL_HT_DIRECT)
+        return fill_u32((uint32_t *)ht.mem, direct_bitmap_words(ht.capacity), 0u, s);
+    return fill_u64((uint64_t *)ht.mem, ht.capacity, kEmptySlot, s);
+}
+
+// --------------------------------------------------------------- build ----
+// One thread per build row: a 64-bit compare-and-swap claims an empty slot
+// {EMPTY, 0} -> {key, payload} (linear probing), or an atomic OR sets the
+// key's presence bit and the payload is stored (direct table).
+template <int KIND>
+__global__ __launch_bounds__(256) void ht_build_kernel(DevTable t, const int32_t *__restrict__ keys,
+                                                       const int32_t *__restrict__ payload,
+                                                       const int32_t *__restrict__ filter_col,
+                                                       int32_t flo, int32_t fhi, int64_t n,
+                                                       int32_t *status) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        if (filter_col && !in_range(filter_col[i], flo, fhi)) continue;
+        const int32_t k = keys[i];
+        const int32_t v = payload ? payload[i] : 0;
+        if constexpr (KIND == CRYSTAL_HT_DIRECT) {
+            const uint32_t off = (uint32_t)k - (uint32_t)t.key_min;
+            if ((int64_t)off >= t.span) {
+                set_status(status, CRYSTAL_ERANGE);
+                continue;
+            }
+            const uint32_t bit = 1u << (off & 31u);
+            const uint32_t old = atomicOr(const_cast<uint32_t *>(t.bitmap) + (off >> 5), bit);
+            if (old & bit) {
+                set_status(status, CRYSTAL_EDUPKEY);
+                continue;
+            }
+            if (t.payload) const_cast<int32_t *>(t.payload)[off] = v;
+        } else {
+            if (k == kEmptyKey) {
+                set_status(status, CRYSTAL_EINVAL);
+                continue;
+            }
+            unsigned long long *slots = (unsigned long long *)const_cast<v2i *>(t.slots);
+            const unsigned long long want = (unsigned long long)(uint32_t)k |
+                                            ((unsigned long long)(uint32_t)v << 32);
+            uint32_t sl = hash_slot(k, t.shift);
+            bool placed = false;
+            for (uint32_t step = 0; step <= t.mask; ++step) {
+                const unsigned long long old = atomicCAS(slots + sl, (unsigned long long)kEmptySlot, want);
+                if (old == kEmptySlot) {
+                    placed = true;
+                    break;
+                }
+                if ((int32_t)(uint32_t)old == k) {
+                    set_status(status, CRYSTAL_EDUPKEY);
+                    placed = true;
+                    break;
+                }
+                sl = (sl + 1u) & t.mask;
+            }
+            if (!placed) set_status(status, CRYSTAL_EFULL);
+        }
+    }
+}
+
+hipError_t launch_ht_build(const crystal_ht &ht, const int32_t *keys, const int32_t *payload,
+                           const int32_t *filter_col, int32_t flo, int32_t fhi, int64_t n,
+                           int32_t *status, hipStream_t s) {
+    hipError_t e = launch_ht_clear(ht, s);
+    if (e != hipSuccess || n == 0) return e;
+    const DevTable t = to_dev(ht);
+    int64_t grid = (n + 255) / 256;
+    const int64_t cap = (int64_t)device_cu_count() * 32;
+    if (grid > cap) grid = cap;
+    if (ht.kind == CRYSTAL_HT_DIRECT)
+        hipLaunchKernelGGL(ht_build_kernel<CRYSTAL_HT_DIRECT>, dim3((unsigned)grid), dim3(256), 0, s,
+                           t, keys, payload, filter_col, flo, fhi, n, status);
+    else
+        hipLaunchKernelGGL(ht_build_kernel<CRYSTAL_HT_LINEAR>, dim3((unsigned)grid), dim3(256), 0, s,
+                           t, keys, payload, filter_col, flo, fhi, n, status);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------- probe ----
+// Query Q4: BlockLoad a tile of probe keys (and probe payloads), probe every
+// item, keep a per-thread sum and match count, BlockAggregate, and add the
+// workgroup's totals with two 64-bit atomics.  MODE 0: linear probing in
+// global memory; MODE 1: linear probing in a copy of the table staged in LDS
+// once per workgroup; MODE 2: direct table.
+template <int BLOCK, int IPT, int MODE>
+__global__ __launch_bounds__(BLOCK) void ht_probe_kernel(DevTable t, const int32_t *__restrict__ fk,
+                                                         const int32_t *__restrict__ pp, int64_t n,
+                                                         uint64_t *__restrict__ out_sum,
+                                                         uint64_t *__restrict__ out_cnt,
+                                                         int64_t n_tiles) {
+    using T = TileShape<BLOCK, IPT>;
+    extern __shared__ v4i lds_raw[];
+    __shared__ uint64_t red[T::WAVES];
+    const v2i *slots = t.slots;
+    if constexpr (MODE == 1) {
+        // stage the whole table: capacity * 8 bytes, 16 bytes per load
+        const int64_t n16 = ((int64_t)t.mask + 1) / 2;
+        const v4i *src = reinterpret_cast<const v4i *>(t.slots);
+        for (int64_t i = threadIdx.x; i < n16; i += BLOCK) lds_raw[i] = src[i];
+        __syncthreads();
+        slots = reinterpret_cast<const v2i *>(lds_raw);
+    }
+    uint64_t sum = 0, cnt = 0;
+    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        const int64_t base = tile * T::ITEMS;
+        int32_t key[IPT], pv[IPT];
+        block_load<BLOCK, IPT, true>(fk, base, n, key);
+        if (pp) block_load<BLOCK, IPT, true>(pp, base, n, pv);
+        const uint32_t valid = valid_mask<BLOCK, IPT>(base, n);
+#pragma unroll
+        for (int k = 0; k < IPT; ++k) {
+            if (!((valid >> k) & 1u)) continue;
+            int32_t pay = 0;
+            bool hit;
+            if constexpr (MODE == 2)
+                hit = probe_direct(t, key[k], pay, t.has_payload);
+            else
+                hit = key[k] != kEmptyKey && probe_linear(slots, t.mask, t.shift, key[k], pay);
+            if (hit) {
+                sum += (uint64_t)(int64_t)pay + (pp ? (uint64_t)(int64_t)pv[k] : 0ull);
+                cnt += 1;
+            }
+        }
+    }
+    const uint64_t bs = block_sum_u64<BLOCK>(sum, red);
+    __syncthreads();
+    const uint64_t bc = block_sum_u64<BLOCK>(cnt, red);
+    if (threadIdx.x == 0) {
+        if (bs) atomic_add_u64(out_sum, bs);
+        if (bc) atomic_add_u64(out_cnt, bc);
+    }
+}
+
+template <int BLOCK, int IPT>
+static hipError_t probe_t(const LaunchCfg &cfg_in, const crystal_ht &ht, const int32_t *fk,
+                          const int32_t *pp, int64_t n, uint64_t *out, uint64_t *cnt, hipStream_t s) {
+    using T = TileShape<BLOCK, IPT>;
+    const int64_t n_tiles = (n + T::ITEMS - 1) / T::ITEMS;
+    const DevTable t = to_dev(ht);
+    LaunchCfg cfg = cfg_in;
+    const int64_t table_bytes = ht.kind == CRYSTAL_HT_LINEAR ? ht.capacity * 8 : 0;
+    const bool stage = ht.kind == CRYSTAL_HT_LINEAR && table_bytes <= device_lds_per_block() - 4096;
+    if (stage && cfg.grid_per_cu <= 0) cfg.grid_per_cu = 1;  // stage once per resident workgroup
+    const int64_t grid = grid_for(n_tiles, cfg);
+    if (grid == 0) return hipSuccess;
+    if (ht.kind == CRYSTAL_HT_DIRECT) {
+        hipLaunchKernelGGL((ht_probe_kernel<BLOCK, IPT, 2>), dim3((unsigned)grid), dim3(BLOCK), 0, s,
+                           t, fk, pp, n, out, cnt, n_tiles);
+    } else if (stage) {
+        auto fn = ht_probe_kernel<BLOCK, IPT, 1>;
+        hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)table_bytes);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(BLOCK), (size_t)table_bytes, s, t, fk, pp, n,
+                           out, cnt, n_tiles);
+    } else {
+        hipLaunchKernelGGL((ht_probe_kernel<BLOCK, IPT, 0>), dim3((unsigned)grid), dim3(BLOCK), 0, s,
+                           t, fk, pp, n, out, cnt, n_tiles);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_ht_probe(const LaunchCfg &cfg, const crystal_ht &ht, const int32_t *fk,
+                           const int32_t *probe_payload, int64_t n, uint64_t *sum, uint64_t *count,
+                           hipStream_t s) {
+    hipError_t e = zero_pair(sum, count, s);
+    if (e != hipSuccess || n == 0) return e;
+    switch (CRYSTAL_VARIANT_KEY(cfg.block, cfg.ipt)) {
+#define X(B, I) \
+    case CRYSTAL_VARIANT_KEY(B, I): return probe_t<B, I>(cfg, ht, fk, probe_payload, n, sum, count, s);
+        CRYSTAL_VARIANTS_VEC(X)
+#undef X
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// -------------------------------------------------------------- group-by ---
+// LDS_PART: each workgroup accumulates into an LDS copy of the group array
+// (ds_add_u64) over the tiles it strides through, then flushes the non-zero
+// entries with global 64-bit atomics.  Otherwise every row adds directly.
+template <int BLOCK, int IPT, bool LDS_PART>
+__global__ __launch_bounds__(BLOCK) void groupby_kernel(const int32_t *__restrict__ g,
+                                                        const int32_t *__restrict__ v, int64_t n,
+                                                        int64_t n_groups,
+                                                        uint64_t *__restrict__ sums,
+                                                        int32_t *status, int64_t n_tiles) {
+    using T = TileShape<BLOCK, IPT>;
+    extern __shared__ uint64_t part[];
+    if constexpr (LDS_PART) {
+        for (int64_t i = threadIdx.x; i < n_groups; i += BLOCK) part[i] = 0;
+        __syncthreads();
+    }
+    bool bad = false;
+    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        const int64_t base = tile * T::ITEMS;
+        int32_t gk[IPT], vk[IPT];
+        block_load<BLOCK, IPT, true>(g, base, n, gk);
+        block_load<BLOCK, IPT, true>(v, base, n, vk);
+        const uint32_t valid = valid_mask<BLOCK, IPT>(base, n);
+#pragma unroll
+        for (int k = 0; k < IPT; ++k) {
+            if (!((valid >> k) & 1u)) continue;
+            if ((uint64_t)(int64_t)gk[k] >= (uint64_t)n_groups) {
+                bad = true;
+                continue;
+            }
+            const uint64_t add = (uint64_t)(int64_t)vk[k];
+            if constexpr (LDS_PART)
+                atomicAdd((unsigned long long *)&part[gk[k]], (unsigned long long)add);
+            else
+                atomic_add_u64(sums + gk[k], add);
+        }
+    }
+    if (bad) set_status(status, CRYSTAL_ERANGE);
+    if constexpr (LDS_PART) {
+        __syncthreads();
+        for (int64_t i = threadIdx.x; i < n_groups; i += BLOCK) {
+            const uint64_t x = part[i];
+            if (x) atomic_add_u64(sums + i, x);
+        }
+    }
+}
+
+template <int BLOCK, int IPT>
+static hipError_t groupby_t(const LaunchCfg &cfg_in, const int32_t *g, const int32_t *v, int64_t n,
+                            int64_t n_groups, uint64_t *sums, int32_t *status, hipStream_t s) {
+    using T = TileShape<BLOCK, IPT>;
+    const int64_t n_tiles = (n + T::ITEMS - 1) / T::ITEMS;
+    LaunchCfg cfg = cfg_in;
+    const int64_t lds = n_groups * 8;
+    // LDS partials pay off when every workgroup sees many rows per group
+    const bool part = lds <= device_lds_per_block() / 2 && n >= 64 * n_groups * (int64_t)device_cu_count();
+    if (part && cfg.grid_per_cu <= 0) cfg.grid_per_cu = 2;
+    const int64_t grid = grid_for(n_tiles, cfg);
+    if (grid == 0) return hipSuccess;
+    if (part) {
+        auto fn = groupby_kernel<BLOCK, IPT, true>;
+        hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(BLOCK), (size_t)lds, s, g, v, n, n_groups,
+                           sums, status, n_tiles);
+    } else {
+        hipLaunchKernelGGL((groupby_kernel<BLOCK, IPT, false>), dim3((unsigned)grid), dim3(BLOCK), 0, s,
+                           g, v, n, n_groups, sums, status, n_tiles);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_groupby(const LaunchCfg &cfg, const int32_t *group, const int32_t *value,
+                          int64_t n, int64_t n_groups, uint64_t *sums, int32_t *status,
+                          hipStream_t s) {
+    hipError_t e = fill_u64(sums, n_groups, 0ull, s);
+    if (e != hipSuccess || n == 0) return e;
+    switch (CRYSTAL_VARIANT_KEY(cfg.block, cfg.ipt)) {
+#define X(B, I) \
+    case CRYSTAL_VARIANT_KEY(B, I): return groupby_t<B, I>(cfg, group, value, n, n_groups, sums, status, s);
+        CRYSTAL_VARIANTS_VEC(X)
+#undef X
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace crystal

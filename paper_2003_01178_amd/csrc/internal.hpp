@@ -1,0 +1,104 @@
+// Host-side internals shared by the C ABI and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "crystal.h"
+
+namespace crystal {
+
+struct LaunchCfg {
+    int block;
+    int ipt;
+    int grid_per_cu;  // 0: one workgroup per tile
+};
+
+// Compute units of the current device (cached per device).
+int device_cu_count();
+// Largest dynamic LDS a workgroup may allocate on the current device.
+int64_t device_lds_per_block();
+
+// Workgroups to launch for n_tiles tiles under cfg.
+inline int64_t grid_for(int64_t n_tiles, const LaunchCfg &cfg) {
+    if (n_tiles <= 0) return 0;
+    if (cfg.grid_per_cu <= 0) return n_tiles;
+    int64_t g = (int64_t)cfg.grid_per_cu * device_cu_count();
+    return g < n_tiles ? g : n_tiles;
+}
+
+LaunchCfg tune_lookup(int kernel, int64_t n);
+
+inline crystal_status from_hip(hipError_t e) {
+    return e == hipSuccess ? CRYSTAL_OK : CRYSTAL_EHIP;
+}
+
+inline bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+// ------------------------------------------------------------- launchers ----
+// Every launcher returns hipSuccess or the launch error; argument checking has
+// been done by the C ABI layer.
+hipError_t fill_u64(uint64_t *p, int64_t n, uint64_t value, hipStream_t s);
+hipError_t fill_u32(uint32_t *p, int64_t n, uint32_t value, hipStream_t s);
+// Zero two separate 64-bit words with one launch.
+hipError_t zero_pair(uint64_t *a, uint64_t *b, hipStream_t s);
+
+hipError_t launch_select(const LaunchCfg &cfg, const int32_t *in, int64_t n, int32_t lo,
+                         int32_t hi, int32_t *out, uint64_t *count, hipStream_t s);
+hipError_t launch_project(const LaunchCfg &cfg, const float *x1, const float *x2, int64_t n,
+                          float a, float b, float *out, bool sigmoid, hipStream_t s);
+
+struct DevTable;
+hipError_t launch_ht_clear(const crystal_ht &ht, hipStream_t s);
+hipError_t launch_ht_build(const crystal_ht &ht, const int32_t *keys, const int32_t *payload,
+                           const int32_t *filter_col, int32_t flo, int32_t fhi, int64_t n,
+                           int32_t *status, hipStream_t s);
+hipError_t launch_ht_probe(const LaunchCfg &cfg, const crystal_ht &ht, const int32_t *fk,
+                           const int32_t *probe_payload, int64_t n, uint64_t *sum, uint64_t *count,
+                           hipStream_t s);
+hipError_t launch_groupby(const LaunchCfg &cfg, const int32_t *group, const int32_t *value,
+                          int64_t n, int64_t n_groups, uint64_t *sums, int32_t *status,
+                          hipStream_t s);
+
+// Device form of a star query (validated, table descriptors resolved).
+struct StarJoinDev {
+    // table
+    const uint32_t *bitmap;
+    const int32_t *payload;
+    const void *slots;
+    int64_t span;
+    uint32_t mask;
+    int32_t key_min;
+    int32_t kind;
+    int32_t shift;
+    int32_t has_payload;
+    // plan
+    int32_t fk_col;
+    int32_t f_bits, f_shift;
+    uint32_t f_mask;
+    int32_t f_lo, f_hi;
+    int32_t g_bits, g_shift;
+    uint32_t g_mask;
+    int32_t g_base;
+    int64_t g_stride;
+};
+
+struct StarPlanDev {
+    const int32_t *cols[CRYSTAL_MAX_COLS];
+    int64_t n_rows;
+    int64_t n_groups;
+    int32_t n_preds;
+    int32_t n_joins;
+    int32_t pred_col[CRYSTAL_MAX_PREDS];
+    int32_t pred_lo[CRYSTAL_MAX_PREDS];
+    int32_t pred_hi[CRYSTAL_MAX_PREDS];
+    int32_t agg, agg_col0, agg_col1;
+    int32_t scalar;  // single group and no group fields: BlockAggregate path
+    StarJoinDev joins[CRYSTAL_MAX_JOINS];
+};
+
+crystal_status star_plan_to_dev(const crystal_star_query &q, StarPlanDev &d);
+hipError_t launch_star(const LaunchCfg &cfg, const StarPlanDev &plan, uint64_t *out,
+                       int32_t *status, hipStream_t s);
+
+}  // namespace crystal

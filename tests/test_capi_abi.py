@@ -1,0 +1,108 @@
+"""The C-ABI library loads and exports every symbol include/crystal.h declares;
+host-only calls (descriptors, tuning table, struct layout) work without a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "crystal.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(crystal_[a-z0-9_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def cx():
+    from paper_2003_01178_amd import crystal
+    crystal.load()
+    return crystal
+
+
+def test_every_declared_symbol_is_exported(cx):
+    names = declared_functions()
+    assert len(names) >= 15
+    lib = ctypes.CDLL(cx.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_struct_layout_matches_binding(cx):
+    lib = cx.load()
+    assert lib.crystal_abi_version() == 1
+    for which, ty in enumerate((cx.Range, cx.HT, cx.Pred, cx.Join, cx.StarQueryC)):
+        assert lib.crystal_struct_size(which) == ctypes.sizeof(ty), ty.__name__
+    assert lib.crystal_struct_size(99) == 0
+
+
+def test_status_strings(cx):
+    lib = cx.load()
+    for code in range(8):
+        assert lib.crystal_status_string(code).decode() not in ("", "unknown status")
+    assert lib.crystal_status_string(1234).decode() == "unknown status"
+
+
+def test_ht_descriptors(cx):
+    lib = cx.load()
+    ht = cx.HT()
+    assert lib.crystal_ht_init(ctypes.byref(ht), cx.HT_LINEAR, 1 << 13, 0, 0, 1) == cx.OK
+    assert ht.capacity == 1 << 14 and ht.log2_capacity == 14
+    assert lib.crystal_ht_bytes(ctypes.byref(ht)) == (1 << 14) * 8          # 128 KiB at 50% fill
+    assert lib.crystal_ht_init(ctypes.byref(ht), cx.HT_LINEAR, 3, 0, 0, 1) == cx.OK
+    assert ht.capacity == 64                                                 # minimum capacity
+    assert lib.crystal_ht_init(ctypes.byref(ht), cx.HT_LINEAR, 5, 0, 0, 1) == cx.OK
+    assert ht.capacity == 64
+    assert lib.crystal_ht_init(ctypes.byref(ht), cx.HT_LINEAR, 33, 0, 0, 1) == cx.OK
+    assert ht.capacity == 128
+    assert lib.crystal_ht_init(ctypes.byref(ht), cx.HT_DIRECT, 0, 10, 2009, 1) == cx.OK
+    assert ht.capacity == 2000 and ht.key_min == 10
+    words = ((2000 + 31) // 32 + 63) // 64 * 64
+    assert lib.crystal_ht_bytes(ctypes.byref(ht)) == words * 4 + 2000 * 4
+    assert lib.crystal_ht_init(ctypes.byref(ht), cx.HT_DIRECT, 0, 10, 2009, 0) == cx.OK
+    assert lib.crystal_ht_bytes(ctypes.byref(ht)) == words * 4
+    assert lib.crystal_ht_init(ctypes.byref(ht), cx.HT_DIRECT, 0, 5, 4, 0) == cx.EINVAL
+    assert lib.crystal_ht_init(ctypes.byref(ht), 7, 10, 0, 0, 0) == cx.EINVAL
+    assert lib.crystal_ht_init(ctypes.byref(ht), cx.HT_LINEAR, -1, 0, 0, 0) == cx.EINVAL
+
+
+def test_host_argument_errors_return_without_launch(cx):
+    lib = cx.load()
+    assert lib.crystal_select(None, -1, cx.Range(0, 1), None, None, None) == cx.EINVAL
+    assert lib.crystal_select(ctypes.c_void_p(16), 10, cx.Range(0, 1), None, ctypes.c_void_p(16), None) == cx.EINVAL
+    assert lib.crystal_select(ctypes.c_void_p(20), 10, cx.Range(0, 1), ctypes.c_void_p(32),
+                              ctypes.c_void_p(16), None) == cx.EINVAL           # misaligned column
+    assert lib.crystal_project(None, None, 5, 1.0, 1.0, None, None) == cx.EINVAL
+    assert lib.crystal_groupby_agg(None, None, 0, 0, ctypes.c_void_p(16), ctypes.c_void_p(16), None) == cx.EINVAL
+    ht = cx.HT()
+    assert lib.crystal_ht_build(ctypes.byref(ht), None, None, None, cx.Range(0, 0), 0,
+                                ctypes.c_void_p(16), None) == cx.EINVAL           # no memory
+    q = cx.StarQueryC()
+    q.n_groups = 0
+    assert lib.crystal_run_star_query(ctypes.byref(q), ctypes.c_void_p(16), ctypes.c_void_p(16), None) == cx.EINVAL
+    q.n_groups, q.n_joins = 1, 5
+    assert lib.crystal_run_star_query(ctypes.byref(q), ctypes.c_void_p(16), ctypes.c_void_p(16), None) == cx.EINVAL
+
+
+def test_tuning_table(cx, tmp_path):
+    cx.tune_reset()
+    sel = cx.tune_variants(cx.K_SELECT)
+    assert (128, 4) in sel and (256, 8) in sel and (64, 1) in sel and len(sel) == 25
+    assert len(cx.tune_variants(cx.K_STAR)) == 15
+    d = cx.tune_get(cx.K_STAR, 120_000_000)
+    cx.tune_set(cx.K_STAR, 512, 8, 2, bucket_lo=20, bucket_hi=30)
+    assert cx.tune_get(cx.K_STAR, 120_000_000) == (512, 8, 2)                # bucket 26
+    assert cx.tune_get(cx.K_STAR, 1000) == d
+    with pytest.raises(cx.CrystalError):
+        cx.tune_set(cx.K_STAR, 512, 3, 0)                                    # not compiled
+    p = tmp_path / "tune.txt"
+    cx.tune_save(p)
+    cx.tune_reset()
+    assert cx.tune_get(cx.K_STAR, 120_000_000) == d
+    cx.tune_load(p)
+    assert cx.tune_get(cx.K_STAR, 120_000_000) == (512, 8, 2)
+    cx.tune_reset()

@@ -1,0 +1,215 @@
+"""GPU parity of the operator calls (select, project, hash build/probe,
+group-by) against the CPU oracle, through the C ABI."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from helpers import announce, project_close
+from paper_2003_01178_amd import crystal as cx
+from paper_2003_01178_amd import datagen
+
+pytestmark = pytest.mark.gpu
+I32_MIN, I32_MAX = cx.I32_MIN, cx.I32_MAX
+SIZES = [0, 1, 63, 64, 255, 4096, 4097, 3 * 4096 + 17, 100_003, 1_000_003]
+SHAPES = [(64, 1), (128, 4), (256, 16), (1024, 16), (512, 2)]
+
+
+@pytest.fixture(autouse=True)
+def _reset_tuning():
+    cx.tune_reset()
+    yield
+    cx.tune_reset()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+# ------------------------------------------------------------------ select --
+@pytest.mark.parametrize("n", SIZES)
+@pytest.mark.parametrize("sigma", [0.0, 0.1, 0.5, 1.0])
+def test_select_matches_oracle(n, sigma):
+    announce("select", n, sigma)
+    y = datagen.select_column(n, workload=1000 + n)
+    lo, hi = datagen.select_threshold_range(sigma)
+    out, cnt = cx.select(dev(y), lo, hi)
+    c = int(cnt.item())
+    want = oracle.select(y, lo, hi)
+    assert c == want.size
+    got = out[:c].cpu().numpy()
+    assert np.array_equal(np.sort(got), np.sort(want))
+
+
+@pytest.mark.parametrize("block,ipt", SHAPES)
+def test_select_tile_shapes(block, ipt):
+    announce("select shape", block, ipt)
+    cx.tune_set(cx.K_SELECT, block, ipt, 0)
+    for gpc in (0, 2):
+        cx.tune_set(cx.K_SELECT, block, ipt, gpc)
+        n = 3 * block * ipt + 5
+        y = datagen.select_column(n, workload=7)
+        lo, hi = 0, 2 ** 30
+        out, cnt = cx.select(dev(y), lo, hi)
+        want = oracle.select(y, lo, hi)
+        c = int(cnt.item())
+        assert c == want.size
+        assert np.array_equal(np.sort(out[:c].cpu().numpy()), np.sort(want))
+
+
+def test_select_tile_example_and_extremes():
+    announce("select extremes")
+    y = np.array([9, 2, 7, 8, 1, 3, 6, 12, 10, 0, 11, 4, 5, 14, 13, 15], dtype=np.int32)
+    out, cnt = cx.select(dev(y), 6, I32_MAX)
+    assert int(cnt.item()) == 10
+    assert sorted(out[:10].cpu().tolist()) == sorted([9, 10, 14, 7, 6, 11, 13, 8, 12, 15])
+    z = np.array([I32_MIN, -1, 0, 1, I32_MAX] * 1000, dtype=np.int32)
+    for lo, hi in [(I32_MIN, I32_MAX), (I32_MIN, I32_MIN), (I32_MAX, I32_MAX), (0, 0), (5, 4)]:
+        out, cnt = cx.select(dev(z), lo, hi)
+        want = oracle.select(z, lo, hi)
+        assert int(cnt.item()) == want.size
+        assert np.array_equal(np.sort(out[:want.size].cpu().numpy()), np.sort(want))
+
+
+def test_select_deterministic_multiset():
+    announce("select repeat")
+    y = datagen.select_column(1 << 20, workload=5)
+    x = dev(y)
+    ref = None
+    for _ in range(3):
+        out, cnt = cx.select(x, I32_MIN, 2 ** 30)
+        s = torch.sort(out[:int(cnt.item())])[0].cpu().numpy()
+        ref = s if ref is None else ref
+        assert np.array_equal(s, ref)
+
+
+# ----------------------------------------------------------------- project --
+@pytest.mark.parametrize("n", SIZES)
+@pytest.mark.parametrize("sigmoid", [False, True])
+def test_project_matches_oracle(n, sigmoid):
+    announce("project", n, sigmoid)
+    x1, x2 = datagen.project_columns(n, workload=300 + n)
+    got = cx.project(dev(x1), dev(x2), 2.0, 3.0, sigmoid=sigmoid).cpu().numpy()
+    if sigmoid:
+        want = oracle.project_sigmoid(x1, x2, 2.0, 3.0)
+        assert np.all(np.abs(got.astype(np.float64) - want) <= 1e-6 * np.abs(want))
+    else:
+        want = oracle.project(x1, x2, 2.0, 3.0)
+        assert project_close(got, want, x1, x2, 2.0, 3.0)
+
+
+def test_project_exact_grid_and_signs():
+    announce("project exact")
+    rng = np.random.default_rng(1)
+    i1, i2 = rng.integers(0, 2 ** 20, 100_000), rng.integers(0, 2 ** 20, 100_000)
+    x1, x2 = (i1 / 2 ** 20).astype(np.float32), (i2 / 2 ** 20).astype(np.float32)
+    got = cx.project(dev(x1), dev(x2), 2.0, 3.0).cpu().numpy()
+    assert np.array_equal(got, oracle.project(x1, x2, 2.0, 3.0))      # exact in fp32
+    for a, b in [(-1.5, 0.25), (3.0, -2.0), (0.0, 0.0)]:
+        got = cx.project(dev(x1), dev(x2), a, b).cpu().numpy()
+        assert project_close(got, oracle.project(x1, x2, a, b), x1, x2, a, b)
+
+
+@pytest.mark.parametrize("block,ipt", [(64, 4), (128, 8), (1024, 16)])
+def test_project_tile_shapes(block, ipt):
+    announce("project shape", block, ipt)
+    cx.tune_set(cx.K_PROJECT, block, ipt, 1)
+    x1, x2 = datagen.project_columns(5 * block * ipt + 3, workload=4)
+    got = cx.project(dev(x1), dev(x2), 2.0, 3.0).cpu().numpy()
+    assert project_close(got, oracle.project(x1, x2, 2.0, 3.0), x1, x2, 2.0, 3.0)
+
+
+# -------------------------------------------------------------- hash join --
+@pytest.mark.parametrize("d", [1, 100, 1 << 13, 1 << 16, 1 << 20])
+@pytest.mark.parametrize("kind", [cx.HT_LINEAR, cx.HT_DIRECT])
+def test_join_matches_oracle(d, kind):
+    announce("join", d, kind)
+    t = datagen.join_tables(d, n_probe=1_000_003, workload=2000 + d)
+    ht = cx.HashTable(kind, d, 0, d - 1)
+    st = ht.build(dev(t.dim_key), payload=dev(t.dim_val))
+    res = ht.probe(dev(t.fk)).cpu().tolist()
+    cx.check_status(st)
+    assert tuple(res) == oracle.join_sum(t.dim_key, t.dim_val, t.fk)
+    assert res[1] == t.fk.size                                    # every probe key exists
+    # Q4 form with a probe-side payload
+    pv = np.arange(t.fk.size, dtype=np.int32) - 500_000
+    res = ht.probe(dev(t.fk), dev(pv)).cpu().tolist()
+    assert tuple(res) == oracle.join_sum(t.dim_key, t.dim_val, t.fk, pval=pv)
+
+
+@pytest.mark.parametrize("kind", [cx.HT_LINEAR, cx.HT_DIRECT])
+def test_join_filtered_build_misses_and_keys_only(kind):
+    announce("join filtered", kind)
+    rng = np.random.default_rng(4)
+    d = 50_000
+    key = (rng.permutation(d) * 3 - 70_000).astype(np.int32)      # sparse, negative keys
+    val = rng.integers(I32_MIN, I32_MAX, size=d, dtype=np.int32, endpoint=True)
+    filt = rng.integers(0, 25, size=d, dtype=np.int32)
+    fk = rng.integers(-80_000, 90_000, size=333_333, dtype=np.int32)   # many misses
+    ht = cx.HashTable(kind, d, int(key.min()), int(key.max()))
+    st = ht.build(dev(key), dev(val), filter_col=dev(filt), filter=(3, 9))
+    res = ht.probe(dev(fk)).cpu().tolist()
+    cx.check_status(st)
+    assert tuple(res) == oracle.join_sum(key, val, fk, bfilter=filt, flo=3, fhi=9)
+    ko = cx.HashTable(kind, d, int(key.min()), int(key.max()), has_payload=False)
+    st = ko.build(dev(key))
+    res = ko.probe(dev(fk)).cpu().tolist()
+    cx.check_status(st)
+    assert tuple(res) == oracle.join_sum(key, None, fk)
+
+
+def test_join_empty_inputs():
+    announce("join empty")
+    ht = cx.HashTable(cx.HT_LINEAR, 10)
+    st = ht.build(dev(np.zeros(0, np.int32)), dev(np.zeros(0, np.int32)))
+    assert ht.probe(dev(np.arange(100, dtype=np.int32))).cpu().tolist() == [0, 0]
+    assert ht.probe(dev(np.zeros(0, np.int32))).cpu().tolist() == [0, 0]
+    cx.check_status(st)
+
+
+def test_join_device_errors():
+    announce("join errors")
+    ht = cx.HashTable(cx.HT_LINEAR, 8)
+    st = ht.build(dev(np.array([1, 2, 3, 2], np.int32)), dev(np.arange(4, dtype=np.int32)))
+    assert int(st.item()) == cx.EDUPKEY
+    st = ht.build(dev(np.array([1, I32_MIN], np.int32)), dev(np.arange(2, dtype=np.int32)))
+    assert int(st.item()) == cx.EINVAL
+    full = cx.HashTable(cx.HT_LINEAR, 8)                           # 64 slots
+    st = full.build(dev(np.arange(65, dtype=np.int32)), dev(np.arange(65, dtype=np.int32)))
+    assert int(st.item()) == cx.EFULL
+    dt = cx.HashTable(cx.HT_DIRECT, 0, 0, 99)
+    st = dt.build(dev(np.array([5, 100], np.int32)), dev(np.arange(2, dtype=np.int32)))
+    assert int(st.item()) == cx.ERANGE
+    st = dt.build(dev(np.array([5, 6, 5], np.int32)), dev(np.arange(3, dtype=np.int32)))
+    assert int(st.item()) == cx.EDUPKEY
+
+
+# ---------------------------------------------------------------- group-by --
+@pytest.mark.parametrize("groups", [1, 7, 7000, 100_000])
+@pytest.mark.parametrize("n", [0, 1, 4097, 2_000_003])
+def test_groupby_matches_oracle(groups, n):
+    announce("groupby", groups, n)
+    rng = np.random.default_rng(groups + n)
+    g = rng.integers(0, groups, size=n, dtype=np.int32)
+    v = rng.integers(I32_MIN, I32_MAX, size=n, dtype=np.int32, endpoint=True)
+    sums, st = cx.groupby_agg(dev(g), dev(v), groups)
+    got = sums.cpu().numpy()
+    cx.check_status(st)
+    assert np.array_equal(got, oracle.groupby(g, v, groups))
+
+
+def test_groupby_lds_path_and_range_error():
+    announce("groupby lds")
+    n, groups = 40_000_000, 64                    # enough rows per group for LDS partials
+    g = (np.arange(n) % groups).astype(np.int32)
+    v = np.arange(n, dtype=np.int32)
+    sums, st = cx.groupby_agg(dev(g), dev(v), groups)
+    cx.check_status(st)
+    assert np.array_equal(sums.cpu().numpy(), oracle.groupby(g, v, groups))
+    g[123] = groups
+    sums, st = cx.groupby_agg(dev(g), dev(v), groups)
+    assert int(st.item()) == cx.ERANGE
+    g[123] = 0
+    want = oracle.groupby(g, v, groups)
+    want[0] -= 123                                 # the skipped row (v = 123, group 0 in g)
+    assert np.array_equal(sums.cpu().numpy(), want)

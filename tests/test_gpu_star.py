@@ -1,0 +1,189 @@
+"""GPU parity of the fused star-query kernel (SSB Q1.1 shape and the
+four-join group-by shape of the section 5.3 case study) against the oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from helpers import STAR_GROUPS, announce, q11_oracle, star_oracle, star_oracle_joins
+from paper_2003_01178_amd import crystal as cx
+from paper_2003_01178_amd import datagen, queries
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _reset_tuning():
+    cx.tune_reset()
+    yield
+    cx.tune_reset()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def q11_dev(f):
+    return [dev(f.datekey), dev(f.discount), dev(f.quantity), dev(f.price)]
+
+
+# ----------------------------------------------------------------- Q1.1 ----
+@pytest.mark.parametrize("n", [0, 1, 4095, 4097, 100_003, 1_000_000])
+def test_q11_matches_oracle(n):
+    announce("q11", n)
+    f = datagen.q11_fact(n, workload=500 + n)
+    out, st = queries.Q11Plan(*q11_dev(f)).run()
+    cx.check_status(st)
+    assert int(out.item()) == q11_oracle(f)
+
+
+def test_q11_random_constants_and_shapes():
+    f = datagen.q11_fact(777_777, workload=41)
+    cols = q11_dev(f)
+    rng = np.random.default_rng(2)
+    for trial, (block, ipt, gpc) in enumerate([(64, 4, 0), (128, 8, 0), (256, 16, 2), (512, 8, 1),
+                                               (1024, 4, 0), (256, 4, 4)]):
+        announce("q11 shape", block, ipt, gpc)
+        cx.tune_set(cx.K_STAR, block, ipt, gpc)
+        year, d, q = datagen.random_q11_constants(rng)
+        out, st = queries.Q11Plan(*cols, year=year, disc=(d, d + 2), qty_max=q).run()
+        cx.check_status(st)
+        assert int(out.item()) == q11_oracle(f, year, (d, d + 2), q), (trial, year, d, q)
+
+
+# ------------------------------------------------------------ four joins ---
+@pytest.fixture(scope="module")
+def star_small():
+    t = datagen.star_tables(n=1_000_003, workload=3)
+    return t, queries.StarSchema(t)
+
+
+@pytest.mark.parametrize("order", [(1, 0, 2, 3), (0, 1, 2, 3), (3, 2, 1, 0), (2, 0, 3, 1)])
+def test_star_matches_oracle(star_small, order):
+    announce("star", order)
+    t, s = star_small
+    want, surv = star_oracle(t)
+    assert surv > 0
+    s.status.zero_()
+    s.build()
+    out, st = s.plan(order).run()
+    cx.check_status(st)
+    cx.check_status(s.status)
+    assert np.array_equal(out.cpu().numpy(), want)
+
+
+def test_star_random_constants(star_small):
+    t, s = star_small
+    rng = np.random.default_rng(8)
+    plan = s.plan()
+    for trial in range(5):
+        consts = datagen.random_star_constants(rng)
+        announce("star consts", consts)
+        s.status.zero_()
+        s.build(consts)
+        out, st = plan.run()
+        cx.check_status(st)
+        cx.check_status(s.status)
+        want, _ = star_oracle(t, consts)
+        assert np.array_equal(out.cpu().numpy(), want), (trial, consts)
+
+
+@pytest.mark.parametrize("block,ipt,gpc", [(64, 4, 0), (128, 16, 0), (256, 8, 3), (1024, 16, 1)])
+def test_star_tile_shapes(star_small, block, ipt, gpc):
+    announce("star shape", block, ipt, gpc)
+    t, s = star_small
+    cx.tune_set(cx.K_STAR, block, ipt, gpc)
+    s.status.zero_()
+    s.build()
+    out, st = s.plan().run()
+    cx.check_status(st)
+    assert np.array_equal(out.cpu().numpy(), star_oracle(t)[0])
+
+
+def test_star_ragged_sizes():
+    for n in [0, 1, 255, 4097, 3 * 4096 + 5]:
+        announce("star ragged", n)
+        t = datagen.star_tables(n=n, workload=60 + n)
+        s = queries.StarSchema(t)
+        s.build()
+        out, st = s.plan().run()
+        cx.check_status(st)
+        assert np.array_equal(out.cpu().numpy(), star_oracle(t)[0])
+
+
+def _pack(filter_attr, group_attr, gshift):
+    return (filter_attr.astype(np.int64) | (group_attr.astype(np.int64) << gshift)).astype(np.int32)
+
+
+@pytest.mark.parametrize("kind", [cx.HT_DIRECT, cx.HT_LINEAR])
+def test_star_probe_time_filters_on_packed_payloads(star_small, kind):
+    """Unfiltered tables whose payload packs (filter, group); the dimension
+    predicates and the group fields are read from the payload at probe time."""
+    announce("star packed", kind)
+    t, s = star_small
+    tables = []
+    for j, d in enumerate(t.dims):
+        grp = (d.year - 1992) if j == 0 else d.group
+        ht = cx.HashTable(kind, d.n, int(d.key.min()), int(d.key.max()), has_payload=True)
+        st = ht.build(dev(d.key), dev(_pack(d.filter, grp, 5)))
+        cx.check_status(st)
+        tables.append(ht)
+    rng = np.random.default_rng(12)
+    for trial in range(3):
+        consts = datagen.random_star_constants(rng)
+        joins = []
+        for j in (1, 0, 2, 3):
+            jj = dict(table=tables[j], fk_col=j, filter=(5, 0, consts[j], consts[j]))
+            if j == 0:
+                jj["group"] = (3, 5, 0, 1000)
+            if j == 2:
+                jj["group"] = (10, 5, 0, 1)
+            joins.append(jj)
+        q = cx.StarQuery(s.fact_cols, n_groups=STAR_GROUPS, joins=joins, agg=cx.AGG_SUM, agg_cols=(4, 0))
+        out, st = q.run()
+        cx.check_status(st)
+        want, _ = star_oracle(t, consts)
+        assert np.array_equal(out.cpu().numpy(), want), (trial, consts)
+
+
+@pytest.mark.parametrize("agg", [cx.AGG_SUM, cx.AGG_SUM_PRODUCT, cx.AGG_SUM_DIFF, cx.AGG_COUNT])
+def test_star_aggregates_and_fact_predicates(star_small, agg):
+    announce("star agg", agg)
+    t, s = star_small
+    s.status.zero_()
+    s.build()
+    joins_dev = []
+    for j in (0, 2):                        # two joins plus two fact predicates
+        jj = dict(table=s.tables[j], fk_col=j)
+        jj["group"] = (32, 0, 1992, 1000) if j == 0 else (32, 0, 0, 1)
+        joins_dev.append(jj)
+    preds = [(4, 100_000, 600_000), (5, 1, 900_000)]
+    q = cx.StarQuery(s.fact_cols, n_groups=STAR_GROUPS, preds=preds, joins=joins_dev, agg=agg,
+                     agg_cols=(4, 5))
+    out, st = q.run()
+    cx.check_status(st)
+    oj = [jj for jj in star_oracle_joins(t, t.consts) if jj["fk_col"] in (0, 2)]
+    want = oracle.star([*t.fk, t.m1, t.m2], STAR_GROUPS, preds=preds, joins=oj, agg=agg, agg_cols=(4, 5))
+    assert np.array_equal(out.cpu().numpy(), want)
+    # scalar form (one group, no group fields): BlockAggregate path
+    qs = cx.StarQuery(s.fact_cols, n_groups=1, preds=preds,
+                      joins=[dict(table=s.tables[j], fk_col=j) for j in (0, 2)], agg=agg, agg_cols=(4, 5))
+    out, st = qs.run()
+    cx.check_status(st)
+    oj1 = [dict(jj, group=None) for jj in oj]
+    want1 = oracle.star([*t.fk, t.m1, t.m2], 1, preds=preds, joins=oj1, agg=agg, agg_cols=(4, 5))
+    assert int(out.item()) == int(want1[0])
+
+
+def test_star_group_out_of_range_sets_status(star_small):
+    announce("star erange")
+    t, s = star_small
+    s.status.zero_()
+    s.build()
+    joins = [dict(table=s.tables[1], fk_col=1), dict(table=s.tables[2], fk_col=2, group=(32, 0, 0, 1))]
+    q = cx.StarQuery(s.fact_cols, n_groups=500, joins=joins, agg=cx.AGG_COUNT)   # groups go to 999
+    out, st = q.run()
+    assert int(st.item()) == cx.ERANGE
+    oj = [jj for jj in star_oracle_joins(t, t.consts) if jj["fk_col"] in (1, 2)]
+    full = oracle.star([*t.fk, t.m1, t.m2], 1000, joins=oj, agg=oracle.AGG_COUNT)
+    assert np.array_equal(out.cpu().numpy(), full[:500])                        # rows in range kept
