@@ -33,7 +33,7 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=5)
-    p.add_argument("--workload", default="star", choices=["star", "q11", "select", "project", "join"])
+    p.add_argument("--workload", default="star", choices=["star", "q11", "select", "project", "join", "copy"])
     p.add_argument("--rows", type=int, default=0, help="override the fact/column length")
     p.add_argument("--sigma", type=float, default=0.5, help="select selectivity")
     p.add_argument("--dim", type=int, default=1 << 20, help="join build size D")
@@ -123,7 +123,7 @@ def main():
         sys.exit(3)
     cx.load()
     kernel_id = {"star": cx.K_STAR, "q11": cx.K_STAR, "select": cx.K_SELECT,
-                 "project": cx.K_PROJECT, "join": cx.K_HT_PROBE}[args.workload]
+                 "project": cx.K_PROJECT, "join": cx.K_HT_PROBE, "copy": cx.K_SELECT}[args.workload]
     if args.tune:
         b, i, g = (int(x) for x in args.tune.split(","))
         cx.tune_set(kernel_id, b, i, g)
@@ -315,6 +315,28 @@ def main():
                               "probes": n, "table_bytes": ht.nbytes, "tile": list(cx.tune_get(cx.K_HT_PROBE, n))})
         roof.update(kernel="crystal::ht_probe_kernel", achieved=b / (kern_ms * 1e-3) / 1e9, algorithmic_bytes=b,
                     kernel_ms=kern_ms)
+
+    elif args.workload == "copy":
+        # calibration: a plain device-to-device copy of known size (read n*4, write n*4 bytes)
+        n = args.rows or (1 << 28)
+        src = torch.arange(n, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(W):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        timer = Timer(torch)
+        t0 = time.perf_counter()
+        for _ in range(K):
+            timer.run(lambda: dst.copy_(src))
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        kern_ms = timer.mean_ms()
+        b = 8 * n
+        result.update(metric="bytes/s (plain copy, calibration)", value=b * K / elapsed, unit="B/s",
+                      ms_per_step=elapsed / K * 1e3, dtype="int32",
+                      config={"workload": f"device copy of {n} int32 ({4 * n} bytes read, {4 * n} written)",
+                              "rows": n})
+        roof.update(kernel="copy", achieved=b / (kern_ms * 1e-3) / 1e9, algorithmic_bytes=b, kernel_ms=kern_ms)
 
     roof["frac"] = roof["achieved"] / roof["peak"]
     result["roofline"] = roof

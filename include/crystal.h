@@ -165,12 +165,15 @@ crystal_status crystal_groupby_agg(const int32_t *group, const int32_t *value, i
 /*   SELECT agg FROM fact, dim_1..dim_J                                      */
 /*   WHERE fact predicates AND fact.fk_j = dim_j.key AND dimension filters  */
 /*   GROUP BY dense index                                                    */
-/* One kernel.  Per tile: BlockLoad of the first column, then, in plan      */
-/* order, each fact predicate and each join reads its column with           */
-/* BlockLoadSel (only items still alive), probes (BlockProbeHT) and clears  */
-/* the items that fail; the survivors' group index and measure are formed   */
-/* and added (BlockAggregate for a single group, global 64-bit atomics per  */
-/* survivor otherwise).                                                      */
+/* One persistent kernel.  Per tile: BlockLoad of the first step's column,  */
+/* then BlockLoadSel (only items still alive) of the second step's column,  */
+/* each step probing (BlockProbeHT) or testing its predicate and clearing   */
+/* the items that fail; rows still alive are compacted into an LDS queue    */
+/* (BlockScan + BlockShuffle) and finished in batches: remaining steps, the */
+/* group index and the measure, added with 64-bit atomics per survivor      */
+/* (grouped) or reduced per workgroup (BlockAggregate) and summed by a      */
+/* finalize kernel (single group).  Steps run in plan order: predicates,    */
+/* then joins.                                                               */
 /*                                                                          */
 /* Payload fields: a join may read two fields from the 32-bit payload of    */
 /* the matched entry, field = (uint32(payload) >> shift) & (2^bits - 1), or */
@@ -223,10 +226,18 @@ typedef struct crystal_star_query {
     crystal_join joins[CRYSTAL_MAX_JOINS]; /* evaluated after the predicates */
 } crystal_star_query;
 
-/* Run one query.  out: device, n_groups int64, overwritten.  The plan needs
- * at least one predicate or join (the first one's column is read in full). */
+/* Device scratch bytes a call needs: per-workgroup partial sums when the
+ * result is a single group (0 for grouped plans or an invalid plan). */
+size_t crystal_star_query_scratch_bytes(const crystal_star_query *q);
+
+/* Run one query.  out: device, n_groups int64, overwritten.  scratch: device
+ * memory of at least crystal_star_query_scratch_bytes(q) bytes, 16-byte
+ * aligned, owned by the caller (may be NULL when that size is 0); too small
+ * a buffer returns CRYSTAL_ESCRATCH.  Calls that share a scratch buffer must
+ * be ordered on one stream.  A plan with no step aggregates every row. */
 crystal_status crystal_run_star_query(const crystal_star_query *q, int64_t *out,
-                                      int32_t *status, void *stream);
+                                      int32_t *status, void *scratch, size_t scratch_bytes,
+                                      void *stream);
 
 /* ------------------------------------------------------------------------ */
 /* Tile-size tuning (section 3.3: the tile is BLOCK threads x IPT items per */

@@ -1,0 +1,186 @@
+"""Tile-shape autotuner (section 3.3: the tile is BLOCK threads x IPT items).
+
+For each kernel, every compiled (BLOCK, IPT) variant is timed at several
+workgroups-per-CU settings on the workload it serves, with HIP events on the
+launch stream; variants whose result differs from the first variant's are
+discarded.  The winner for each workload size is written into the library's
+tuning table for the size buckets nearest to that size, and the table is
+saved as a text cache (``tune/gfx950.txt``) that ``crystal.load()`` reads.
+
+Usage: ``python -m paper_2003_01178_amd.autotune [--kernels star,select,...]
+[--out PATH] [--quick]``.  Prints a JSON report.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+from . import crystal as cx
+from . import datagen, queries
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_OUT = os.path.join(HERE, "tune", "gfx950.txt")
+GPCS = (0, 1, 2, 4, 8)
+
+
+def time_ms(fn, reps=10, warmup=2):
+    for _ in range(warmup):
+        fn()
+    ev = []
+    for _ in range(reps):
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        fn()
+        e.record()
+        ev.append((s, e))
+    torch.cuda.synchronize()
+    return float(np.median([s.elapsed_time(e) for s, e in ev]))
+
+
+def bucket(n):
+    return max(0, int(n).bit_length() - 1)
+
+
+def sweep(kernel, n, call, result_of, candidates=None, gpcs=GPCS, reps=10, log=None):
+    """Time every (block, ipt, grid_per_cu); return sorted [(ms, b, i, g)]."""
+    b0 = bucket(n)
+    rows, ref = [], None
+    for b, i in candidates or cx.tune_variants(kernel):
+        for g in gpcs:
+            cx.tune_set(kernel, b, i, g, bucket_lo=b0, bucket_hi=b0)
+            call()
+            torch.cuda.synchronize()
+            r = result_of()
+            if ref is None:
+                ref = r
+            elif not np.array_equal(r, ref):
+                if log:
+                    log(f"  discard {b}x{i} g{g}: result differs")
+                continue
+            ms = time_ms(call, reps=reps)
+            rows.append((ms, b, i, g))
+            if log:
+                log(f"  {kernel} n={n} {b}x{i} g{g}: {ms * 1e3:.1f} us")
+    rows.sort()
+    return rows
+
+
+def assign(kernel, results):
+    """results: [(n, (b, i, g))]; cover all buckets, splitting between sizes."""
+    results = sorted(results)
+    bks = [bucket(n) for n, _ in results]
+    for k, (n, (b, i, g)) in enumerate(results):
+        lo = 0 if k == 0 else (bks[k - 1] + bks[k]) // 2 + 1
+        hi = 63 if k == len(results) - 1 else (bks[k] + bks[k + 1]) // 2
+        cx.tune_set(kernel, b, i, g, bucket_lo=lo, bucket_hi=hi)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--kernels", default="star,q11,select,project,probe,groupby")
+    ap.add_argument("--out", default=DEFAULT_OUT)
+    ap.add_argument("--quick", action="store_true", help="fewer candidates and sizes")
+    ap.add_argument("--reps", type=int, default=10)
+    args = ap.parse_args(argv)
+    log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
+    cx.load()
+    cx.tune_reset()
+    report = {}
+    kernels = args.kernels.split(",")
+    quick_vec = [(128, 8), (256, 8), (256, 16), (512, 8), (1024, 8), (256, 4)]
+    star_results = []
+
+    if "star" in kernels:
+        n = 120_000_000
+        t = datagen.star_tables(n=n, workload=3)
+        s = queries.StarSchema(t)
+        s.build()
+        plan = s.plan()
+        out = torch.empty(queries.STAR_GROUPS, dtype=torch.int64, device="cuda")
+        st = cx.new_status()
+        rows = sweep(cx.K_STAR, n, lambda: plan.run(out=out, status=st), lambda: out.cpu().numpy(),
+                     candidates=quick_vec if args.quick else None, reps=args.reps, log=log)
+        star_results.append((n, rows[0][1:]))
+        report["star_120M"] = rows[:8]
+        del s, t
+        torch.cuda.empty_cache()
+    if "q11" in kernels:
+        n = 6_000_000
+        f = datagen.q11_fact(n)
+        plan = queries.Q11Plan(*[queries.to_dev(c) for c in (f.datekey, f.discount, f.quantity, f.price)])
+        out = torch.empty(1, dtype=torch.int64, device="cuda")
+        st = cx.new_status()
+        rows = sweep(cx.K_STAR, n, lambda: plan.run(out=out, status=st), lambda: out.cpu().numpy(),
+                     candidates=quick_vec if args.quick else None, reps=args.reps, log=log)
+        star_results.append((n, rows[0][1:]))
+        report["q11_6M"] = rows[:8]
+    if star_results:
+        assign(cx.K_STAR, star_results)
+
+    if "select" in kernels:
+        n = 1 << 29
+        x = queries.to_dev(datagen.select_column(n))
+        lo, hi = datagen.select_threshold_range(0.5)
+        o = torch.empty(n, dtype=torch.int32, device="cuda")
+        c = torch.empty(1, dtype=torch.int64, device="cuda")
+        cands = [(128, 4), (256, 4), (256, 8), (256, 16), (512, 8), (512, 16), (1024, 8)] if args.quick else None
+        rows = sweep(cx.K_SELECT, n, lambda: cx.select(x, lo, hi, out=o, count=c), lambda: c.cpu().numpy(),
+                     candidates=cands, gpcs=(0, 2, 4), reps=args.reps, log=log)
+        assign(cx.K_SELECT, [(n, rows[0][1:])])
+        report["select_2^29"] = rows[:8]
+        del x, o
+        torch.cuda.empty_cache()
+    if "project" in kernels:
+        n = 1 << 29
+        x1h, x2h = datagen.project_columns(n)
+        x1, x2 = queries.to_dev(x1h), queries.to_dev(x2h)
+        o = torch.empty(n, dtype=torch.float32, device="cuda")
+        rows = sweep(cx.K_PROJECT, n, lambda: cx.project(x1, x2, 2.0, 3.0, out=o),
+                     lambda: o[:: 1 << 16].cpu().numpy(), candidates=quick_vec if args.quick else None,
+                     gpcs=(0, 2, 4), reps=args.reps, log=log)
+        assign(cx.K_PROJECT, [(n, rows[0][1:])])
+        report["project_2^29"] = rows[:8]
+        del x1, x2, o
+        torch.cuda.empty_cache()
+    if "probe" in kernels:
+        n = 1 << 28
+        jt = datagen.join_tables(1 << 20, n_probe=n)
+        ht = cx.HashTable(cx.HT_LINEAR, 1 << 20)
+        ht.build(queries.to_dev(jt.dim_key), queries.to_dev(jt.dim_val))
+        fk = queries.to_dev(jt.fk)
+        res = torch.empty(2, dtype=torch.int64, device="cuda")
+        rows = sweep(cx.K_HT_PROBE, n, lambda: ht.probe(fk, out=res), lambda: res.cpu().numpy(),
+                     candidates=quick_vec if args.quick else None, gpcs=(1, 2, 4, 8), reps=args.reps, log=log)
+        assign(cx.K_HT_PROBE, [(n, rows[0][1:])])
+        report["probe_D2^20"] = rows[:8]
+        del fk
+        torch.cuda.empty_cache()
+    if "groupby" in kernels:
+        n = 1 << 26
+        rng = np.random.default_rng(0)
+        g = queries.to_dev(rng.integers(0, 7000, size=n, dtype=np.int32))
+        v = queries.to_dev(rng.integers(0, 1000, size=n, dtype=np.int32))
+        o = torch.empty(7000, dtype=torch.int64, device="cuda")
+        st = cx.new_status()
+        rows = sweep(cx.K_GROUPBY, n, lambda: cx.groupby_agg(g, v, 7000, out=o, status=st),
+                     lambda: o.cpu().numpy(), candidates=quick_vec if args.quick else None,
+                     gpcs=(1, 2, 4), reps=args.reps, log=log)
+        assign(cx.K_GROUPBY, [(n, rows[0][1:])])
+        report["groupby_2^26_7000"] = rows[:8]
+
+    os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
+    cx.tune_save(args.out)
+    report["saved"] = args.out
+    report["device"] = torch.cuda.get_device_name(0)
+    report["when"] = time.strftime("%Y-%m-%d %H:%M:%S")
+    print(json.dumps(report))
+
+
+if __name__ == "__main__":
+    main()

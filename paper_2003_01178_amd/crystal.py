@@ -13,7 +13,8 @@ import os
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libcrystal.so")
+# CRYSTAL_LIB selects another build of the same library (e.g. a tuning experiment)
+LIB_PATH = os.environ.get("CRYSTAL_LIB", os.path.join(_HERE, "libcrystal.so"))
 
 OK, EINVAL, ESCRATCH, EFULL, EDUPKEY, EHIP, EBUSY, ERANGE = range(8)
 HT_LINEAR, HT_DIRECT = 0, 1
@@ -73,7 +74,8 @@ def _declare(lib):
         "crystal_ht_build": (c_i32, [P(HT), c_vp, c_vp, c_vp, Range, c_i64, c_vp, c_vp]),
         "crystal_ht_probe": (c_i32, [P(HT), c_vp, c_vp, c_i64, c_vp, c_vp, c_vp]),
         "crystal_groupby_agg": (c_i32, [c_vp, c_vp, c_i64, c_i64, c_vp, c_vp, c_vp]),
-        "crystal_run_star_query": (c_i32, [P(StarQueryC), c_vp, c_vp, c_vp]),
+        "crystal_star_query_scratch_bytes": (ctypes.c_size_t, [P(StarQueryC)]),
+        "crystal_run_star_query": (c_i32, [P(StarQueryC), c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp]),
         "crystal_tune_variants": (c_i32, [c_i32, P(c_i32), P(c_i32), c_i32]),
         "crystal_tune_set": (c_i32, [c_i32, c_i32, c_i32, c_i32, c_i32, c_i32]),
         "crystal_tune_get": (c_i32, [c_i32, c_i64, P(c_i32), P(c_i32), P(c_i32)]),
@@ -274,14 +276,18 @@ class StarQuery:
         self.c = q
         self.n_groups = int(n_groups)
         self.n_rows = n
+        dev = cols[0].device if cols else "cuda"
+        nbytes = load().crystal_star_query_scratch_bytes(ctypes.byref(q))
+        self.scratch = torch.empty(max(16, nbytes), dtype=torch.uint8, device=dev) if nbytes else None
+        self.scratch_bytes = nbytes
 
     def run(self, out=None, status=None, stream=None):
         lib = load()
         dev = self.cols[0].device if self.cols else "cuda"
         out = torch.empty(self.n_groups, dtype=torch.int64, device=dev) if out is None else out
         status = new_status(dev) if status is None else status
-        _check(lib.crystal_run_star_query(ctypes.byref(self.c), _ptr(out), _ptr(status), _stream(stream)),
-               "crystal_run_star_query")
+        _check(lib.crystal_run_star_query(ctypes.byref(self.c), _ptr(out), _ptr(status), _ptr(self.scratch),
+                                          self.scratch_bytes, _stream(stream)), "crystal_run_star_query")
         return out, status
 
 

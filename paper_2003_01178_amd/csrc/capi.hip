@@ -35,6 +35,19 @@ int device_cu_count() {
     return g_cu[d];
 }
 
+int64_t device_lds_per_cu() {
+    static int64_t cache[64];
+    const int d = cur_device();
+    if (!cache[d]) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, d) != hipSuccess ||
+            v <= 0)
+            v = 65536;
+        cache[d] = v;
+    }
+    return cache[d];
+}
+
 int64_t device_lds_per_block() {
     const int d = cur_device();
     if (!g_lds[d]) {
@@ -307,14 +320,25 @@ crystal_status crystal_groupby_agg(const int32_t *group, const int32_t *value, i
                                    (uint64_t *)sums, status, as_stream(stream)));
 }
 
+size_t crystal_star_query_scratch_bytes(const crystal_star_query *q) {
+    if (!q) return 0;
+    StarPlanDev d;
+    if (star_plan_to_dev(*q, d) != CRYSTAL_OK || !d.scalar) return 0;
+    return (size_t)star_max_grid(q->n_rows) * 8;
+}
+
 crystal_status crystal_run_star_query(const crystal_star_query *q, int64_t *out, int32_t *status,
-                                      void *stream) {
+                                      void *scratch, size_t scratch_bytes, void *stream) {
     if (!q || !out || !status) return CRYSTAL_EINVAL;
     StarPlanDev d;
     crystal_status st = star_plan_to_dev(*q, d);
     if (st != CRYSTAL_OK) return st;
+    if (d.scalar) {
+        if (!scratch || !aligned16(scratch)) return scratch ? CRYSTAL_EINVAL : CRYSTAL_ESCRATCH;
+        if (scratch_bytes < (size_t)star_max_grid(q->n_rows) * 8) return CRYSTAL_ESCRATCH;
+    }
     return from_hip(launch_star(tune_lookup(CRYSTAL_K_STAR, q->n_rows), d, (uint64_t *)out, status,
-                                as_stream(stream)));
+                                (uint64_t *)scratch, as_stream(stream)));
 }
 
 // ----------------------------------------------------------------- tuning --

@@ -18,6 +18,8 @@ struct LaunchCfg {
 int device_cu_count();
 // Largest dynamic LDS a workgroup may allocate on the current device.
 int64_t device_lds_per_block();
+// LDS of one compute unit of the current device.
+int64_t device_lds_per_cu();
 
 // Workgroups to launch for n_tiles tiles under cfg.
 inline int64_t grid_for(int64_t n_tiles, const LaunchCfg &cfg) {
@@ -94,11 +96,21 @@ struct StarPlanDev {
     int32_t pred_hi[CRYSTAL_MAX_PREDS];
     int32_t agg, agg_col0, agg_col1;
     int32_t scalar;  // single group and no group fields: BlockAggregate path
+    // set by the launcher: LDS word offsets of the staged bitmaps of the two
+    // dense steps (-1: not staged) and of the survivor queue
+    int32_t stage_off[2];
+    int32_t queue_off;
+    int32_t queue_cap;
     StarJoinDev joins[CRYSTAL_MAX_JOINS];
 };
 
+// Persistent star-kernel workgroups per CU never exceed this.
+constexpr int kStarMaxGridPerCu = 32;
+// Largest grid the star kernel launches for n rows (sizes the scalar partials).
+int64_t star_max_grid(int64_t n_rows);
+
 crystal_status star_plan_to_dev(const crystal_star_query &q, StarPlanDev &d);
 hipError_t launch_star(const LaunchCfg &cfg, const StarPlanDev &plan, uint64_t *out,
-                       int32_t *status, hipStream_t s);
+                       int32_t *status, uint64_t *partials, hipStream_t s);
 
 }  // namespace crystal

@@ -1,158 +1,354 @@
 // Fused star-query kernel: the pipelined multi-join probe of the section 5.3
 // case study, and the fact-side selection of SSB Q1.1 (section 3.1), in one
-// launch with nothing materialised between operators.
+// launch with nothing materialised in device memory between operators.
+//
+// Workgroups are persistent and stride over tiles of BLOCK x IPT rows.
+//
+// Dense phase (the first one or two steps of the plan): the first step's
+// column is read in full (BlockLoad), the second step's column only at the
+// 128-bit vectors that still hold a live row (BlockLoadSel), so the bytes
+// fetched per column fall with the selectivity before it (the r1 term of the
+// section 5.3 model).  The two steps are software-pipelined across tiles:
+// while tile k is finished, the second-step loads of tile k+1 and the
+// first-step loads of tile k+2 are in flight.  Presence-only direct joins of
+// the dense phase probe a copy of their bitmap staged in LDS.
+//
+// Sparse phase: rows alive after the dense phase are compacted into an LDS
+// queue per wave (an exclusive scan of the per-lane counts with ballots, then
+// each lane writes its rows at its offset: the BlockScan and BlockShuffle of
+// section 3.2 at wave granularity, so no workgroup barrier is needed) and
+// finished in batches of 64 rows, one row per lane, so the remaining steps'
+// loads of a whole batch are in flight together instead of one dependent
+// round trip per tile.
+//
+// Aggregation: grouped results are added with 64-bit atomics per surviving
+// row (survivors are sparse); a scalar result is reduced per workgroup
+// (BlockAggregate) into a partial in scratch memory and summed by a one-
+// workgroup finalize kernel, which avoids same-address atomics from every
+// workgroup.
 #include "block.hpp"
 #include "internal.hpp"
 #include "variants.hpp"
 
 namespace crystal {
 
-__device__ __forceinline__ bool star_probe(const StarJoinDev &j, int32_t key, int32_t &payload,
-                                           bool want_payload) {
+__device__ __forceinline__ int step_col(const StarPlanDev &p, int s) {
+    return s < p.n_preds ? p.pred_col[s] : p.joins[s - p.n_preds].fk_col;
+}
+
+__device__ __forceinline__ bool star_probe(const StarJoinDev &j, int32_t key, int32_t &payload) {
     if (j.kind == CRYSTAL_HT_DIRECT) {
         const uint32_t off = (uint32_t)key - (uint32_t)j.key_min;
         if ((int64_t)off >= j.span) return false;
         const bool hit = (j.bitmap[off >> 5] >> (off & 31u)) & 1u;
-        if (hit && want_payload) payload = j.payload[off];
+        if (hit && j.payload) payload = j.payload[off];
         return hit;
     }
     if (key == kEmptyKey) return false;
     return probe_linear((const v2i *)j.slots, j.mask, j.shift, key, payload);
 }
 
-// One join step over the tile: BlockProbeHT on every live item, then the
-// dimension predicate on the payload field when the plan has one.
+// One step for one row (sparse phase).
+__device__ __forceinline__ bool star_step_row(const StarPlanDev &p, int s, int32_t v) {
+    if (s < p.n_preds) return in_range(v, p.pred_lo[s], p.pred_hi[s]);
+    const StarJoinDev &j = p.joins[s - p.n_preds];
+    int32_t pay = 0;
+    bool hit = star_probe(j, v, pay);
+    if (hit && j.f_bits > 0) hit = in_range(payload_field(pay, j.f_shift, j.f_mask, j.f_bits), j.f_lo, j.f_hi);
+    return hit;
+}
+
+// BlockProbeHT of a direct table for a whole tile: presence bits for every
+// item at once (dead items read entry 0), then the payload filter if any.
 template <int IPT>
-__device__ __forceinline__ uint32_t star_join_step(const StarJoinDev &j, const int32_t (&key)[IPT],
-                                                   uint32_t alive) {
-    if (j.kind == CRYSTAL_HT_DIRECT && j.f_bits == 0) {
-        // presence only: issue every bitmap load before testing any bit
-        uint32_t word[IPT];
-        uint32_t inspan = 0;
+__device__ __forceinline__ uint32_t probe_direct_tile(const StarJoinDev &j, const uint32_t *bits,
+                                                      const int32_t (&key)[IPT], uint32_t alive) {
+    uint32_t word[IPT];
+    uint32_t ok = 0;
 #pragma unroll
-        for (int k = 0; k < IPT; ++k) {
-            const uint32_t off = (uint32_t)key[k] - (uint32_t)j.key_min;
-            const bool ok = ((alive >> k) & 1u) && (int64_t)off < j.span;
-            inspan |= (uint32_t)ok << k;
-            word[k] = ok ? j.bitmap[off >> 5] : 0u;
-        }
-        uint32_t hit = 0;
-#pragma unroll
-        for (int k = 0; k < IPT; ++k) {
-            const uint32_t off = (uint32_t)key[k] - (uint32_t)j.key_min;
-            hit |= ((word[k] >> (off & 31u)) & 1u) << k;
-        }
-        return alive & inspan & hit;
+    for (int k = 0; k < IPT; ++k) {
+        const uint32_t off = (uint32_t)key[k] - (uint32_t)j.key_min;
+        const bool in = ((alive >> k) & 1u) && (int64_t)off < j.span;
+        ok |= (uint32_t)in << k;
+        word[k] = bits[in ? (off >> 5) : 0u];
     }
+    uint32_t hit = 0;
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) {
+        const uint32_t off = (uint32_t)key[k] - (uint32_t)j.key_min;
+        hit |= ((word[k] >> (off & 31u)) & 1u) << k;
+    }
+    hit &= ok;
+    if (j.f_bits == 0) return hit;
+    int32_t pay[IPT];
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) {
+        const uint32_t off = (uint32_t)key[k] - (uint32_t)j.key_min;
+        pay[k] = j.payload[((hit >> k) & 1u) ? off : 0u];
+    }
+    uint32_t pass = 0;
+#pragma unroll
+    for (int k = 0; k < IPT; ++k)
+        pass |= (uint32_t)in_range(payload_field(pay[k], j.f_shift, j.f_mask, j.f_bits), j.f_lo, j.f_hi) << k;
+    return hit & pass;
+}
+
+template <int IPT>
+__device__ __forceinline__ uint32_t probe_linear_tile(const StarJoinDev &j, const int32_t (&key)[IPT],
+                                                      uint32_t alive) {
 #pragma unroll
     for (int k = 0; k < IPT; ++k) {
         if (!((alive >> k) & 1u)) continue;
         int32_t pay = 0;
-        bool hit = star_probe(j, key[k], pay, j.f_bits > 0);
-        if (hit && j.f_bits > 0)
-            hit = in_range(payload_field(pay, j.f_shift, j.f_mask, j.f_bits), j.f_lo, j.f_hi);
+        bool hit = key[k] != kEmptyKey && probe_linear((const v2i *)j.slots, j.mask, j.shift, key[k], pay);
+        if (hit && j.f_bits > 0) hit = in_range(payload_field(pay, j.f_shift, j.f_mask, j.f_bits), j.f_lo, j.f_hi);
         if (!hit) alive &= ~(1u << k);
     }
     return alive;
 }
 
+// One dense step over a tile.  `staged` is the LDS copy of the step's bitmap
+// (or null).
+template <int IPT>
+__device__ __forceinline__ uint32_t star_step_tile(const StarPlanDev &p, int s, const uint32_t *staged,
+                                                   const int32_t (&v)[IPT], uint32_t alive) {
+    if (s < p.n_preds) return block_pred_range<IPT>(v, alive, p.pred_lo[s], p.pred_hi[s]);
+    const StarJoinDev &j = p.joins[s - p.n_preds];
+    if (j.kind == CRYSTAL_HT_DIRECT) return probe_direct_tile<IPT>(j, staged ? staged : j.bitmap, v, alive);
+    return probe_linear_tile<IPT>(j, v, alive);
+}
+
+// Group index and measure of one surviving row, added to the output (grouped)
+// or to the thread's partial (scalar).
+__device__ __forceinline__ void aggregate_row(const StarPlanDev &p, int64_t idx, uint64_t *__restrict__ out,
+                                              uint64_t &scalar_acc, bool &bad_group) {
+    int64_t g = 0;
+    if (!p.scalar) {
+        for (int jj = 0; jj < p.n_joins; ++jj) {
+            const StarJoinDev &j = p.joins[jj];
+            if (j.g_bits == 0) continue;
+            int32_t pay = 0;
+            star_probe(j, p.cols[j.fk_col][idx], pay);
+            g += ((int64_t)payload_field(pay, j.g_shift, j.g_mask, j.g_bits) - (int64_t)j.g_base) * j.g_stride;
+        }
+    }
+    uint64_t val = 1;
+    if (p.agg != CRYSTAL_AGG_COUNT) {
+        const int64_t a = p.cols[p.agg_col0][idx];
+        if (p.agg == CRYSTAL_AGG_SUM) {
+            val = (uint64_t)a;
+        } else {
+            const int64_t b = p.cols[p.agg_col1][idx];
+            val = p.agg == CRYSTAL_AGG_SUM_PRODUCT ? (uint64_t)(a * b) : (uint64_t)(a - b);
+        }
+    }
+    if (p.scalar)
+        scalar_acc += val;
+    else if ((uint64_t)g < (uint64_t)p.n_groups)
+        atomic_add_u64(out + g, val);
+    else
+        bad_group = true;
+}
+
+// Sparse phase for one queued row: the remaining steps, then the aggregate.
+__device__ __forceinline__ void finish_row(const StarPlanDev &p, int dense, int64_t row,
+                                           uint64_t *__restrict__ out, uint64_t &scalar_acc, bool &bad_group) {
+    const int n_steps = p.n_preds + p.n_joins;
+    for (int s = dense; s < n_steps; ++s)
+        if (!star_step_row(p, s, p.cols[step_col(p, s)][row])) return;
+    aggregate_row(p, row, out, scalar_acc, bad_group);
+}
+
 template <int BLOCK, int IPT>
 __global__ __launch_bounds__(BLOCK) void star_kernel(const StarPlanDev p, uint64_t *__restrict__ out,
-                                                     int32_t *status, int64_t n_tiles) {
+                                                     int32_t *status, int64_t n_tiles,
+                                                     uint64_t *__restrict__ partials) {
     using T = TileShape<BLOCK, IPT>;
+    static_assert(T::ITEMS <= 65536, "queue entries hold a 16-bit tile offset");
     __shared__ uint64_t red[T::WAVES];
+    extern __shared__ v4i lds_dyn[];
+    uint32_t *lds = reinterpret_cast<uint32_t *>(lds_dyn);
+
     const int n_steps = p.n_preds + p.n_joins;
+    const int dense = n_steps < 2 ? n_steps : 2;
+    // stage the dense steps' bitmaps (whole 64-word blocks, 16 bytes at a time)
+    const uint32_t *staged[2] = {nullptr, nullptr};
+    for (int d = 0; d < dense; ++d) {
+        if (p.stage_off[d] < 0) continue;
+        const StarJoinDev &j = p.joins[d - p.n_preds];
+        const int64_t n16 = ((j.span + 31) / 32 + 63) / 64 * 16;
+        v4i *dst = reinterpret_cast<v4i *>(lds + p.stage_off[d]);
+        const v4i *src = reinterpret_cast<const v4i *>(j.bitmap);
+        for (int64_t i = threadIdx.x; i < n16; i += BLOCK) dst[i] = src[i];
+        staged[d] = lds + p.stage_off[d];
+    }
+    // one survivor queue per wave: rows are compacted with ballots inside the
+    // wave, so waves never wait for each other
+    const uint32_t lane = lane_id();
+    const uint32_t qmask = (uint32_t)p.queue_cap - 1u;
+    uint32_t *queue = lds + p.queue_off + (threadIdx.x / kWave) * p.queue_cap;
+    __syncthreads();
+
     uint64_t scalar_acc = 0;
     bool bad_group = false;
+    uint32_t head = 0, tail = 0;  // queue cursors, equal in every lane of the wave
+    const int64_t stride = gridDim.x;
+    const int col0 = dense >= 1 ? step_col(p, 0) : 0;
+    const int col1 = dense >= 2 ? step_col(p, 1) : 0;
 
-    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-        const int64_t base = tile * T::ITEMS;
-        uint32_t alive = valid_mask<BLOCK, IPT>(base, p.n_rows);
-        int32_t v[IPT];
+    // prologue: tile 0 through its first step, its second-step loads and the
+    // first-step loads of tile 1 in flight
+    int64_t t_cur = blockIdx.x;
+    uint32_t k_cur = 0;  // position of t_cur in this workgroup's tile sequence
+    int32_t a[IPT], b[IPT];
+    uint32_t alive_c = 0;
+    if (t_cur < n_tiles) {
+        alive_c = valid_mask<BLOCK, IPT>(t_cur * T::ITEMS, p.n_rows);
+        if (dense >= 1) {
+            block_load<BLOCK, IPT, true>(p.cols[col0], t_cur * T::ITEMS, p.n_rows, a);
+            alive_c = star_step_tile<IPT>(p, 0, staged[0], a, alive_c);
+        }
+        if (dense >= 2) block_load_sel<BLOCK, IPT, true>(p.cols[col1], t_cur * T::ITEMS, p.n_rows, alive_c, b);
+        if (dense >= 1 && t_cur + stride < n_tiles)
+            block_load<BLOCK, IPT, true>(p.cols[col0], (t_cur + stride) * T::ITEMS, p.n_rows, a);
+    }
 
-        // select / probe pipeline: the first column in full, the rest selectively
-        for (int s = 0; s < n_steps; ++s) {
-            const bool is_pred = s < p.n_preds;
-            const int col = is_pred ? p.pred_col[s] : p.joins[s - p.n_preds].fk_col;
-            if (s == 0)
-                block_load<BLOCK, IPT, true>(p.cols[col], base, p.n_rows, v);
-            else
-                block_load_sel<BLOCK, IPT, true>(p.cols[col], base, p.n_rows, alive, v);
-            if (is_pred)
-                alive = block_pred_range<IPT>(v, alive, p.pred_lo[s], p.pred_hi[s]);
-            else
-                alive = star_join_step<IPT>(p.joins[s - p.n_preds], v, alive);
+    while (t_cur < n_tiles) {
+        const int64_t t_nxt = t_cur + stride;
+        const bool has_nxt = t_nxt < n_tiles;
+        uint32_t alive_n = 0;
+        int32_t b2[IPT];
+        if (has_nxt) {
+            alive_n = valid_mask<BLOCK, IPT>(t_nxt * T::ITEMS, p.n_rows);
+            if (dense >= 1) alive_n = star_step_tile<IPT>(p, 0, staged[0], a, alive_n);
+            if (dense >= 2) block_load_sel<BLOCK, IPT, true>(p.cols[col1], t_nxt * T::ITEMS, p.n_rows, alive_n, b2);
+            if (dense >= 1 && t_nxt + stride < n_tiles)
+                block_load<BLOCK, IPT, true>(p.cols[col0], (t_nxt + stride) * T::ITEMS, p.n_rows, a);
         }
-        if (!alive) continue;
+        if (dense >= 2) alive_c = star_step_tile<IPT>(p, 1, staged[1], b, alive_c);
 
-        // survivors: group index from the dimension payloads, then the measure
-        int64_t grp[IPT];
-#pragma unroll
-        for (int k = 0; k < IPT; ++k) grp[k] = 0;
-        if (!p.scalar) {
-            for (int jj = 0; jj < p.n_joins; ++jj) {
-                const StarJoinDev &j = p.joins[jj];
-                if (j.g_bits == 0) continue;
-                block_load_sel<BLOCK, IPT, false>(p.cols[j.fk_col], base, p.n_rows, alive, v);
-#pragma unroll
-                for (int k = 0; k < IPT; ++k) {
-                    if (!((alive >> k) & 1u)) continue;
-                    int32_t pay = 0;
-                    star_probe(j, v[k], pay, true);
-                    const int32_t f = payload_field(pay, j.g_shift, j.g_mask, j.g_bits);
-                    grp[k] += ((int64_t)f - (int64_t)j.g_base) * j.g_stride;
-                }
+        // compact the wave's live rows of this tile into its queue
+        uint32_t total;
+        const uint32_t off = wave_exclusive_scan_small<T::CBITS>((uint32_t)__popc(alive_c), total);
+        if (total) {
+            uint32_t pos = tail + off;
+            uint32_t m = alive_c;
+            while (m) {
+                const int k = __builtin_ctz(m);
+                m &= m - 1u;
+                const uint32_t local = (uint32_t)(((k / T::VEC) * BLOCK + threadIdx.x) * T::VEC + (k % T::VEC));
+                queue[pos & qmask] = (k_cur << 16) | local;
+                ++pos;
             }
+            tail += total;
+            __builtin_amdgcn_wave_barrier();
+            while (tail - head >= (uint32_t)kWave) {
+                const uint32_t e = queue[(head + lane) & qmask];
+                const int64_t row = ((int64_t)blockIdx.x + (int64_t)(e >> 16) * stride) * T::ITEMS + (e & 0xffffu);
+                finish_row(p, dense, row, out, scalar_acc, bad_group);
+                head += kWave;
+            }
+            __builtin_amdgcn_wave_barrier();
         }
-        int32_t a[IPT], b[IPT];
-        if (p.agg != CRYSTAL_AGG_COUNT)
-            block_load_sel<BLOCK, IPT, false>(p.cols[p.agg_col0], base, p.n_rows, alive, a);
-        if (p.agg == CRYSTAL_AGG_SUM_PRODUCT || p.agg == CRYSTAL_AGG_SUM_DIFF)
-            block_load_sel<BLOCK, IPT, false>(p.cols[p.agg_col1], base, p.n_rows, alive, b);
+        if (!has_nxt) break;
+        t_cur = t_nxt;
+        ++k_cur;
+        alive_c = alive_n;
 #pragma unroll
-        for (int k = 0; k < IPT; ++k) {
-            if (!((alive >> k) & 1u)) continue;
-            uint64_t val;
-            switch (p.agg) {
-            case CRYSTAL_AGG_SUM: val = (uint64_t)(int64_t)a[k]; break;
-            case CRYSTAL_AGG_SUM_PRODUCT: val = (uint64_t)((int64_t)a[k] * (int64_t)b[k]); break;
-            case CRYSTAL_AGG_SUM_DIFF: val = (uint64_t)((int64_t)a[k] - (int64_t)b[k]); break;
-            default: val = 1; break;
-            }
-            if (p.scalar) {
-                scalar_acc += val;
-            } else if ((uint64_t)grp[k] < (uint64_t)p.n_groups) {
-                atomic_add_u64(out + grp[k], val);
-            } else {
-                bad_group = true;
-            }
-        }
+        for (int k = 0; k < IPT; ++k) b[k] = b2[k];
+    }
+    if (lane < tail - head) {
+        const uint32_t e = queue[(head + lane) & qmask];
+        const int64_t row = ((int64_t)blockIdx.x + (int64_t)(e >> 16) * stride) * T::ITEMS + (e & 0xffffu);
+        finish_row(p, dense, row, out, scalar_acc, bad_group);
     }
     if (bad_group) set_status(status, CRYSTAL_ERANGE);
     if (p.scalar) {
         const uint64_t t = block_sum_u64<BLOCK>(scalar_acc, red);
-        if (threadIdx.x == 0 && t) atomic_add_u64(out, t);
+        if (threadIdx.x == 0) partials[blockIdx.x] = t;
     }
 }
 
+// Sum of the per-workgroup partials of a scalar query.
+__global__ __launch_bounds__(256) void star_finalize_kernel(const uint64_t *__restrict__ partials, int64_t n,
+                                                            uint64_t *__restrict__ out) {
+    __shared__ uint64_t red[4];
+    uint64_t s = 0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) s += partials[i];
+    s = block_sum_u64<256>(s, red);
+    if (threadIdx.x == 0) out[0] = s;
+}
+
+// ------------------------------------------------------------------ host ---
+static constexpr int64_t kStageBytesPerStep = 32768;
+
+static int64_t bitmap_bytes(const StarJoinDev &j) { return ((j.span + 31) / 32 + 63) / 64 * 64 * 4; }
+
+// Smallest tile is 64 x 4 rows; the grid also grows so that no workgroup
+// handles more than 65535 tiles (queue entries hold a 16-bit tile index).
+int64_t star_max_grid(int64_t n_rows) {
+    const int64_t resident = (int64_t)kStarMaxGridPerCu * device_cu_count();
+    const int64_t by_index = ((n_rows + 255) / 256 + 65534) / 65535;
+    return resident > by_index ? resident : by_index;
+}
+
 template <int BLOCK, int IPT>
-static hipError_t star_t(const LaunchCfg &cfg, const StarPlanDev &p, uint64_t *out,
-                         int32_t *status, hipStream_t s) {
+static hipError_t star_t(const LaunchCfg &cfg, StarPlanDev p, uint64_t *out, int32_t *status,
+                         uint64_t *partials, hipStream_t s) {
     using T = TileShape<BLOCK, IPT>;
     const int64_t n_tiles = (p.n_rows + T::ITEMS - 1) / T::ITEMS;
-    const int64_t grid = grid_for(n_tiles, cfg);
-    if (grid == 0) return hipSuccess;
-    hipLaunchKernelGGL((star_kernel<BLOCK, IPT>), dim3((unsigned)grid), dim3(BLOCK), 0, s, p, out,
-                       status, n_tiles);
+    // LDS: staged bitmaps of presence-only direct joins among the dense steps, then the queue
+    const int n_steps = p.n_preds + p.n_joins;
+    const int dense = n_steps < 2 ? n_steps : 2;
+    int64_t words = 0;
+    for (int d = 0; d < 2; ++d) {
+        p.stage_off[d] = -1;
+        if (d >= dense || d < p.n_preds) continue;
+        const StarJoinDev &j = p.joins[d - p.n_preds];
+        if (j.kind != CRYSTAL_HT_DIRECT || j.f_bits != 0 || bitmap_bytes(j) > kStageBytesPerStep) continue;
+        p.stage_off[d] = (int32_t)words;
+        words += bitmap_bytes(j) / 4;
+    }
+    // per-wave queue: up to one wave's tile share (64 * IPT rows) on top of
+    // fewer than 64 rows left from earlier tiles
+    int64_t qcap = 1;
+    while (qcap < kWave + kWave * IPT) qcap <<= 1;
+    p.queue_off = (int32_t)words;
+    p.queue_cap = (int32_t)qcap;
+    const int64_t lds_bytes = (words + qcap * T::WAVES) * 4;
+    // workgroups: fill the CUs as far as waves and LDS allow, unless tuned
+    int64_t per_cu = cfg.grid_per_cu > 0 ? cfg.grid_per_cu : 2048 / BLOCK;
+    const int64_t lds_cap = device_lds_per_cu() / (lds_bytes + 1024);
+    if (per_cu > lds_cap) per_cu = lds_cap > 0 ? lds_cap : 1;
+    if (per_cu > kStarMaxGridPerCu) per_cu = kStarMaxGridPerCu;
+    int64_t grid = per_cu * device_cu_count();
+    const int64_t min_grid = (n_tiles + 65534) / 65535;  // queue entries hold a 16-bit tile index
+    if (grid < min_grid) grid = min_grid;
+    if (grid > n_tiles) grid = n_tiles;
+    if (grid < 1) grid = 1;
+    auto fn = star_kernel<BLOCK, IPT>;
+    if (lds_bytes > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)lds_bytes);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(BLOCK), (size_t)lds_bytes, s, p, out, status, n_tiles,
+                       partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !p.scalar) return e;
+    hipLaunchKernelGGL(star_finalize_kernel, dim3(1), dim3(256), 0, s, partials, grid, out);
     return hipGetLastError();
 }
 
-hipError_t launch_star(const LaunchCfg &cfg, const StarPlanDev &plan, uint64_t *out,
-                       int32_t *status, hipStream_t s) {
-    hipError_t e = fill_u64(out, plan.n_groups, 0ull, s);
-    if (e != hipSuccess || plan.n_rows == 0) return e;
+hipError_t launch_star(const LaunchCfg &cfg, const StarPlanDev &plan, uint64_t *out, int32_t *status,
+                       uint64_t *partials, hipStream_t s) {
+    if (!plan.scalar) {
+        hipError_t e = fill_u64(out, plan.n_groups, 0ull, s);
+        if (e != hipSuccess) return e;
+    }
+    if (plan.n_rows == 0) return plan.scalar ? fill_u64(out, 1, 0ull, s) : hipSuccess;
     switch (CRYSTAL_VARIANT_KEY(cfg.block, cfg.ipt)) {
-#define X(B, I) case CRYSTAL_VARIANT_KEY(B, I): return star_t<B, I>(cfg, plan, out, status, s);
+#define X(B, I) case CRYSTAL_VARIANT_KEY(B, I): return star_t<B, I>(cfg, plan, out, status, partials, s);
         CRYSTAL_VARIANTS_VEC(X)
 #undef X
     default: return hipErrorInvalidValue;

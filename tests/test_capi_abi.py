@@ -83,9 +83,21 @@ def test_host_argument_errors_return_without_launch(cx):
                                 ctypes.c_void_p(16), None) == cx.EINVAL           # no memory
     q = cx.StarQueryC()
     q.n_groups = 0
-    assert lib.crystal_run_star_query(ctypes.byref(q), ctypes.c_void_p(16), ctypes.c_void_p(16), None) == cx.EINVAL
+    vp16 = ctypes.c_void_p(16)
+    assert lib.crystal_run_star_query(ctypes.byref(q), vp16, vp16, None, 0, None) == cx.EINVAL
     q.n_groups, q.n_joins = 1, 5
-    assert lib.crystal_run_star_query(ctypes.byref(q), ctypes.c_void_p(16), ctypes.c_void_p(16), None) == cx.EINVAL
+    assert lib.crystal_run_star_query(ctypes.byref(q), vp16, vp16, None, 0, None) == cx.EINVAL
+    # a scalar plan needs scratch: missing or short scratch is reported before any launch
+    q.n_joins, q.n_cols, q.n_rows, q.n_preds = 0, 1, 100, 1
+    q.cols[0] = 4096
+    q.preds[0] = cx.Pred(0, cx.Range(0, 5))
+    q.agg = cx.AGG_COUNT
+    need = lib.crystal_star_query_scratch_bytes(ctypes.byref(q))
+    assert need >= 8 * 256
+    assert lib.crystal_run_star_query(ctypes.byref(q), vp16, vp16, None, 0, None) == cx.ESCRATCH
+    assert lib.crystal_run_star_query(ctypes.byref(q), vp16, vp16, ctypes.c_void_p(4096), need - 8, None) == cx.ESCRATCH
+    q.n_groups = 10                     # grouped plan: no scratch needed
+    assert lib.crystal_star_query_scratch_bytes(ctypes.byref(q)) == 0
 
 
 def test_tuning_table(cx, tmp_path):
