@@ -65,10 +65,11 @@ __device__ __forceinline__ uint32_t probe_direct_tile(const StarJoinDev &j, cons
                                                       const int32_t (&key)[IPT], uint32_t alive) {
     uint32_t word[IPT];
     uint32_t ok = 0;
+    const uint32_t last = (uint32_t)(j.span - 1);  // span >= 1: off is in the table iff off <= last
 #pragma unroll
     for (int k = 0; k < IPT; ++k) {
         const uint32_t off = (uint32_t)key[k] - (uint32_t)j.key_min;
-        const bool in = ((alive >> k) & 1u) && (int64_t)off < j.span;
+        const bool in = ((alive >> k) & 1u) && off <= last;
         ok |= (uint32_t)in << k;
         word[k] = bits[in ? (off >> 5) : 0u];
     }
@@ -107,14 +108,41 @@ __device__ __forceinline__ uint32_t probe_linear_tile(const StarJoinDev &j, cons
     return alive;
 }
 
-// One dense step over a tile.  `staged` is the LDS copy of the step's bitmap
-// (or null).
+// Presence test of a whole tile against a bitmap staged in LDS.  `lds` is the
+// workgroup's dynamic LDS, so every lookup is a ds_read (a pointer that might
+// also point to global memory would compile to flat loads through the vector
+// memory path).
 template <int IPT>
-__device__ __forceinline__ uint32_t star_step_tile(const StarPlanDev &p, int s, const uint32_t *staged,
-                                                   const int32_t (&v)[IPT], uint32_t alive) {
+__device__ __forceinline__ uint32_t probe_staged_tile(const uint32_t *lds, int32_t stage_off, int32_t key_min,
+                                                      int64_t span, const int32_t (&key)[IPT], uint32_t alive) {
+    uint32_t word[IPT];
+    uint32_t ok = 0;
+    const uint32_t last = (uint32_t)(span - 1);  // span >= 1: off is in the table iff off <= last
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) {
+        const uint32_t off = (uint32_t)key[k] - (uint32_t)key_min;
+        const bool in = ((alive >> k) & 1u) && off <= last;
+        ok |= (uint32_t)in << k;
+        word[k] = lds[stage_off + (in ? (off >> 5) : 0u)];
+    }
+    uint32_t hit = 0;
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) {
+        const uint32_t off = (uint32_t)key[k] - (uint32_t)key_min;
+        hit |= ((word[k] >> (off & 31u)) & 1u) << k;
+    }
+    return hit & ok;
+}
+
+// One dense step over a tile: a predicate, or a probe of the LDS-staged
+// bitmap (stage_off >= 0), a direct table or a linear-probing table.
+template <int IPT>
+__device__ __forceinline__ uint32_t star_step_tile(const StarPlanDev &p, int s, const uint32_t *lds,
+                                                   int32_t stage_off, const int32_t (&v)[IPT], uint32_t alive) {
     if (s < p.n_preds) return block_pred_range<IPT>(v, alive, p.pred_lo[s], p.pred_hi[s]);
     const StarJoinDev &j = p.joins[s - p.n_preds];
-    if (j.kind == CRYSTAL_HT_DIRECT) return probe_direct_tile<IPT>(j, staged ? staged : j.bitmap, v, alive);
+    if (stage_off >= 0) return probe_staged_tile<IPT>(lds, stage_off, j.key_min, j.span, v, alive);
+    if (j.kind == CRYSTAL_HT_DIRECT) return probe_direct_tile<IPT>(j, j.bitmap, v, alive);
     return probe_linear_tile<IPT>(j, v, alive);
 }
 
@@ -159,7 +187,7 @@ __device__ __forceinline__ void finish_row(const StarPlanDev &p, int dense, int6
     aggregate_row(p, row, out, scalar_acc, bad_group);
 }
 
-template <int BLOCK, int IPT>
+template <int BLOCK, int IPT, int PF>
 __global__ __launch_bounds__(BLOCK) void star_kernel(const StarPlanDev p, uint64_t *__restrict__ out,
                                                      int32_t *status, int64_t n_tiles,
                                                      uint64_t *__restrict__ partials) {
@@ -172,15 +200,15 @@ __global__ __launch_bounds__(BLOCK) void star_kernel(const StarPlanDev p, uint64
     const int n_steps = p.n_preds + p.n_joins;
     const int dense = n_steps < 2 ? n_steps : 2;
     // stage the dense steps' bitmaps (whole 64-word blocks, 16 bytes at a time)
-    const uint32_t *staged[2] = {nullptr, nullptr};
+    const int32_t so0 = dense >= 1 ? p.stage_off[0] : -1;
+    const int32_t so1 = dense >= 2 ? p.stage_off[1] : -1;
     for (int d = 0; d < dense; ++d) {
-        if (p.stage_off[d] < 0) continue;
+        const int32_t so = d == 0 ? so0 : so1;
+        if (so < 0) continue;
         const StarJoinDev &j = p.joins[d - p.n_preds];
         const int64_t n16 = ((j.span + 31) / 32 + 63) / 64 * 16;
-        v4i *dst = reinterpret_cast<v4i *>(lds + p.stage_off[d]);
         const v4i *src = reinterpret_cast<const v4i *>(j.bitmap);
-        for (int64_t i = threadIdx.x; i < n16; i += BLOCK) dst[i] = src[i];
-        staged[d] = lds + p.stage_off[d];
+        for (int64_t i = threadIdx.x; i < n16; i += BLOCK) lds_dyn[so / 4 + i] = src[i];
     }
     // one survivor queue per wave: rows are compacted with ballots inside the
     // wave, so waves never wait for each other
@@ -196,36 +224,44 @@ __global__ __launch_bounds__(BLOCK) void star_kernel(const StarPlanDev p, uint64
     const int col0 = dense >= 1 ? step_col(p, 0) : 0;
     const int col1 = dense >= 2 ? step_col(p, 1) : 0;
 
-    // prologue: tile 0 through its first step, its second-step loads and the
-    // first-step loads of tile 1 in flight
+    // Pipeline over this workgroup's tiles t_0, t_1, ...: while tile t_k is
+    // finished, the second-step loads of t_{k+1} and the first-step loads of
+    // t_{k+1} .. t_{k+PF} are in flight.  Loads land in alternating register
+    // buffers (the loop is unrolled by two), so no buffer is copied while
+    // its loads are still outstanding.
+    int32_t a0[IPT], a1[IPT];  // first-step column of upcoming tiles
+    int32_t b0[IPT], b1[IPT];  // second-step column of the current and the next tile
     int64_t t_cur = blockIdx.x;
-    uint32_t k_cur = 0;  // position of t_cur in this workgroup's tile sequence
-    int32_t a[IPT], b[IPT];
+    uint32_t k_cur = 0;        // position of t_cur in this workgroup's tile sequence
     uint32_t alive_c = 0;
     if (t_cur < n_tiles) {
         alive_c = valid_mask<BLOCK, IPT>(t_cur * T::ITEMS, p.n_rows);
         if (dense >= 1) {
-            block_load<BLOCK, IPT, true>(p.cols[col0], t_cur * T::ITEMS, p.n_rows, a);
-            alive_c = star_step_tile<IPT>(p, 0, staged[0], a, alive_c);
+            block_load<BLOCK, IPT, true>(p.cols[col0], t_cur * T::ITEMS, p.n_rows, a0);
+            alive_c = star_step_tile<IPT>(p, 0, lds, so0, a0, alive_c);
         }
-        if (dense >= 2) block_load_sel<BLOCK, IPT, true>(p.cols[col1], t_cur * T::ITEMS, p.n_rows, alive_c, b);
+        if (dense >= 2) block_load_sel<BLOCK, IPT, true>(p.cols[col1], t_cur * T::ITEMS, p.n_rows, alive_c, b0);
         if (dense >= 1 && t_cur + stride < n_tiles)
-            block_load<BLOCK, IPT, true>(p.cols[col0], (t_cur + stride) * T::ITEMS, p.n_rows, a);
+            block_load<BLOCK, IPT, true>(p.cols[col0], (t_cur + stride) * T::ITEMS, p.n_rows, a0);
+        if (PF == 2 && dense >= 1 && t_cur + 2 * stride < n_tiles)
+            block_load<BLOCK, IPT, true>(p.cols[col0], (t_cur + 2 * stride) * T::ITEMS, p.n_rows, a1);
     }
 
-    while (t_cur < n_tiles) {
+    // One pipeline iteration.  `an` holds the first-step column of t_nxt;
+    // `bc` the second-step column of t_cur; `bn` receives that of t_nxt.
+    auto iterate = [&](int32_t (&an)[IPT], int32_t (&bc)[IPT], int32_t (&bn)[IPT]) -> bool {
         const int64_t t_nxt = t_cur + stride;
         const bool has_nxt = t_nxt < n_tiles;
         uint32_t alive_n = 0;
-        int32_t b2[IPT];
         if (has_nxt) {
             alive_n = valid_mask<BLOCK, IPT>(t_nxt * T::ITEMS, p.n_rows);
-            if (dense >= 1) alive_n = star_step_tile<IPT>(p, 0, staged[0], a, alive_n);
-            if (dense >= 2) block_load_sel<BLOCK, IPT, true>(p.cols[col1], t_nxt * T::ITEMS, p.n_rows, alive_n, b2);
-            if (dense >= 1 && t_nxt + stride < n_tiles)
-                block_load<BLOCK, IPT, true>(p.cols[col0], (t_nxt + stride) * T::ITEMS, p.n_rows, a);
+            if (dense >= 1) alive_n = star_step_tile<IPT>(p, 0, lds, so0, an, alive_n);
+            if (dense >= 2) block_load_sel<BLOCK, IPT, true>(p.cols[col1], t_nxt * T::ITEMS, p.n_rows, alive_n, bn);
+            const int64_t t_pf = t_nxt + PF * stride;
+            if (dense >= 1 && t_pf < n_tiles)
+                block_load<BLOCK, IPT, true>(p.cols[col0], t_pf * T::ITEMS, p.n_rows, an);
         }
-        if (dense >= 2) alive_c = star_step_tile<IPT>(p, 1, staged[1], b, alive_c);
+        if (dense >= 2) alive_c = star_step_tile<IPT>(p, 1, lds, so1, bc, alive_c);
 
         // compact the wave's live rows of this tile into its queue
         uint32_t total;
@@ -250,12 +286,17 @@ __global__ __launch_bounds__(BLOCK) void star_kernel(const StarPlanDev p, uint64
             }
             __builtin_amdgcn_wave_barrier();
         }
-        if (!has_nxt) break;
+        if (!has_nxt) return false;
         t_cur = t_nxt;
         ++k_cur;
         alive_c = alive_n;
-#pragma unroll
-        for (int k = 0; k < IPT; ++k) b[k] = b2[k];
+        return true;
+    };
+    if (t_cur < n_tiles) {
+        for (;;) {
+            if (!iterate(a0, b0, b1)) break;
+            if (!iterate(PF == 2 ? a1 : a0, b1, b0)) break;
+        }
     }
     if (lane < tail - head) {
         const uint32_t e = queue[(head + lane) & qmask];
@@ -326,7 +367,8 @@ static hipError_t star_t(const LaunchCfg &cfg, StarPlanDev p, uint64_t *out, int
     if (grid < min_grid) grid = min_grid;
     if (grid > n_tiles) grid = n_tiles;
     if (grid < 1) grid = 1;
-    auto fn = star_kernel<BLOCK, IPT>;
+    // prefetch depth one tile (a second register buffer costs more waves than it gains)
+    auto fn = star_kernel<BLOCK, IPT, 1>;
     if (lds_bytes > 65536) {
         hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            (int)lds_bytes);
