@@ -69,19 +69,35 @@ size_t crystal_struct_size(int32_t which);
 /* ------------------------------------------------------------------------ */
 /* Selection -- section 4.2, query Q3 (and section 3.2, query Q0):           */
 /*   SELECT y FROM R WHERE pred.lo <= y <= pred.hi                           */
-/* One kernel: BlockLoad, BlockPred, BlockScan, one 64-bit atomic per tile   */
-/* on *out_count to reserve the tile's output range, BlockShuffle through    */
-/* LDS, BlockStore (coalesced).                                              */
+/* One kernel: BlockLoad, BlockPred, BlockScan of the match counts, thread 0 */
+/* reserves the tile's output range with one 64-bit atomic on *out_count     */
+/* (skipped for a tile without matches), BlockShuffle through LDS,           */
+/* BlockStore (coalesced).                                                   */
 /*   in        device, n int32 values                                        */
 /*   out       device, capacity for every match (n values always suffice)    */
 /*   out_count device int64; cleared, then the number of matches             */
-/* Output order: the qualifying values of a tile are contiguous, grouped by  */
-/* thread as in the section 3.2 example; tiles follow the order in which    */
-/* their atomic reservations completed, which varies between runs.  The     */
-/* multiset of values and the count are exact.                              */
+/* Output order: the matches of a tile are contiguous and in input order;    */
+/* tiles follow the order in which their reservations completed, which       */
+/* varies between runs.  The multiset of values and the count are exact.     */
 /* ------------------------------------------------------------------------ */
 crystal_status crystal_select(const int32_t *in, int64_t n, crystal_range pred,
                               int32_t *out, int64_t *out_count, void *stream);
+
+/* The same selection with the qualifying values in input order (a stable    */
+/* compaction, identical on every run).  Each tile publishes its match count */
+/* in its own status word and finds its output offset by decoupled look-back */
+/* over its predecessors' words instead of an atomic reservation; slower on  */
+/* MI355X, whose eight XCD caches are not coherent, so every look-back round */
+/* is a memory round trip.                                                   */
+/*   scratch   device, >= crystal_select_stable_scratch_bytes(n) bytes,      */
+/*             16-byte aligned (tile status words); calls sharing it must be */
+/*             ordered on one stream                                         */
+/*   out_count the number of matches, or -1 if a tile's wait for its         */
+/*             predecessors gave up (ruled out by in-order dispatch)          */
+size_t crystal_select_stable_scratch_bytes(int64_t n);
+crystal_status crystal_select_stable(const int32_t *in, int64_t n, crystal_range pred,
+                                     int32_t *out, int64_t *out_count, void *scratch,
+                                     size_t scratch_bytes, void *stream);
 
 /* ------------------------------------------------------------------------ */
 /* Projection -- section 4.1, query Q1:  SELECT a*x1 + b*x2 FROM R          */

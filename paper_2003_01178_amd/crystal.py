@@ -67,6 +67,8 @@ def _declare(lib):
         "crystal_abi_version": (c_i32, []),
         "crystal_struct_size": (ctypes.c_size_t, [c_i32]),
         "crystal_select": (c_i32, [c_vp, c_i64, Range, c_vp, c_vp, c_vp]),
+        "crystal_select_stable_scratch_bytes": (ctypes.c_size_t, [c_i64]),
+        "crystal_select_stable": (c_i32, [c_vp, c_i64, Range, c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp]),
         "crystal_project": (c_i32, [c_vp, c_vp, c_i64, c_f32, c_f32, c_vp, c_vp]),
         "crystal_project_sigmoid": (c_i32, [c_vp, c_vp, c_i64, c_f32, c_f32, c_vp, c_vp]),
         "crystal_ht_init": (c_i32, [P(HT), c_i32, c_i64, c_i32, c_i32, c_i32]),
@@ -155,14 +157,26 @@ def check_status(status):
 
 
 # ------------------------------------------------------------------ calls --
-def select(x, lo, hi, out=None, count=None, stream=None):
-    """Section 4.2 Q3: values of x with lo <= x <= hi -> (out[:count], count tensor)."""
+def select(x, lo, hi, out=None, count=None, stable=False, scratch=None, stream=None):
+    """Section 4.2 Q3: values of x with lo <= x <= hi -> (out, count tensor).
+
+    stable=False: tiles land in the order of their atomic reservations;
+    stable=True: the values in input order (decoupled look-back)."""
     lib = load()
     n = x.numel()
     out = torch.empty(max(n, 1), dtype=torch.int32, device=x.device) if out is None else out
+    if out.numel() < n:
+        raise ValueError("output buffer smaller than the input")
     count = torch.empty(1, dtype=torch.int64, device=x.device) if count is None else count
-    _check(lib.crystal_select(_col(x), n, Range(int(lo), int(hi)), _ptr(out), _ptr(count),
-                              _stream(stream)), "crystal_select")
+    if not stable:
+        _check(lib.crystal_select(_col(x), n, Range(int(lo), int(hi)), _ptr(out), _ptr(count), _stream(stream)),
+               "crystal_select")
+        return out, count
+    nbytes = lib.crystal_select_stable_scratch_bytes(n)
+    if scratch is None or scratch.numel() < nbytes:
+        scratch = torch.empty(nbytes, dtype=torch.uint8, device=x.device)
+    _check(lib.crystal_select_stable(_col(x), n, Range(int(lo), int(hi)), _ptr(out), _ptr(count), _ptr(scratch),
+                                     scratch.numel(), _stream(stream)), "crystal_select_stable")
     return out, count
 
 

@@ -70,7 +70,7 @@ static std::vector<TuneEntry> g_tune;
 
 static LaunchCfg default_cfg(int kernel) {
     switch (kernel) {
-    case CRYSTAL_K_SELECT: return {256, 16, 0};
+    case CRYSTAL_K_SELECT: return {1024, 16, 0};
     case CRYSTAL_K_PROJECT: return {256, 16, 0};
     case CRYSTAL_K_HT_PROBE: return {256, 16, 8};
     case CRYSTAL_K_GROUPBY: return {256, 16, 0};
@@ -232,14 +232,26 @@ size_t crystal_struct_size(int32_t which) {
 
 crystal_status crystal_select(const int32_t *in, int64_t n, crystal_range pred, int32_t *out,
                               int64_t *out_count, void *stream) {
-    if (n < 0 || !out_count || (n > 0 && (!in || !out || !aligned16(in))))
-        return CRYSTAL_EINVAL;
-    hipStream_t s = as_stream(stream);
-    hipError_t e = fill_u64((uint64_t *)out_count, 1, 0ull, s);
-    if (e != hipSuccess) return CRYSTAL_EHIP;
-    if (n == 0 || pred.lo > pred.hi) return CRYSTAL_OK;
-    return from_hip(launch_select(tune_lookup(CRYSTAL_K_SELECT, n), in, n, pred.lo, pred.hi, out,
-                                  (uint64_t *)out_count, s));
+    if (n < 0 || !out_count || (n > 0 && (!in || !out || !aligned16(in)))) return CRYSTAL_EINVAL;
+    return from_hip(launch_select(tune_lookup(CRYSTAL_K_SELECT, n), in, n, pred.lo, pred.hi, out, out_count,
+                                  nullptr, false, as_stream(stream)));
+}
+
+size_t crystal_select_stable_scratch_bytes(int64_t n) {
+    if (n <= 0) return 16;
+    const int64_t items = select_tile_items(tune_lookup(CRYSTAL_K_SELECT, n));
+    return (size_t)((n + items - 1) / items) * 8 + 16;
+}
+
+crystal_status crystal_select_stable(const int32_t *in, int64_t n, crystal_range pred, int32_t *out,
+                                     int64_t *out_count, void *scratch, size_t scratch_bytes, void *stream) {
+    if (n < 0 || !out_count || (n > 0 && (!in || !out || !aligned16(in)))) return CRYSTAL_EINVAL;
+    if (n > 0 && pred.lo <= pred.hi) {
+        if (!scratch || !aligned16(scratch)) return scratch ? CRYSTAL_EINVAL : CRYSTAL_ESCRATCH;
+        if (scratch_bytes < crystal_select_stable_scratch_bytes(n)) return CRYSTAL_ESCRATCH;
+    }
+    return from_hip(launch_select(tune_lookup(CRYSTAL_K_SELECT, n), in, n, pred.lo, pred.hi, out, out_count,
+                                  (uint64_t *)scratch, true, as_stream(stream)));
 }
 
 static crystal_status project_common(const float *x1, const float *x2, int64_t n, float a, float b,

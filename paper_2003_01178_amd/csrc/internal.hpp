@@ -45,8 +45,10 @@ hipError_t fill_u32(uint32_t *p, int64_t n, uint32_t value, hipStream_t s);
 // Zero two separate 64-bit words with one launch.
 hipError_t zero_pair(uint64_t *a, uint64_t *b, hipStream_t s);
 
-hipError_t launch_select(const LaunchCfg &cfg, const int32_t *in, int64_t n, int32_t lo,
-                         int32_t hi, int32_t *out, uint64_t *count, hipStream_t s);
+hipError_t launch_select(const LaunchCfg &cfg, const int32_t *in, int64_t n, int32_t lo, int32_t hi,
+                         int32_t *out, int64_t *count, uint64_t *status_words, bool stable, hipStream_t s);
+// Items per selection tile under cfg (status words needed: ceil(n / items)).
+int64_t select_tile_items(const LaunchCfg &cfg);
 hipError_t launch_project(const LaunchCfg &cfg, const float *x1, const float *x2, int64_t n,
                           float a, float b, float *out, bool sigmoid, hipStream_t s);
 

@@ -50,57 +50,212 @@ hipError_t fill_u32(uint32_t *p, int64_t n, uint32_t value, hipStream_t s) {
 }
 
 // ------------------------------------------------------------- selection --
-// Tile = BlockLoad -> BlockPred -> BlockScan of the per-thread match counts ->
-// thread 0 reserves the tile's output range with one 64-bit atomic ->
-// BlockShuffle the matches into LDS in thread order -> BlockStore.
-template <int BLOCK, int IPT>
+// Tile = BlockLoad -> BlockPred -> BlockScan of the match counts -> the tile's
+// output offset -> BlockShuffle into LDS (matches in input order within the
+// tile) -> BlockStore.
+//
+// Output offsets, two ways:
+//  - unordered (the method of section 3.2): thread 0 reserves the tile's
+//    output range with one 64-bit atomic on the global counter, skipped when
+//    the tile has no match.  Same-address atomics from the eight XCDs
+//    serialise at the memory-side atomic unit (about 12 ns each on MI355X),
+//    so tiles are large (the tuned default is 1024 x 16 = 16 Ki items) to
+//    keep the reservations well below the time the column takes to stream.
+//  - stable: every tile publishes its match count in its own 64-bit status
+//    word and finds its offset by decoupled look-back over its predecessors'
+//    words (the single-pass scan of Merrill and Garland): each round the
+//    workgroup reads BLOCK predecessors' words and stops at the nearest one
+//    that holds an inclusive prefix.  Tiles then land in input order, so the
+//    output is the qualifying values in input order on every run; the status
+//    words live in memory that all XCDs see, so each round costs a memory
+//    round trip.
+//
+// Status word: bits 63..62 = 0 (nothing yet), 1 (tile count), 2 (inclusive
+// prefix); bits 61..0 = the count.  Words are read and written with
+// agent-scope atomics (coherent across XCDs).  A tile only waits for lower-
+// numbered tiles and there is one tile per workgroup, dispatched in order, so
+// the lowest unfinished tile is always running; should a predecessor still
+// never publish, the wait gives up after a bounded number of polls: that tile
+// publishes the poison prefix 2^61, every later tile inherits it and writes
+// nothing, and the last tile reports a count of -1.
+static constexpr uint64_t kStAgg = 1ull << 62;
+static constexpr uint64_t kStIncl = 2ull << 62;
+static constexpr uint64_t kStValue = (1ull << 62) - 1;
+static constexpr uint64_t kPoison = 1ull << 61;
+static constexpr uint32_t kLookbackPolls = 1u << 15;
+
+__device__ __forceinline__ uint64_t status_load(const uint64_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void status_store(uint64_t *p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Called by every thread of the workgroup.  Publishes the tile's count and
+// returns the number of matches in all earlier tiles (kPoison if unknown).
+// Each round, thread i reads the status word of tile top - i, so a round
+// covers BLOCK predecessors with one memory round trip; the waves' findings
+// are combined through LDS (wave_incl / wave_ready / wave_sum).
+template <int BLOCK>
+__device__ __forceinline__ uint64_t block_lookback(uint64_t *st, int64_t tile, uint64_t count,
+                                                   uint32_t *wave_flags, uint64_t *wave_sum) {
+    constexpr int W = BLOCK / kWave;
+    const uint32_t lane = lane_id();
+    const int w = threadIdx.x / kWave;
+    if (threadIdx.x == 0) status_store(st + tile, (tile == 0 ? kStIncl : kStAgg) | count);
+    if (tile == 0) return 0;
+    uint64_t running = 0;
+    bool poisoned = false;
+    int64_t top = tile - 1;
+    uint32_t polls = 0;
+    for (;;) {
+        const int64_t idx = top - (int64_t)threadIdx.x;
+        const uint64_t v = idx >= 0 ? status_load(st + idx) : kStIncl;  // before tile 0: prefix 0
+        const uint32_t flag = (uint32_t)(v >> 62);
+        const uint64_t incl = ballot(flag == 2u);
+        const uint64_t none = ballot(flag == 0u);
+        // lanes 0..stop, stop = this wave's nearest predecessor with an inclusive prefix
+        const uint64_t upto = incl ? ((incl & (~incl + 1ull)) << 1) - 1ull : ~0ull;
+        const bool mine = (upto >> lane) & 1ull;
+        const bool poison = ballot(mine && (v & kStValue) >= kPoison) != 0;
+        const uint64_t sum = wave_sum_u64(mine ? (v & kStValue) : 0ull);
+        if (lane == 0) {
+            wave_flags[w] = (incl ? 1u : 0u) | ((none & upto) ? 0u : 2u) | (poison ? 4u : 0u);
+            wave_sum[w] = sum;
+        }
+        __syncthreads();
+        // the nearest waves first: add ready waves until one holds an inclusive prefix
+        bool ready = true, done = false;
+        uint64_t add = 0;
+        for (int ww = 0; ww < W; ++ww) {
+            const uint32_t f = wave_flags[ww];
+            if (!(f & 2u)) {
+                ready = false;
+                break;
+            }
+            if (f & 4u) poisoned = true;
+            add += wave_sum[ww];
+            if (f & 1u) {
+                done = true;
+                break;
+            }
+        }
+        __syncthreads();
+        if (poisoned) break;
+        if (!ready) {
+            if (++polls > kLookbackPolls) {
+                poisoned = true;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+            continue;
+        }
+        running += add;
+        if (done) break;
+        top -= BLOCK;
+    }
+    if (poisoned) running = kPoison;
+    if (threadIdx.x == 0) status_store(st + tile, kStIncl | (poisoned ? kPoison : running + count));
+    return running;
+}
+
+template <int BLOCK, int IPT, bool STABLE>
 __global__ __launch_bounds__(BLOCK) void select_kernel(const int32_t *__restrict__ in, int64_t n,
                                                        int32_t lo, int32_t hi,
                                                        int32_t *__restrict__ out,
-                                                       uint64_t *__restrict__ count,
+                                                       uint64_t *__restrict__ st,
+                                                       int64_t *__restrict__ count_out,
                                                        int64_t n_tiles) {
     using T = TileShape<BLOCK, IPT>;
+    constexpr int C = T::CHUNKS, W = T::WAVES, V = T::VEC;
+    constexpr int VBITS = V == 1 ? 1 : V == 2 ? 2 : 3;
     __shared__ int32_t buf[T::ITEMS];
-    __shared__ uint32_t wave_tot[T::WAVES];
-    __shared__ uint64_t out_base;
-    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+    __shared__ uint32_t chunk_tot[C * W];
+    __shared__ uint32_t wave_flags[W];
+    __shared__ uint64_t wave_sum[W];
+    __shared__ uint64_t tile_off;
+    const int w = threadIdx.x / kWave;
+    const uint32_t lane = lane_id();
+    {
+        const int64_t tile = blockIdx.x;
         const int64_t base = tile * T::ITEMS;
         int32_t v[IPT];
         block_load<BLOCK, IPT, true>(in, base, n, v);
         const uint32_t flags = block_pred_range<IPT>(v, valid_mask<BLOCK, IPT>(base, n), lo, hi);
-        uint32_t total;
-        uint32_t off = block_exclusive_scan<BLOCK, T::CBITS>((uint32_t)__popc(flags), wave_tot, total);
-        if (total != 0) {
-            if (threadIdx.x == 0) out_base = atomic_add_u64(count, total);
+        // BlockScan in input order: item (c, t, e) precedes (c, t', e') when t < t',
+        // and chunk c precedes chunk c + 1
+        uint32_t pre[C];
 #pragma unroll
-            for (int k = 0; k < IPT; ++k)
-                if ((flags >> k) & 1u) buf[off++] = v[k];
-            __syncthreads();
-            const uint64_t ob = out_base;
-            for (uint32_t i = threadIdx.x; i < total; i += BLOCK)
-                __builtin_nontemporal_store(buf[i], out + ob + i);
+        for (int c = 0; c < C; ++c) {
+            uint32_t wt;
+            pre[c] = wave_exclusive_scan_small<VBITS>((uint32_t)__popc((flags >> (c * V)) & T::VMASK), wt);
+            if (lane == 0) chunk_tot[c * W + w] = wt;
         }
         __syncthreads();
+        uint32_t cbase[C];
+        uint32_t total = 0;
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int ww = 0; ww < W; ++ww) {
+                const uint32_t t = chunk_tot[c * W + ww];
+                if (ww == w) cbase[c] = total;
+                total += t;
+            }
+        uint64_t ob;
+        if constexpr (STABLE) {
+            ob = block_lookback<BLOCK>(st, tile, total, wave_flags, wave_sum);
+        } else {
+            if (threadIdx.x == 0 && total) tile_off = atomic_add_u64((uint64_t *)count_out, total);
+        }
+        // BlockShuffle: matches to their tile positions in LDS
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            uint32_t pos = cbase[c] + pre[c];
+#pragma unroll
+            for (int e = 0; e < V; ++e)
+                if ((flags >> (c * V + e)) & 1u) buf[pos++] = v[c * V + e];
+        }
+        __syncthreads();
+        if constexpr (!STABLE) ob = total ? tile_off : 0;
+        if (ob < kPoison)
+            for (uint32_t i = threadIdx.x; i < total; i += BLOCK) __builtin_nontemporal_store(buf[i], out + ob + i);
+        if (STABLE && tile == n_tiles - 1 && threadIdx.x == 0) *count_out = ob < kPoison ? (int64_t)(ob + total) : -1;
     }
 }
 
 template <int BLOCK, int IPT>
-static hipError_t select_t(const LaunchCfg &cfg, const int32_t *in, int64_t n, int32_t lo,
-                           int32_t hi, int32_t *out, uint64_t *count, hipStream_t s) {
+static hipError_t select_t(const LaunchCfg &cfg, const int32_t *in, int64_t n, int32_t lo, int32_t hi,
+                           int32_t *out, int64_t *count, uint64_t *st, bool stable, hipStream_t s) {
     using T = TileShape<BLOCK, IPT>;
     const int64_t n_tiles = (n + T::ITEMS - 1) / T::ITEMS;
-    const int64_t grid = grid_for(n_tiles, cfg);
-    if (grid == 0) return hipSuccess;
-    hipLaunchKernelGGL((select_kernel<BLOCK, IPT>), dim3((unsigned)grid), dim3(BLOCK), 0, s, in, n,
-                       lo, hi, out, count, n_tiles);
+    // one workgroup per tile, always: a stable tile only waits for lower-
+    // numbered tiles, which in-order dispatch has already started; workgroups
+    // striding over tiles could wait for a tile whose workgroup is not resident
+    (void)cfg;
+    hipError_t e;
+    if (stable) {
+        e = fill_u64(st, n_tiles, 0ull, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((select_kernel<BLOCK, IPT, true>), dim3((unsigned)n_tiles), dim3(BLOCK), 0, s, in, n,
+                           lo, hi, out, st, count, n_tiles);
+    } else {
+        e = fill_u64((uint64_t *)count, 1, 0ull, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((select_kernel<BLOCK, IPT, false>), dim3((unsigned)n_tiles), dim3(BLOCK), 0, s, in, n,
+                           lo, hi, out, st, count, n_tiles);
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_select(const LaunchCfg &cfg, const int32_t *in, int64_t n, int32_t lo,
-                         int32_t hi, int32_t *out, uint64_t *count, hipStream_t s) {
+int64_t select_tile_items(const LaunchCfg &cfg) { return (int64_t)cfg.block * cfg.ipt; }
+
+hipError_t launch_select(const LaunchCfg &cfg, const int32_t *in, int64_t n, int32_t lo, int32_t hi,
+                         int32_t *out, int64_t *count, uint64_t *status_words, bool stable, hipStream_t s) {
+    if (n == 0 || lo > hi) return fill_u64((uint64_t *)count, 1, 0ull, s);
     switch (CRYSTAL_VARIANT_KEY(cfg.block, cfg.ipt)) {
 #define X(B, I) \
-    case CRYSTAL_VARIANT_KEY(B, I): return select_t<B, I>(cfg, in, n, lo, hi, out, count, s);
+    case CRYSTAL_VARIANT_KEY(B, I): return select_t<B, I>(cfg, in, n, lo, hi, out, count, status_words, stable, s);
         CRYSTAL_VARIANTS_ALL(X)
 #undef X
     default: return hipErrorInvalidValue;

@@ -72,10 +72,17 @@ def test_ht_descriptors(cx):
 
 def test_host_argument_errors_return_without_launch(cx):
     lib = cx.load()
+    vp16 = ctypes.c_void_p(16)
     assert lib.crystal_select(None, -1, cx.Range(0, 1), None, None, None) == cx.EINVAL
-    assert lib.crystal_select(ctypes.c_void_p(16), 10, cx.Range(0, 1), None, ctypes.c_void_p(16), None) == cx.EINVAL
+    assert lib.crystal_select(vp16, 10, cx.Range(0, 1), None, vp16, None) == cx.EINVAL
     assert lib.crystal_select(ctypes.c_void_p(20), 10, cx.Range(0, 1), ctypes.c_void_p(32),
-                              ctypes.c_void_p(16), None) == cx.EINVAL           # misaligned column
+                              vp16, None) == cx.EINVAL                         # misaligned column
+    assert lib.crystal_select_stable(None, -1, cx.Range(0, 1), None, None, None, 0, None) == cx.EINVAL
+    need = lib.crystal_select_stable_scratch_bytes(1 << 29)
+    assert need >= (1 << 29) // (1024 * 16) * 8
+    assert lib.crystal_select_stable(vp16, 1 << 29, cx.Range(0, 1), vp16, vp16, None, 0, None) == cx.ESCRATCH
+    assert lib.crystal_select_stable(vp16, 1 << 29, cx.Range(0, 1), vp16, vp16, vp16, need - 8,
+                                     None) == cx.ESCRATCH
     assert lib.crystal_project(None, None, 5, 1.0, 1.0, None, None) == cx.EINVAL
     assert lib.crystal_groupby_agg(None, None, 0, 0, ctypes.c_void_p(16), ctypes.c_void_p(16), None) == cx.EINVAL
     ht = cx.HT()

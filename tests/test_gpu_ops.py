@@ -27,60 +27,79 @@ def dev(a):
 
 
 # ------------------------------------------------------------------ select --
+def check_select(got_out, got_count, y, lo, hi, stable):
+    want = oracle.select(y, lo, hi)
+    c = int(got_count.item())
+    assert c == want.size
+    got = got_out[:c].cpu().numpy()
+    if stable:
+        assert np.array_equal(got, want)                 # input order, element by element
+    else:
+        # tiles land in reservation order: the multiset is unique, the order is not
+        assert np.array_equal(np.sort(got), np.sort(want))
+
+
+@pytest.mark.parametrize("stable", [False, True])
 @pytest.mark.parametrize("n", SIZES)
 @pytest.mark.parametrize("sigma", [0.0, 0.1, 0.5, 1.0])
-def test_select_matches_oracle(n, sigma):
-    announce("select", n, sigma)
+def test_select_matches_oracle(n, sigma, stable):
+    announce("select", n, sigma, stable)
     y = datagen.select_column(n, workload=1000 + n)
     lo, hi = datagen.select_threshold_range(sigma)
-    out, cnt = cx.select(dev(y), lo, hi)
-    c = int(cnt.item())
-    want = oracle.select(y, lo, hi)
-    assert c == want.size
-    got = out[:c].cpu().numpy()
-    assert np.array_equal(np.sort(got), np.sort(want))
+    out, cnt = cx.select(dev(y), lo, hi, stable=stable)
+    check_select(out, cnt, y, lo, hi, stable)
 
 
 @pytest.mark.parametrize("block,ipt", SHAPES)
 def test_select_tile_shapes(block, ipt):
     announce("select shape", block, ipt)
-    cx.tune_set(cx.K_SELECT, block, ipt, 0)
-    for gpc in (0, 2):
-        cx.tune_set(cx.K_SELECT, block, ipt, gpc)
+    for stable in (False, True):
+        cx.tune_set(cx.K_SELECT, block, ipt, 0)
         n = 3 * block * ipt + 5
         y = datagen.select_column(n, workload=7)
-        lo, hi = 0, 2 ** 30
-        out, cnt = cx.select(dev(y), lo, hi)
-        want = oracle.select(y, lo, hi)
-        c = int(cnt.item())
-        assert c == want.size
-        assert np.array_equal(np.sort(out[:c].cpu().numpy()), np.sort(want))
+        out, cnt = cx.select(dev(y), 0, 2 ** 30, stable=stable)
+        check_select(out, cnt, y, 0, 2 ** 30, stable)
+
+
+def test_select_unordered_keeps_tiles_contiguous():
+    """Each tile's matches form one contiguous run in input order."""
+    announce("select runs")
+    cx.tune_set(cx.K_SELECT, 256, 4, 0)                  # 1024-item tiles
+    n = 64 * 1024
+    y = np.arange(n, dtype=np.int32)
+    out, cnt = cx.select(dev(y), 0, n, stable=False)
+    got = out[:int(cnt.item())].cpu().numpy()
+    runs = got.reshape(-1, 1024)                         # every value matches: whole tiles
+    assert np.all(np.diff(runs, axis=1) == 1) and np.all(runs[:, 0] % 1024 == 0)
+    assert np.array_equal(np.sort(got), y)
 
 
 def test_select_tile_example_and_extremes():
     announce("select extremes")
     y = np.array([9, 2, 7, 8, 1, 3, 6, 12, 10, 0, 11, 4, 5, 14, 13, 15], dtype=np.int32)
-    out, cnt = cx.select(dev(y), 6, I32_MAX)
-    assert int(cnt.item()) == 10
-    assert sorted(out[:10].cpu().tolist()) == sorted([9, 10, 14, 7, 6, 11, 13, 8, 12, 15])
+    for stable in (False, True):
+        out, cnt = cx.select(dev(y), 6, I32_MAX, stable=stable)
+        assert int(cnt.item()) == 10
+        assert out[:10].cpu().tolist() == oracle.select(y, 6, I32_MAX).tolist()   # one tile: input order
     z = np.array([I32_MIN, -1, 0, 1, I32_MAX] * 1000, dtype=np.int32)
     for lo, hi in [(I32_MIN, I32_MAX), (I32_MIN, I32_MIN), (I32_MAX, I32_MAX), (0, 0), (5, 4)]:
-        out, cnt = cx.select(dev(z), lo, hi)
-        want = oracle.select(z, lo, hi)
-        assert int(cnt.item()) == want.size
-        assert np.array_equal(np.sort(out[:want.size].cpu().numpy()), np.sort(want))
+        for stable in (False, True):
+            out, cnt = cx.select(dev(z), lo, hi, stable=stable)
+            check_select(out, cnt, z, lo, hi, stable)
 
 
-def test_select_deterministic_multiset():
+def test_select_stable_is_deterministic():
     announce("select repeat")
-    y = datagen.select_column(1 << 20, workload=5)
+    y = datagen.select_column(1 << 22, workload=5)
     x = dev(y)
+    scratch = torch.empty(1 << 20, dtype=torch.uint8, device="cuda")
     ref = None
-    for _ in range(3):
-        out, cnt = cx.select(x, I32_MIN, 2 ** 30)
-        s = torch.sort(out[:int(cnt.item())])[0].cpu().numpy()
+    for _ in range(5):                       # the same scratch reused: the status words are cleared per call
+        out, cnt = cx.select(x, I32_MIN, 2 ** 30, stable=True, scratch=scratch)
+        s = out[:int(cnt.item())].cpu().numpy()
         ref = s if ref is None else ref
         assert np.array_equal(s, ref)
+    assert np.array_equal(ref, oracle.select(y, I32_MIN, 2 ** 30))
 
 
 # ----------------------------------------------------------------- project --
