@@ -58,12 +58,14 @@ typedef struct crystal_range {
 const char *crystal_status_string(int32_t status);
 
 /* ABI version of this header (incremented on any layout change). */
-#define CRYSTAL_ABI_VERSION 1
+#define CRYSTAL_ABI_VERSION 2
 int32_t crystal_abi_version(void);
 
 /* sizeof of the ABI structs as compiled into the library, so a binding can
  * check its own layout: 0 crystal_range, 1 crystal_ht, 2 crystal_pred,
- * 3 crystal_join, 4 crystal_star_query.  Returns 0 for any other value. */
+ * 3 crystal_join, 4 crystal_star_query, 5 crystal_qmask_table,
+ * 6 crystal_batch_query, 7 crystal_batch, 8 crystal_server_template,
+ * 9 crystal_server_config, 10 crystal_server_stats.  0 for any other value. */
 size_t crystal_struct_size(int32_t which);
 
 /* ------------------------------------------------------------------------ */
@@ -254,6 +256,119 @@ size_t crystal_star_query_scratch_bytes(const crystal_star_query *q);
 crystal_status crystal_run_star_query(const crystal_star_query *q, int64_t *out,
                                       int32_t *status, void *scratch, size_t scratch_bytes,
                                       void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Shared-scan batches: up to CRYSTAL_MAX_BATCH queries of one star-query    */
+/* template (same columns, predicate columns, joins, group spec, aggregate;  */
+/* each query with its own predicate constants and dimension filters) are    */
+/* answered in one pass over a range of fact rows.  Each fact column is read */
+/* once per pass and each join costs one 2-byte lookup per row, in the       */
+/* batch's query-mask table of that dimension (bit q of entry k: the         */
+/* dimension row with key k passes query q's dimension filter).  This is an  */
+/* extension of the paper's single-query kernels for serving many queries.   */
+/* ------------------------------------------------------------------------ */
+#define CRYSTAL_MAX_BATCH 16
+
+typedef struct crystal_qmask_table {
+    void *mem;         /* device memory of crystal_qmask_bytes(span) bytes (caller-owned) */
+    int64_t span;      /* keys key_min .. key_min + span - 1                          */
+    int32_t key_min;
+    int32_t reserved;
+} crystal_qmask_table;
+
+size_t crystal_qmask_bytes(int64_t span);
+
+/* Clear the table, then for every dimension row i < n with key keys[i] set bit
+ * q of the key's entry when filter_col[i] lies in ranges[q] (q < n_queries;
+ * every row passes when filter_col is NULL).  ranges: HOST array.  A key
+ * outside the span sets CRYSTAL_ERANGE in *status. */
+crystal_status crystal_qmask_build(const crystal_qmask_table *t, const int32_t *keys,
+                                   const int32_t *filter_col, int64_t n,
+                                   const crystal_range *ranges, int32_t n_queries,
+                                   int32_t *status, void *stream);
+
+typedef struct crystal_batch_query {
+    crystal_range preds[CRYSTAL_MAX_PREDS]; /* this query's fact-predicate ranges, plan order */
+    int64_t *out;                           /* device, n_groups int64, ACCUMULATED (not cleared) */
+} crystal_batch_query;
+
+typedef struct crystal_batch {
+    crystal_star_query plan;                    /* template; its predicate ranges are ignored and
+                                                   its joins' tables are used for group payloads */
+    crystal_qmask_table masks[CRYSTAL_MAX_JOINS]; /* per join, built for this batch's queries */
+    int32_t n_queries;                          /* 1 .. CRYSTAL_MAX_BATCH (0: nothing to do) */
+    int32_t reserved;
+    crystal_batch_query queries[CRYSTAL_MAX_BATCH];
+    int64_t row_begin;                          /* fact rows [row_begin, row_end); row_begin % 4 == 0 */
+    int64_t row_end;
+} crystal_batch;
+
+/* One pass over rows [row_begin, row_end) for every query of the batch,
+ * adding into each query's output.  Query q's answer over a row range is the
+ * plain star query's answer restricted to those rows, so launches over a
+ * partition of the fact table accumulate the full answer. */
+crystal_status crystal_run_shared_scan(const crystal_batch *b, int32_t *status, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Serving: continuous batching of star queries over shared-scan passes.     */
+/* The fact table is cut into segments of segment_rows rows; a server       */
+/* thread runs a clock whose every step scans the next segment once per     */
+/* template for all queries in that template's slots (crystal_run_shared_   */
+/* scan, outputs accumulated per slot).  A query admitted at step p is done */
+/* after one full cycle of segments; its slot output is copied to pinned    */
+/* host memory and the slot is reused.  Requests that arrive while others   */
+/* run wait in a FIFO per template (at most max_queue; beyond that submit   */
+/* returns CRYSTAL_EBUSY) and are admitted into free slots at the next      */
+/* step.  Slot memory is the admission budget: the workspace holds          */
+/* slots_per_template outputs per template.                                  */
+/* ------------------------------------------------------------------------ */
+#define CRYSTAL_SERVER_MAX_TEMPLATES 4
+
+typedef struct crystal_server_template {
+    crystal_star_query plan;                      /* template plan over the one fact table      */
+    const int32_t *dim_keys[CRYSTAL_MAX_JOINS];   /* per join: dimension key column (device)    */
+    const int32_t *dim_filter[CRYSTAL_MAX_JOINS]; /* per join: dimension filter column (device) */
+    int64_t dim_rows[CRYSTAL_MAX_JOINS];
+    crystal_qmask_table masks[CRYSTAL_MAX_JOINS]; /* per join: mask-table memory (caller-owned) */
+} crystal_server_template;
+
+typedef struct crystal_server_config {
+    int32_t n_templates;          /* 1 .. CRYSTAL_SERVER_MAX_TEMPLATES                         */
+    int32_t slots_per_template;   /* 1 .. CRYSTAL_MAX_BATCH concurrent queries per template     */
+    int64_t segment_rows;         /* rows per clock step, a multiple of 4                       */
+    int32_t max_queue;            /* waiting requests per template                              */
+    int32_t inflight_steps;       /* steps issued ahead of the oldest unfinished one (1 .. 64)  */
+    void *workspace;              /* device, >= crystal_server_workspace_bytes(), 16-byte aligned */
+    size_t workspace_bytes;
+    void *stream;                 /* hipStream_t to launch on; NULL: the server creates one     */
+    int32_t fake_executor;        /* 1: no GPU work, every step takes fake_step_ns (tests)      */
+    int32_t reserved;
+    int64_t fake_step_ns;
+    crystal_server_template templates[CRYSTAL_SERVER_MAX_TEMPLATES];
+} crystal_server_config;
+
+typedef struct crystal_server_stats {
+    int64_t admitted, completed, rejected, queued, steps, busy_slot_steps, n_segments;
+} crystal_server_stats;
+
+typedef struct crystal_server crystal_server;
+
+size_t crystal_server_workspace_bytes(const crystal_server_config *cfg);
+/* Validates the configuration, starts the server thread. */
+crystal_status crystal_server_create(const crystal_server_config *cfg, crystal_server **out);
+/* Queue one query of template_id with its constants: preds[i] for the
+ * template's fact predicates, dim_filters[j] for its joins' dimension filter
+ * columns (host arrays).  Returns a ticket. */
+crystal_status crystal_server_submit(crystal_server *s, int32_t template_id, const crystal_range *preds,
+                                     const crystal_range *dim_filters, int64_t *ticket);
+/* *done = 1 once the query has finished; then its n_groups int64 result is
+ * copied into `result` (host, may be NULL), *latency_ns is the time from
+ * submit to completion, and the ticket is released. */
+crystal_status crystal_server_poll(crystal_server *s, int64_t ticket, int64_t *result, int32_t *done,
+                                   int64_t *latency_ns);
+crystal_status crystal_server_get_stats(crystal_server *s, crystal_server_stats *out);
+/* Stops the thread after the work on the GPU has drained; frees the server. */
+crystal_status crystal_server_destroy(crystal_server *s);
 
 /* ------------------------------------------------------------------------ */
 /* Tile-size tuning (section 3.3: the tile is BLOCK threads x IPT items per */

@@ -130,8 +130,9 @@ def main(argv=None):
         o = torch.empty(n, dtype=torch.int32, device="cuda")
         c = torch.empty(1, dtype=torch.int64, device="cuda")
         cands = [(128, 4), (256, 4), (256, 8), (256, 16), (512, 8), (512, 16), (1024, 8)] if args.quick else None
+        # one workgroup per tile always (grid_per_cu does not apply to selection)
         rows = sweep(cx.K_SELECT, n, lambda: cx.select(x, lo, hi, out=o, count=c), lambda: c.cpu().numpy(),
-                     candidates=cands, gpcs=(0, 2, 4), reps=args.reps, log=log)
+                     candidates=cands, gpcs=(0,), reps=args.reps, log=log)
         assign(cx.K_SELECT, [(n, rows[0][1:])])
         report["select_2^29"] = rows[:8]
         del x, o

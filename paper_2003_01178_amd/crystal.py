@@ -51,6 +51,43 @@ class StarQueryC(ctypes.Structure):
                 ("agg_col1", c_i32), ("n_groups", c_i64), ("joins", Join * MAX_JOINS)]
 
 
+MAX_BATCH = 16
+
+
+class QmaskTableC(ctypes.Structure):
+    _fields_ = [("mem", c_vp), ("span", c_i64), ("key_min", c_i32), ("reserved", c_i32)]
+
+
+class BatchQueryC(ctypes.Structure):
+    _fields_ = [("preds", Range * MAX_PREDS), ("out", c_vp)]
+
+
+class BatchC(ctypes.Structure):
+    _fields_ = [("plan", StarQueryC), ("masks", QmaskTableC * MAX_JOINS), ("n_queries", c_i32),
+                ("reserved", c_i32), ("queries", BatchQueryC * MAX_BATCH), ("row_begin", c_i64),
+                ("row_end", c_i64)]
+
+
+MAX_TEMPLATES = 4
+
+
+class ServerTemplateC(ctypes.Structure):
+    _fields_ = [("plan", StarQueryC), ("dim_keys", c_vp * MAX_JOINS), ("dim_filter", c_vp * MAX_JOINS),
+                ("dim_rows", c_i64 * MAX_JOINS), ("masks", QmaskTableC * MAX_JOINS)]
+
+
+class ServerConfigC(ctypes.Structure):
+    _fields_ = [("n_templates", c_i32), ("slots_per_template", c_i32), ("segment_rows", c_i64),
+                ("max_queue", c_i32), ("inflight_steps", c_i32), ("workspace", c_vp),
+                ("workspace_bytes", ctypes.c_size_t), ("stream", c_vp), ("fake_executor", c_i32),
+                ("reserved", c_i32), ("fake_step_ns", c_i64), ("templates", ServerTemplateC * MAX_TEMPLATES)]
+
+
+class ServerStatsC(ctypes.Structure):
+    _fields_ = [(k, c_i64) for k in ("admitted", "completed", "rejected", "queued", "steps", "busy_slot_steps",
+                                      "n_segments")]
+
+
 class CrystalError(RuntimeError):
     def __init__(self, code, what=""):
         super().__init__(f"{what}: {status_string(code)} ({code})" if what else status_string(code))
@@ -78,6 +115,15 @@ def _declare(lib):
         "crystal_groupby_agg": (c_i32, [c_vp, c_vp, c_i64, c_i64, c_vp, c_vp, c_vp]),
         "crystal_star_query_scratch_bytes": (ctypes.c_size_t, [P(StarQueryC)]),
         "crystal_run_star_query": (c_i32, [P(StarQueryC), c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp]),
+        "crystal_qmask_bytes": (ctypes.c_size_t, [c_i64]),
+        "crystal_qmask_build": (c_i32, [P(QmaskTableC), c_vp, c_vp, c_i64, P(Range), c_i32, c_vp, c_vp]),
+        "crystal_run_shared_scan": (c_i32, [P(BatchC), c_vp, c_vp]),
+        "crystal_server_workspace_bytes": (ctypes.c_size_t, [P(ServerConfigC)]),
+        "crystal_server_create": (c_i32, [P(ServerConfigC), P(c_vp)]),
+        "crystal_server_submit": (c_i32, [c_vp, c_i32, P(Range), P(Range), P(c_i64)]),
+        "crystal_server_poll": (c_i32, [c_vp, c_i64, c_vp, P(c_i32), P(c_i64)]),
+        "crystal_server_get_stats": (c_i32, [c_vp, P(ServerStatsC)]),
+        "crystal_server_destroy": (c_i32, [c_vp]),
         "crystal_tune_variants": (c_i32, [c_i32, P(c_i32), P(c_i32), c_i32]),
         "crystal_tune_set": (c_i32, [c_i32, c_i32, c_i32, c_i32, c_i32, c_i32]),
         "crystal_tune_get": (c_i32, [c_i32, c_i64, P(c_i32), P(c_i32), P(c_i32)]),
@@ -104,7 +150,8 @@ def load(path: str = LIB_PATH):
         except Exception as e:  # pragma: no cover - depends on the toolchain
             raise ImportError(f"libcrystal.so is missing and could not be built: {e}") from e
     lib = _declare(ctypes.CDLL(path))
-    for which, ty in enumerate((Range, HT, Pred, Join, StarQueryC)):
+    for which, ty in enumerate((Range, HT, Pred, Join, StarQueryC, QmaskTableC, BatchQueryC, BatchC,
+                                ServerTemplateC, ServerConfigC, ServerStatsC)):
         if lib.crystal_struct_size(which) != ctypes.sizeof(ty):
             raise ImportError(f"ABI layout mismatch for {ty.__name__}")
     _lib = lib
@@ -303,6 +350,159 @@ class StarQuery:
         _check(lib.crystal_run_star_query(ctypes.byref(self.c), _ptr(out), _ptr(status), _ptr(self.scratch),
                                           self.scratch_bytes, _stream(stream)), "crystal_run_star_query")
         return out, status
+
+
+# ----------------------------------------------------------- shared scan --
+class QueryMask:
+    """Query-mask table of one dimension for a shared-scan batch."""
+
+    def __init__(self, key_min, key_max, device="cuda"):
+        lib = load()
+        self.c = QmaskTableC()
+        self.c.span = int(key_max) - int(key_min) + 1
+        self.c.key_min = int(key_min)
+        nbytes = lib.crystal_qmask_bytes(self.c.span)
+        self.mem = torch.empty(max(16, nbytes), dtype=torch.uint8, device=device)
+        self.c.mem = self.mem.data_ptr()
+
+    def build(self, keys, filter_col, ranges, status=None, stream=None):
+        """Bit q of key k: the dimension row with key k has filter_col in ranges[q]."""
+        lib = load()
+        if filter_col is not None and filter_col.numel() != keys.numel():
+            raise ValueError("filter column and keys differ in length")
+        status = new_status(keys.device) if status is None else status
+        rs = (Range * max(1, len(ranges)))(*[Range(int(lo), int(hi)) for lo, hi in ranges])
+        _check(lib.crystal_qmask_build(ctypes.byref(self.c), _col(keys),
+                                       _col(filter_col) if filter_col is not None else None, keys.numel(),
+                                       rs, len(ranges), _ptr(status), _stream(stream)), "crystal_qmask_build")
+        return status
+
+
+class SharedScan:
+    """A shared-scan batch over a template plan (a StarQuery)."""
+
+    def __init__(self, template, masks):
+        if len(masks) != template.c.n_joins:
+            raise ValueError("one query-mask table per join")
+        self.template, self.masks = template, list(masks)
+        self.c = BatchC()
+        self.c.plan = template.c
+        for j, m in enumerate(masks):
+            self.c.masks[j] = m.c
+
+    def run(self, preds, outs, row_begin=0, row_end=None, status=None, stream=None):
+        """preds[q]: the query's fact-predicate ranges; outs[q]: its int64
+        output (accumulated into).  Rows [row_begin, row_end)."""
+        lib = load()
+        if len(preds) != len(outs) or len(outs) > MAX_BATCH:
+            raise ValueError("one output per query, at most 16 queries")
+        c = self.c
+        c.n_queries = len(outs)
+        for q, (pr, o) in enumerate(zip(preds, outs)):
+            if o.dtype != torch.int64 or o.numel() < self.template.n_groups:
+                raise ValueError("each output holds n_groups int64")
+            bq = BatchQueryC()
+            for i, (lo, hi) in enumerate(pr):
+                bq.preds[i] = Range(int(lo), int(hi))
+            bq.out = o.data_ptr()
+            c.queries[q] = bq
+        c.row_begin = int(row_begin)
+        c.row_end = int(self.template.n_rows if row_end is None else row_end)
+        dev = outs[0].device if outs else "cuda"
+        status = new_status(dev) if status is None else status
+        _check(lib.crystal_run_shared_scan(ctypes.byref(c), _ptr(status), _stream(stream)), "crystal_run_shared_scan")
+        return status
+
+
+# ----------------------------------------------------------------- server --
+class Server:
+    """Continuous-batching server over shared-scan passes (crystal_server_*).
+
+    templates: list of dicts with ``plan`` (a StarQuery or a raw StarQueryC)
+    and, per join, ``dims``: (keys, filter, n_rows, QueryMask) -- device
+    columns and the mask-table memory of that dimension.
+    """
+
+    def __init__(self, templates, slots=16, segment_rows=1 << 24, max_queue=1 << 16, inflight=2, stream=None,
+                 fake_step_ns=0, device="cuda"):
+        lib = load()
+        cfg = ServerConfigC()
+        cfg.n_templates = len(templates)
+        cfg.slots_per_template = int(slots)
+        cfg.segment_rows = int(segment_rows)
+        cfg.max_queue = int(max_queue)
+        cfg.inflight_steps = int(inflight)
+        cfg.fake_executor = 1 if fake_step_ns else 0
+        cfg.fake_step_ns = int(fake_step_ns)
+        self.keep = []
+        self.n_groups, self.n_preds, self.n_joins = [], [], []
+        for t, tp in enumerate(templates):
+            plan = tp["plan"]
+            pc = plan.c if hasattr(plan, "c") else plan
+            self.keep.append(plan)
+            st = ServerTemplateC()
+            st.plan = pc
+            for j, (keys, filt, rows, qm) in enumerate(tp.get("dims", [])):
+                st.dim_keys[j] = keys.data_ptr() if hasattr(keys, "data_ptr") else keys
+                st.dim_filter[j] = filt.data_ptr() if hasattr(filt, "data_ptr") else filt
+                st.dim_rows[j] = int(rows)
+                st.masks[j] = qm.c if hasattr(qm, "c") else qm
+                self.keep.append((keys, filt, qm))
+            cfg.templates[t] = st
+            self.n_groups.append(int(pc.n_groups))
+            self.n_preds.append(int(pc.n_preds))
+            self.n_joins.append(int(pc.n_joins))
+        nbytes = lib.crystal_server_workspace_bytes(ctypes.byref(cfg))
+        if not cfg.fake_executor:
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
+            cfg.workspace = self.workspace.data_ptr()
+            cfg.workspace_bytes = nbytes
+            if stream is not None:
+                cfg.stream = stream.cuda_stream
+                self.stream = stream
+        self.cfg = cfg
+        h = c_vp()
+        _check(lib.crystal_server_create(ctypes.byref(cfg), ctypes.byref(h)), "crystal_server_create")
+        self.h = h
+
+    def submit(self, template_id, preds=(), filters=()):
+        """Returns a ticket, or None when the template's queue is full."""
+        lib = load()
+        pr = (Range * MAX_PREDS)(*[Range(int(a), int(b)) for a, b in preds])
+        fr = (Range * MAX_JOINS)(*[Range(int(a), int(b)) for a, b in filters])
+        tk = c_i64()
+        rc = lib.crystal_server_submit(self.h, int(template_id), pr, fr, ctypes.byref(tk))
+        if rc == EBUSY:
+            return None
+        _check(rc, "crystal_server_submit")
+        return tk.value
+
+    def poll(self, ticket, template_id):
+        """(done, result int64 array or None, latency_ns)."""
+        import numpy as np
+        lib = load()
+        out = np.zeros(self.n_groups[template_id], dtype=np.int64)
+        done, lat = c_i32(), c_i64()
+        _check(lib.crystal_server_poll(self.h, int(ticket), out.ctypes.data_as(c_vp), ctypes.byref(done),
+                                       ctypes.byref(lat)), "crystal_server_poll")
+        return (True, out, lat.value) if done.value else (False, None, 0)
+
+    def stats(self):
+        st = ServerStatsC()
+        _check(load().crystal_server_get_stats(self.h, ctypes.byref(st)), "crystal_server_get_stats")
+        return {k: getattr(st, k) for k, _ in ServerStatsC._fields_}
+
+    def close(self):
+        if self.h:
+            rc = load().crystal_server_destroy(self.h)
+            self.h = None
+            _check(rc, "crystal_server_destroy")
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ----------------------------------------------------------------- tuning --

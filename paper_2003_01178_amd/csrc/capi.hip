@@ -75,7 +75,7 @@ static LaunchCfg default_cfg(int kernel) {
     case CRYSTAL_K_HT_PROBE: return {256, 16, 8};
     case CRYSTAL_K_GROUPBY: return {256, 16, 0};
     case CRYSTAL_K_STAR: return {256, 16, 0};
-    case CRYSTAL_K_SHARED_SCAN: return {256, 16, 4};
+    case CRYSTAL_K_SHARED_SCAN: return {256, 8, 0};
     default: return {256, 16, 0};
     }
 }
@@ -226,6 +226,12 @@ size_t crystal_struct_size(int32_t which) {
     case 2: return sizeof(crystal_pred);
     case 3: return sizeof(crystal_join);
     case 4: return sizeof(crystal_star_query);
+    case 5: return sizeof(crystal_qmask_table);
+    case 6: return sizeof(crystal_batch_query);
+    case 7: return sizeof(crystal_batch);
+    case 8: return sizeof(crystal_server_template);
+    case 9: return sizeof(crystal_server_config);
+    case 10: return sizeof(crystal_server_stats);
     default: return 0;
     }
 }
@@ -351,6 +357,59 @@ crystal_status crystal_run_star_query(const crystal_star_query *q, int64_t *out,
     }
     return from_hip(launch_star(tune_lookup(CRYSTAL_K_STAR, q->n_rows), d, (uint64_t *)out, status,
                                 (uint64_t *)scratch, as_stream(stream)));
+}
+
+// ------------------------------------------------------------ shared scan --
+size_t crystal_qmask_bytes(int64_t span) {
+    if (span <= 0) return 0;
+    return (size_t)((span + 1) / 2) * 4;
+}
+
+crystal_status crystal_qmask_build(const crystal_qmask_table *t, const int32_t *keys, const int32_t *filter_col,
+                                   int64_t n, const crystal_range *ranges, int32_t n_queries, int32_t *status,
+                                   void *stream) {
+    if (!t || !t->mem || !aligned16(t->mem) || t->span <= 0 || t->span > (int64_t(1) << 32) || n < 0 ||
+        (n > 0 && !keys) || n_queries < 0 || n_queries > CRYSTAL_MAX_BATCH || (n_queries > 0 && !ranges) ||
+        !status)
+        return CRYSTAL_EINVAL;
+    QmaskRanges r = {};
+    r.n = n_queries;
+    for (int q = 0; q < n_queries; ++q) {
+        r.lo[q] = ranges[q].lo;
+        r.hi[q] = ranges[q].hi;
+    }
+    return from_hip(launch_qmask_build((uint16_t *)t->mem, t->span, t->key_min, keys, filter_col, n, r, status,
+                                       as_stream(stream)));
+}
+
+crystal_status crystal_run_shared_scan(const crystal_batch *b, int32_t *status, void *stream) {
+    if (!b || !status || b->n_queries < 0 || b->n_queries > CRYSTAL_MAX_BATCH) return CRYSTAL_EINVAL;
+    BatchDev d;
+    memset(&d, 0, sizeof(d));
+    crystal_status st = star_plan_to_dev(b->plan, d.plan);
+    if (st != CRYSTAL_OK) return st;
+    if (b->row_begin < 0 || b->row_end > b->plan.n_rows || (b->row_begin & 3)) return CRYSTAL_EINVAL;
+    for (int j = 0; j < b->plan.n_joins; ++j) {
+        const crystal_qmask_table &m = b->masks[j];
+        if (!m.mem || !aligned16(m.mem) || m.span <= 0 || m.span > (int64_t(1) << 32)) return CRYSTAL_EINVAL;
+        d.mask[j] = (const uint16_t *)m.mem;
+        d.mask_span[j] = m.span;
+        d.mask_kmin[j] = m.key_min;
+    }
+    d.n_queries = b->n_queries;
+    d.all_queries = b->n_queries >= 32 ? 0xffffffffu : ((1u << b->n_queries) - 1u);
+    for (int q = 0; q < b->n_queries; ++q) {
+        if (!b->queries[q].out) return CRYSTAL_EINVAL;
+        d.out[q] = (uint64_t *)b->queries[q].out;
+        for (int i = 0; i < b->plan.n_preds; ++i) {
+            d.pred_lo[q][i] = b->queries[q].preds[i].lo;
+            d.pred_hi[q][i] = b->queries[q].preds[i].hi;
+        }
+    }
+    d.row_begin = b->row_begin;
+    d.row_end = b->row_end;
+    return from_hip(launch_shared_scan(tune_lookup(CRYSTAL_K_SHARED_SCAN, b->row_end - b->row_begin), d, status,
+                                       as_stream(stream)));
 }
 
 // ----------------------------------------------------------------- tuning --

@@ -112,6 +112,34 @@ constexpr int kStarMaxGridPerCu = 32;
 int64_t star_max_grid(int64_t n_rows);
 
 crystal_status star_plan_to_dev(const crystal_star_query &q, StarPlanDev &d);
+
+// ----------------------------------------------------------- shared scan --
+constexpr int kMaxBatch = CRYSTAL_MAX_BATCH;
+
+struct QmaskRanges {
+    int32_t n;
+    int32_t lo[kMaxBatch];
+    int32_t hi[kMaxBatch];
+};
+
+struct BatchDev {
+    StarPlanDev plan;                          // the template
+    const uint16_t *mask[CRYSTAL_MAX_JOINS];   // per join: the batch's query-mask table
+    int64_t mask_span[CRYSTAL_MAX_JOINS];
+    int32_t mask_kmin[CRYSTAL_MAX_JOINS];
+    int32_t n_queries;
+    uint32_t all_queries;                      // (1 << n_queries) - 1
+    int32_t pred_lo[kMaxBatch][CRYSTAL_MAX_PREDS];
+    int32_t pred_hi[kMaxBatch][CRYSTAL_MAX_PREDS];
+    uint64_t *out[kMaxBatch];
+    int64_t row_begin;
+    int64_t row_end;
+};
+
+hipError_t launch_qmask_build(uint16_t *table, int64_t span, int32_t key_min, const int32_t *keys,
+                              const int32_t *filter_col, int64_t n, const QmaskRanges &r, int32_t *status,
+                              hipStream_t s);
+hipError_t launch_shared_scan(const LaunchCfg &cfg, const BatchDev &b, int32_t *status, hipStream_t s);
 hipError_t launch_star(const LaunchCfg &cfg, const StarPlanDev &plan, uint64_t *out,
                        int32_t *status, uint64_t *partials, hipStream_t s);
 

@@ -9,6 +9,11 @@
   them in plan order and adds SUM(m1) into a dense group array indexed by
   (year - 1992) * 1000 + dim3.group.
 
+* ``ServingTemplates`` -- the shared-scan forms of both shapes over one fact
+  table (the star schema plus the Q1.1 columns): unfiltered dimension tables
+  that carry the group payloads, one query-mask table per dimension, and
+  batches of up to 16 queries that differ only in their constants.
+
 Only plan construction lives here; every step runs in the library's kernels.
 """
 from __future__ import annotations
@@ -90,3 +95,82 @@ class StarSchema:
             joins.append(jj)
         return cx.StarQuery(self.fact_cols, n_groups=STAR_GROUPS, joins=joins,
                             agg=cx.AGG_SUM, agg_cols=(4, 0))
+
+
+# ------------------------------------------------------------ serving forms --
+Q11_COLS = ("discount", "quantity", "price")
+
+
+class ServingTemplates:
+    """Star-schema fact table with the Q1.1 columns, and the two query templates.
+
+    Fact columns: 0-3 the foreign keys (0 = date key), 4-5 the measures,
+    6 discount, 7 quantity, 8 price.
+    """
+
+    STAR, Q11 = 0, 1
+
+    def __init__(self, schema: StarSchema):
+        if not all(k in schema.extra for k in Q11_COLS):
+            raise ValueError("the fact table needs the Q1.1 columns")
+        self.s = schema
+        dev = schema.device
+        self.cols = [*schema.fk, schema.m1, schema.m2, *[schema.extra[k] for k in Q11_COLS]]
+        # unfiltered dimension tables: presence plus the group payloads
+        self.tables = []
+        self.status = cx.new_status(dev)
+        for j, d in enumerate(schema.dims):
+            payload = d["year"] if j == 0 else (d["group"] if j == 2 else None)
+            ht = cx.HashTable(cx.HT_DIRECT, d["n"], d["key_min"], d["key_max"], has_payload=payload is not None,
+                              device=dev)
+            ht.build(d["key"], payload=payload, status=self.status)
+            self.tables.append(ht)
+        self.masks = [cx.QueryMask(d["key_min"], d["key_max"], device=dev) for d in schema.dims]
+        joins = []
+        for j in DEFAULT_JOIN_ORDER:
+            jj = dict(table=self.tables[j], fk_col=j)
+            if j == 0:
+                jj["group"] = (32, 0, datagen.FIRST_YEAR, GROUPS_PER_YEAR)
+            if j == 2:
+                jj["group"] = (32, 0, 0, 1)
+            joins.append(jj)
+        self.star_template = cx.StarQuery(self.cols, n_groups=STAR_GROUPS, joins=joins, agg=cx.AGG_SUM,
+                                          agg_cols=(4, 0))
+        self.star_scan = cx.SharedScan(self.star_template, [self.masks[j] for j in DEFAULT_JOIN_ORDER])
+        self.q11_template = cx.StarQuery(self.cols, n_groups=1,
+                                         preds=[(0, 0, 0), (6, 0, 0), (7, 0, 0)],
+                                         agg=cx.AGG_SUM_PRODUCT, agg_cols=(8, 6))
+        self.q11_scan = cx.SharedScan(self.q11_template, [])
+
+    @property
+    def n_rows(self):
+        return self.s.n
+
+    def build_star_masks(self, consts_per_query, stream=None):
+        """Dimension j of query q keeps rows with filter == consts_per_query[q][j]."""
+        for j, d in enumerate(self.s.dims):
+            self.masks[j].build(d["key"], d["filter"], [(c[j], c[j]) for c in consts_per_query],
+                                status=self.status, stream=stream)
+
+    @staticmethod
+    def q11_preds(year, disc_lo, qty_max):
+        lo, hi = datagen.q11_year_range(year)
+        return [(lo, hi), (disc_lo, disc_lo + 2), (cx.I32_MIN, qty_max)]
+
+    def run_star_batch(self, outs, row_begin=0, row_end=None, status=None, stream=None):
+        return self.star_scan.run([[] for _ in outs], outs, row_begin, row_end, status=status, stream=stream)
+
+    def run_q11_batch(self, consts, outs, row_begin=0, row_end=None, status=None, stream=None):
+        preds = [self.q11_preds(*c) for c in consts]
+        return self.q11_scan.run(preds, outs, row_begin, row_end, status=status, stream=stream)
+
+    def single_star(self, consts):
+        """The same star query as one plain launch (filtered builds)."""
+        self.s.build(consts)
+        return self.s.plan().run()[0]
+
+    def single_q11(self, year, disc_lo, qty_max):
+        preds = self.q11_preds(year, disc_lo, qty_max)
+        q = cx.StarQuery(self.cols, n_groups=1, preds=[(0, *preds[0]), (6, *preds[1]), (7, *preds[2])],
+                         agg=cx.AGG_SUM_PRODUCT, agg_cols=(8, 6))
+        return q.run()[0]

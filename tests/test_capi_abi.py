@@ -34,8 +34,10 @@ def test_every_declared_symbol_is_exported(cx):
 
 def test_struct_layout_matches_binding(cx):
     lib = cx.load()
-    assert lib.crystal_abi_version() == 1
-    for which, ty in enumerate((cx.Range, cx.HT, cx.Pred, cx.Join, cx.StarQueryC)):
+    assert lib.crystal_abi_version() == 2
+    for which, ty in enumerate((cx.Range, cx.HT, cx.Pred, cx.Join, cx.StarQueryC, cx.QmaskTableC,
+                                cx.BatchQueryC, cx.BatchC, cx.ServerTemplateC, cx.ServerConfigC,
+                                cx.ServerStatsC)):
         assert lib.crystal_struct_size(which) == ctypes.sizeof(ty), ty.__name__
     assert lib.crystal_struct_size(99) == 0
 
