@@ -33,7 +33,7 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=5)
-    p.add_argument("--workload", default="star", choices=["star", "q11", "select", "project", "join", "copy"])
+    p.add_argument("--workload", default="star", choices=["star", "q11", "select", "project", "join", "copy", "serve"])
     p.add_argument("--rows", type=int, default=0, help="override the fact/column length")
     p.add_argument("--sigma", type=float, default=0.5, help="select selectivity")
     p.add_argument("--dim", type=int, default=1 << 20, help="join build size D")
@@ -42,6 +42,9 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
     p.add_argument("--tune", default="", help="kernel block,ipt,grid_per_cu override, e.g. 256,16,0")
+    p.add_argument("--rates", default="200,500,1000,2000", help="serve: Poisson arrival rates (q/s)")
+    p.add_argument("--seconds", type=float, default=3.0, help="serve: arrival window per rate")
+    p.add_argument("--segments", type=int, default=8, help="serve: clock segments of the fact table")
     return p.parse_args()
 
 
@@ -108,6 +111,109 @@ class Timer:
         return float(np.mean([s.elapsed_time(e) for s, e in self.pairs])) if self.pairs else 0.0
 
 
+def serve(args, torch, cx, datagen, queries, roof):
+    """Served mixed workload: Poisson arrivals of star-template and Q1.1-template
+    queries with seeded constants, answered by the continuous-batching server
+    over shared-scan passes; compared with one launch per query."""
+    n = args.rows or 600_000_000
+    t0 = time.time()
+    t = datagen.star_tables(n=n, workload=4, with_q11_columns=True)
+    print(f"# generated {n} fact rows x 9 columns in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    sv = queries.ServingTemplates(queries.StarSchema(t))
+    del t
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(2003)
+
+    def draw(k):
+        if k % 2 == 0:
+            return 0, datagen.random_star_constants(rng)
+        return 1, datagen.random_q11_constants(rng)
+
+    # one launch per query (filtered builds + fused kernel, or the Q1.1 kernel)
+    single = []
+    t0 = time.perf_counter()
+    for k in range(64):
+        tp, c = draw(k)
+        r = sv.single_star(c) if tp == 0 else sv.single_q11(*c)
+        single.append((tp, c, r))
+    torch.cuda.synchronize()
+    single_qps = 64 / (time.perf_counter() - t0)
+    seg = (n // args.segments + 3) // 4 * 4
+    order = queries.DEFAULT_JOIN_ORDER
+    d = sv.s.dims
+    star = dict(plan=sv.star_template, dims=[(d[j]["key"], d[j]["filter"], d[j]["n"], sv.masks[j]) for j in order])
+    srv = cx.Server([star, dict(plan=sv.q11_template)], slots=16, segment_rows=seg, max_queue=1 << 16, inflight=2)
+    per_rate = []
+    checks = mismatches = 0
+    try:
+        for rate in [float(x) for x in args.rates.split(",")]:
+            arrivals = np.cumsum(rng.exponential(1.0 / rate, size=int(rate * args.seconds * 1.2) + 8))
+            arrivals = arrivals[arrivals < args.seconds]
+            pending, lat, submitted = {}, [], 0
+            st0 = srv.stats()
+            start = time.perf_counter()
+            i = 0
+            while i < len(arrivals) or pending:
+                now = time.perf_counter() - start
+                while i < len(arrivals) and arrivals[i] <= now:
+                    tp, c = draw(i)
+                    if tp == 0:
+                        tk = srv.submit(0, filters=[(c[j], c[j]) for j in order])
+                    else:
+                        tk = srv.submit(1, preds=sv.q11_preds(*c))
+                    if tk is not None:
+                        pending[tk] = (tp, c)
+                        submitted += 1
+                    i += 1
+                for tk in list(pending):
+                    tp, c = pending[tk]
+                    done, out, ns = srv.poll(tk, tp)
+                    if done:
+                        lat.append(ns / 1e6)
+                        del pending[tk]
+                        if checks < 48 and len(lat) % 7 == 1:
+                            want = sv.single_star(c).cpu().numpy() if tp == 0 else np.array(
+                                [int(sv.single_q11(*c).item())])
+                            checks += 1
+                            mismatches += int(not np.array_equal(out, want))
+                time.sleep(0.0002)
+            wall = time.perf_counter() - start
+            st1 = srv.stats()
+            steps = st1["steps"] - st0["steps"]
+            lat = np.array(lat)
+            per_rate.append({"offered_qps": rate, "served_qps": len(lat) / wall, "queries": int(len(lat)),
+                             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                             "clock_steps": int(steps),
+                             "mean_batch": (st1["busy_slot_steps"] - st0["busy_slot_steps"]) / max(1, steps)})
+            print(f"# rate {rate}: {per_rate[-1]}", file=sys.stderr, flush=True)
+        # saturation: a burst of 256 queries at once
+        tks = []
+        start = time.perf_counter()
+        for k in range(256):
+            tp, c = draw(k)
+            tk = srv.submit(0, filters=[(c[j], c[j]) for j in order]) if tp == 0 else srv.submit(
+                1, preds=sv.q11_preds(*c))
+            tks.append((tk, tp))
+        left = dict(tks)
+        while left:
+            for tk in list(left):
+                if srv.poll(tk, left[tk])[0]:
+                    del left[tk]
+            time.sleep(0.0002)
+        burst_qps = 256 / (time.perf_counter() - start)
+    finally:
+        srv.close()
+    best = max(per_rate, key=lambda r: r["served_qps"])
+    roof.update(kernel="crystal::shared_scan_kernel", achieved=0.0, kernel_ms=0.0)
+    return dict(metric="served queries/s + p99 latency (shared-scan continuous batching)",
+                value=burst_qps, unit="queries/s", ms_per_step=1e3 / burst_qps, dtype="int32",
+                config={"workload": f"served mix: fact {n} rows x 9 int32 columns, 50/50 star-join / Q1.1 "
+                                    "templates with seeded constants, Poisson arrivals",
+                        "segments": args.segments, "slots_per_template": 16},
+                serving={"rates": per_rate, "burst_256_qps": burst_qps, "single_launch_qps": single_qps,
+                         "checked_vs_single_launch": checks, "mismatches": mismatches})
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -122,8 +228,8 @@ def main():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(3)
     cx.load()
-    kernel_id = {"star": cx.K_STAR, "q11": cx.K_STAR, "select": cx.K_SELECT,
-                 "project": cx.K_PROJECT, "join": cx.K_HT_PROBE, "copy": cx.K_SELECT}[args.workload]
+    kernel_id = {"star": cx.K_STAR, "q11": cx.K_STAR, "select": cx.K_SELECT, "project": cx.K_PROJECT,
+                 "join": cx.K_HT_PROBE, "copy": cx.K_SELECT, "serve": cx.K_SHARED_SCAN}[args.workload]
     if args.tune:
         b, i, g = (int(x) for x in args.tune.split(","))
         cx.tune_set(kernel_id, b, i, g)
@@ -337,6 +443,9 @@ def main():
                       config={"workload": f"device copy of {n} int32 ({4 * n} bytes read, {4 * n} written)",
                               "rows": n})
         roof.update(kernel="copy", achieved=b / (kern_ms * 1e-3) / 1e9, algorithmic_bytes=b, kernel_ms=kern_ms)
+
+    elif args.workload == "serve":
+        result.update(serve(args, torch, cx, datagen, queries, roof))
 
     roof["frac"] = roof["achieved"] / roof["peak"]
     result["roofline"] = roof
