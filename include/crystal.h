@@ -371,6 +371,20 @@ crystal_status crystal_server_get_stats(crystal_server *s, crystal_server_stats 
 crystal_status crystal_server_destroy(crystal_server *s);
 
 /* ------------------------------------------------------------------------ */
+/* HIP graphs: record every crystal_* call made on `stream` between begin and */
+/* end (stream capture), then replay the whole launch sequence with one call. */
+/* The library clears outputs and tables with fill kernels, never memset     */
+/* nodes, so each replay recomputes every result from its inputs.  Pointers  */
+/* and plan constants are frozen at capture; make one eager call of each     */
+/* entry point on the device before capturing (it caches device attributes). */
+/* ------------------------------------------------------------------------ */
+typedef struct crystal_graph crystal_graph;
+crystal_status crystal_graph_begin(void *stream);
+crystal_status crystal_graph_end(void *stream, crystal_graph **out);
+crystal_status crystal_graph_launch(crystal_graph *g, void *stream);
+crystal_status crystal_graph_destroy(crystal_graph *g);
+
+/* ------------------------------------------------------------------------ */
 /* Tile-size tuning (section 3.3: the tile is BLOCK threads x IPT items per */
 /* thread; the best shape depends on the kernel and the input).  The table  */
 /* maps (kernel, size bucket = floor(log2 n)) to a compiled variant.  A     */

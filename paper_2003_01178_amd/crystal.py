@@ -124,6 +124,10 @@ def _declare(lib):
         "crystal_server_poll": (c_i32, [c_vp, c_i64, c_vp, P(c_i32), P(c_i64)]),
         "crystal_server_get_stats": (c_i32, [c_vp, P(ServerStatsC)]),
         "crystal_server_destroy": (c_i32, [c_vp]),
+        "crystal_graph_begin": (c_i32, [c_vp]),
+        "crystal_graph_end": (c_i32, [c_vp, P(c_vp)]),
+        "crystal_graph_launch": (c_i32, [c_vp, c_vp]),
+        "crystal_graph_destroy": (c_i32, [c_vp]),
         "crystal_tune_variants": (c_i32, [c_i32, P(c_i32), P(c_i32), c_i32]),
         "crystal_tune_set": (c_i32, [c_i32, c_i32, c_i32, c_i32, c_i32, c_i32]),
         "crystal_tune_get": (c_i32, [c_i32, c_i64, P(c_i32), P(c_i32), P(c_i32)]),
@@ -412,6 +416,50 @@ class SharedScan:
         status = new_status(dev) if status is None else status
         _check(lib.crystal_run_shared_scan(ctypes.byref(c), _ptr(status), _stream(stream)), "crystal_run_shared_scan")
         return status
+
+
+# ----------------------------------------------------------------- graphs --
+class Graph:
+    """Capture the crystal calls made on a (non-default) stream, replay them.
+
+    with Graph.capture(stream) as g: ...calls on `stream`...
+    g.launch(stream)
+    """
+
+    def __init__(self):
+        self.h = None
+
+    @classmethod
+    def capture(cls, stream):
+        g = cls()
+        g.stream = stream
+        return g
+
+    def __enter__(self):
+        _check(load().crystal_graph_begin(c_vp(self.stream.cuda_stream)), "crystal_graph_begin")
+        return self
+
+    def __exit__(self, exc_type, exc, tb):
+        h = c_vp()
+        rc = load().crystal_graph_end(c_vp(self.stream.cuda_stream), ctypes.byref(h))
+        if exc_type is None:
+            _check(rc, "crystal_graph_end")
+        self.h = h
+        return False
+
+    def launch(self, stream=None):
+        _check(load().crystal_graph_launch(self.h, _stream(stream or self.stream)), "crystal_graph_launch")
+
+    def close(self):
+        if self.h:
+            load().crystal_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ----------------------------------------------------------------- server --

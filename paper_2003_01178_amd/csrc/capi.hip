@@ -412,6 +412,44 @@ crystal_status crystal_run_shared_scan(const crystal_batch *b, int32_t *status, 
                                        as_stream(stream)));
 }
 
+// ----------------------------------------------------------------- graphs --
+struct crystal_graph {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+crystal_status crystal_graph_begin(void *stream) {
+    if (!stream) return CRYSTAL_EINVAL;  // the legacy default stream cannot be captured
+    return from_hip(hipStreamBeginCapture(as_stream(stream), hipStreamCaptureModeThreadLocal));
+}
+
+crystal_status crystal_graph_end(void *stream, crystal_graph **out) {
+    if (!stream || !out) return CRYSTAL_EINVAL;
+    *out = nullptr;
+    hipGraph_t g = nullptr;
+    if (hipStreamEndCapture(as_stream(stream), &g) != hipSuccess || !g) return CRYSTAL_EHIP;
+    hipGraphExec_t e = nullptr;
+    if (hipGraphInstantiate(&e, g, nullptr, nullptr, 0) != hipSuccess) {
+        hipGraphDestroy(g);
+        return CRYSTAL_EHIP;
+    }
+    *out = new crystal_graph{g, e};
+    return CRYSTAL_OK;
+}
+
+crystal_status crystal_graph_launch(crystal_graph *g, void *stream) {
+    if (!g) return CRYSTAL_EINVAL;
+    return from_hip(hipGraphLaunch(g->exec, as_stream(stream)));
+}
+
+crystal_status crystal_graph_destroy(crystal_graph *g) {
+    if (!g) return CRYSTAL_EINVAL;
+    hipError_t e1 = hipGraphExecDestroy(g->exec);
+    hipError_t e2 = hipGraphDestroy(g->graph);
+    delete g;
+    return (e1 == hipSuccess && e2 == hipSuccess) ? CRYSTAL_OK : CRYSTAL_EHIP;
+}
+
 // ----------------------------------------------------------------- tuning --
 int32_t crystal_tune_variants(int32_t kernel, int32_t *blocks, int32_t *ipts, int32_t max) {
     if (kernel < 0 || kernel >= CRYSTAL_K_COUNT) return 0;
