@@ -263,9 +263,12 @@ static hipError_t groupby_t(const LaunchCfg &cfg_in, const int32_t *g, const int
     const int64_t n_tiles = (n + T::ITEMS - 1) / T::ITEMS;
     LaunchCfg cfg = cfg_in;
     const int64_t lds = n_groups * 8;
-    // LDS partials pay off when every workgroup sees many rows per group
-    const bool part = lds <= device_lds_per_block() / 2 && n >= 64 * n_groups * (int64_t)device_cu_count();
-    if (part && cfg.grid_per_cu <= 0) cfg.grid_per_cu = 2;
+    // LDS partials cost one flush of n_groups atomics per workgroup instead
+    // of one atomic per row: worth it when rows outnumber those flushes
+    LaunchCfg pcfg = cfg;
+    if (pcfg.grid_per_cu <= 0) pcfg.grid_per_cu = 1;
+    const bool part = lds <= device_lds_per_block() / 2 && n >= 4 * grid_for(n_tiles, pcfg) * n_groups;
+    if (part) cfg = pcfg;
     const int64_t grid = grid_for(n_tiles, cfg);
     if (grid == 0) return hipSuccess;
     if (part) {
