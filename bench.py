@@ -91,6 +91,25 @@ def star_algorithmic_bytes(t, order, line=FETCH_BYTES):
     return total, int(alive.sum())
 
 
+def measured_traffic(order, n):
+    """HBM bytes per star-kernel launch from the committed rocprofv3 counter
+    record (FETCH_SIZE and WRITE_SIZE scaled by a plain copy), or None when
+    the record is missing, was taken on another workload, or the kernel
+    sources changed since."""
+    from paper_2003_01178_amd import rocprof_summary
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "star_kernel_120M_traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_hash") != rocprof_summary.source_hash():
+        return None
+    if rec.get("fact_rows", n) != n or rec.get("join_order", list(order)) != list(order):
+        return None
+    return rec.get("traffic_bytes")
+
+
 class Timer:
     """HIP events around one call on the current stream, averaged."""
 
@@ -287,6 +306,7 @@ def main():
         roof.update(kernel="crystal::star_kernel", achieved=alg_bytes / (kern_ms * 1e-3) / 1e9,
                     algorithmic_bytes=alg_bytes, bytes_per_row=alg_bytes / n, kernel_ms=kern_ms,
                     kernel_rows_per_s=n / (kern_ms * 1e-3))
+        roof["traffic"] = measured_traffic(order, n)
         if not args.no_cpu_baseline:
             import oracle
             from_cols = [*t.fk, t.m1, t.m2]
