@@ -13,8 +13,9 @@ import os
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_LIB = os.path.join(_HERE, "libcrystal.so")
 # CRYSTAL_LIB selects another build of the same library (e.g. a tuning experiment)
-LIB_PATH = os.environ.get("CRYSTAL_LIB", os.path.join(_HERE, "libcrystal.so"))
+LIB_PATH = os.environ.get("CRYSTAL_LIB", DEFAULT_LIB)
 
 OK, EINVAL, ESCRATCH, EFULL, EDUPKEY, EHIP, EBUSY, ERANGE = range(8)
 HT_LINEAR, HT_DIRECT = 0, 1
@@ -148,6 +149,8 @@ def load(path: str = LIB_PATH):
     if _lib is not None:
         return _lib
     if not os.path.exists(path):
+        if path != DEFAULT_LIB:
+            raise ImportError(f"{path} does not exist")
         try:
             from . import build as _build
             _build.build()

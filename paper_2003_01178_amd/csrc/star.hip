@@ -134,6 +134,36 @@ __device__ __forceinline__ uint32_t probe_staged_tile(const uint32_t *lds, int32
     return hit & ok;
 }
 
+// The LDS-staged presence test split in two, so that the registers holding
+// the keys are free (and can receive the next tile's loads) while the
+// ds_reads are in flight: begin() turns keys into word indices and bit
+// positions and issues the reads; end() tests the bits.
+template <int IPT>
+struct StagedProbe {
+    uint32_t word[IPT];
+    uint32_t bit[IPT];
+    uint32_t ok;
+    __device__ __forceinline__ void begin(const uint32_t *lds, int32_t stage_off, int32_t key_min, int64_t span,
+                                          const int32_t (&key)[IPT], uint32_t alive) {
+        const uint32_t last = (uint32_t)(span - 1);
+        ok = 0;
+#pragma unroll
+        for (int k = 0; k < IPT; ++k) {
+            const uint32_t off = (uint32_t)key[k] - (uint32_t)key_min;
+            const bool in = ((alive >> k) & 1u) && off <= last;
+            ok |= (uint32_t)in << k;
+            bit[k] = off & 31u;
+            word[k] = lds[stage_off + (in ? (off >> 5) : 0u)];
+        }
+    }
+    __device__ __forceinline__ uint32_t end() const {
+        uint32_t hit = 0;
+#pragma unroll
+        for (int k = 0; k < IPT; ++k) hit |= ((word[k] >> bit[k]) & 1u) << k;
+        return hit & ok;
+    }
+};
+
 // One dense step over a tile: a predicate, or a probe of the LDS-staged
 // bitmap (stage_off >= 0), a direct table or a linear-probing table.
 template <int IPT>
@@ -255,11 +285,20 @@ __global__ __launch_bounds__(BLOCK) void star_kernel(const StarPlanDev p, uint64
         uint32_t alive_n = 0;
         if (has_nxt) {
             alive_n = valid_mask<BLOCK, IPT>(t_nxt * T::ITEMS, p.n_rows);
-            if (dense >= 1) alive_n = star_step_tile<IPT>(p, 0, lds, so0, an, alive_n);
-            if (dense >= 2) block_load_sel<BLOCK, IPT, true>(p.cols[col1], t_nxt * T::ITEMS, p.n_rows, alive_n, bn);
             const int64_t t_pf = t_nxt + PF * stride;
-            if (dense >= 1 && t_pf < n_tiles)
-                block_load<BLOCK, IPT, true>(p.cols[col0], t_pf * T::ITEMS, p.n_rows, an);
+            if (dense >= 1 && so0 >= 0) {
+                // staged first step: issue its LDS reads, then reuse the key
+                // registers for the prefetch before testing the bits
+                StagedProbe<IPT> pr;
+                pr.begin(lds, so0, p.joins[0].key_min, p.joins[0].span, an, alive_n);
+                if (t_pf < n_tiles) block_load<BLOCK, IPT, true>(p.cols[col0], t_pf * T::ITEMS, p.n_rows, an);
+                alive_n = pr.end();
+            } else {
+                if (dense >= 1) alive_n = star_step_tile<IPT>(p, 0, lds, so0, an, alive_n);
+                if (dense >= 1 && t_pf < n_tiles)
+                    block_load<BLOCK, IPT, true>(p.cols[col0], t_pf * T::ITEMS, p.n_rows, an);
+            }
+            if (dense >= 2) block_load_sel<BLOCK, IPT, true>(p.cols[col1], t_nxt * T::ITEMS, p.n_rows, alive_n, bn);
         }
         if (dense >= 2) alive_c = star_step_tile<IPT>(p, 1, lds, so1, bc, alive_c);
 
