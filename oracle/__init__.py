@@ -4,7 +4,7 @@ Plain row-at-a-time CPU definitions of what the tile-based query path of
 Shanbhag, Madden and Yu (SIGMOD 2020) computes: selection (section 4.2, Q3),
 projection (section 4.1, Q1/Q2), hash join with sum (section 4.3, Q4), dense
 group-by aggregation, and star queries (section 3.1 SSB Q1.1, section 5.3 SSB
-Q2.1).  The arithmetic lives in ``crystal_oracle.c`` (plain C, compiled with
+Q2.1), and radix histogram / partition / sort of key-value pairs (section 4.4).  The arithmetic lives in ``crystal_oracle.c`` (plain C, compiled with
 gcc, no SIMD intrinsics, FP contraction off); this module only marshals numpy
 arrays into it.
 
@@ -96,6 +96,12 @@ def load(path: str = _LIB):
     lib.oracle_groupby.restype = ctypes.c_int
     lib.oracle_star.argtypes = [ctypes.POINTER(_StarPlan), vp, ctypes.POINTER(i64)]
     lib.oracle_star.restype = ctypes.c_int
+    lib.oracle_radix_histogram.argtypes = [vp, i64, i32, i32, vp]
+    lib.oracle_radix_histogram.restype = ctypes.c_int
+    lib.oracle_radix_partition.argtypes = [vp, vp, i64, i32, i32, vp, vp]
+    lib.oracle_radix_partition.restype = ctypes.c_int
+    lib.oracle_sort_pairs.argtypes = [vp, vp, i64, vp, vp]
+    lib.oracle_sort_pairs.restype = ctypes.c_int
     if path == _LIB:
         _lib = lib
     return lib
@@ -250,3 +256,39 @@ def star(fact_cols, n_groups, preds=(), joins=(), agg=AGG_SUM, agg_cols=(0, 0), 
     if rc:
         raise OracleError(rc, "star")
     return (out, surv.value) if return_survivors else out
+
+
+def radix_histogram(keys, shift: int, bits: int, lib=None):
+    """Counts of digit (key >> shift) & (2^bits - 1), keys as uint32 (section 4.4)."""
+    lib = lib or load()
+    k, kp = _c(keys, np.uint32)
+    hist = np.zeros(1 << int(bits), dtype=np.int64)
+    rc = lib.oracle_radix_histogram(kp, k.size, int(shift), int(bits), hist.ctypes.data_as(ctypes.c_void_p))
+    if rc:
+        raise OracleError(rc, "radix_histogram")
+    return hist
+
+
+def radix_partition(keys, vals, shift: int, bits: int, lib=None):
+    """Stable partition of (key, value) pairs by digit (section 4.4)."""
+    lib = lib or load()
+    k, kp = _c(keys, np.uint32)
+    v, vp = _c(vals, np.uint32)
+    ok, ov = np.empty_like(k), np.empty_like(v)
+    rc = lib.oracle_radix_partition(kp, vp, k.size, int(shift), int(bits), ok.ctypes.data_as(ctypes.c_void_p),
+                                    ov.ctypes.data_as(ctypes.c_void_p))
+    if rc:
+        raise OracleError(rc, "radix_partition")
+    return ok, ov
+
+
+def sort_pairs(keys, vals, lib=None):
+    """Stable sort of (key, value) pairs by unsigned 32-bit key (section 4.4)."""
+    lib = lib or load()
+    k, kp = _c(keys, np.uint32)
+    v, vp = _c(vals, np.uint32)
+    ok, ov = np.empty_like(k), np.empty_like(v)
+    rc = lib.oracle_sort_pairs(kp, vp, k.size, ok.ctypes.data_as(ctypes.c_void_p), ov.ctypes.data_as(ctypes.c_void_p))
+    if rc:
+        raise OracleError(rc, "sort_pairs")
+    return ok, ov

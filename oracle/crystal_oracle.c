@@ -314,3 +314,75 @@ int oracle_star(const oracle_star_plan *p, int64_t *out, int64_t *survivors)
     for (int32_t j = 0; j < p->n_joins; ++j) key_index_free(&ix[j]);
     return rc;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Radix partitioning (section 4.4): with radix r and start bit a, the digit */
+/* of key e is bits a .. a+r-1 of e (unsigned); a partition pass places the */
+/* elements into 2^r contiguous partitions by digit.  The histogram counts   */
+/* each digit; the partition is stable (within a partition, input order).   */
+/* ------------------------------------------------------------------------ */
+static uint32_t digit_of(uint32_t key, int32_t shift, int32_t bits)
+{
+    return (key >> shift) & ((1u << bits) - 1u);
+}
+
+int oracle_radix_histogram(const uint32_t *keys, int64_t n, int32_t shift, int32_t bits, int64_t *hist)
+{
+    if (n < 0 || bits < 1 || bits > 16 || shift < 0 || shift + bits > 32) return ORACLE_EINVAL;
+    for (int64_t d = 0; d < ((int64_t)1 << bits); ++d) hist[d] = 0;
+    for (int64_t i = 0; i < n; ++i) hist[digit_of(keys[i], shift, bits)] += 1;
+    return ORACLE_OK;
+}
+
+int oracle_radix_partition(const uint32_t *keys, const uint32_t *vals, int64_t n, int32_t shift, int32_t bits,
+                           uint32_t *out_keys, uint32_t *out_vals)
+{
+    if (n < 0 || bits < 1 || bits > 16 || shift < 0 || shift + bits > 32) return ORACLE_EINVAL;
+    const int64_t nd = (int64_t)1 << bits;
+    int64_t *next = (int64_t *)calloc((size_t)nd, sizeof(int64_t));
+    if (!next) return ORACLE_EINVAL;
+    /* counting sort: count, exclusive prefix, then place in input order */
+    for (int64_t i = 0; i < n; ++i) next[digit_of(keys[i], shift, bits)] += 1;
+    int64_t run = 0;
+    for (int64_t d = 0; d < nd; ++d) {
+        int64_t c = next[d];
+        next[d] = run;
+        run += c;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t pos = next[digit_of(keys[i], shift, bits)]++;
+        out_keys[pos] = keys[i];
+        if (vals) out_vals[pos] = vals[i];
+    }
+    free(next);
+    return ORACLE_OK;
+}
+
+/* Sort of 32-bit (key, value) pairs by unsigned key, stable (section 4.4,
+ * the sort the radix passes build up to). */
+static const uint32_t *g_sort_ukeys;
+
+static int cmp_pairs(const void *pa, const void *pb)
+{
+    int64_t a = *(const int64_t *)pa, b = *(const int64_t *)pb;
+    uint32_t ka = g_sort_ukeys[a], kb = g_sort_ukeys[b];
+    if (ka != kb) return ka < kb ? -1 : 1;
+    return (a > b) - (a < b); /* equal keys keep input order */
+}
+
+int oracle_sort_pairs(const uint32_t *keys, const uint32_t *vals, int64_t n, uint32_t *out_keys,
+                      uint32_t *out_vals)
+{
+    if (n < 0) return ORACLE_EINVAL;
+    int64_t *idx = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    if (!idx) return ORACLE_EINVAL;
+    for (int64_t i = 0; i < n; ++i) idx[i] = i;
+    g_sort_ukeys = keys;
+    qsort(idx, (size_t)n, sizeof(int64_t), cmp_pairs);
+    for (int64_t i = 0; i < n; ++i) {
+        out_keys[i] = keys[idx[i]];
+        if (vals) out_vals[i] = vals[idx[i]];
+    }
+    free(idx);
+    return ORACLE_OK;
+}

@@ -368,10 +368,72 @@ def pin_star_bruteforce(lib):
     assert nonempty >= 10, "degenerate fixtures: too few populated groups"
 
 
+# ---------------------------------------------------------- radix (4.4) ----
+def pin_radix_histogram_closed_form(lib):
+    """keys = 0..n-1 with n = q * 2^(shift+bits) + r: every digit counted exactly."""
+    for shift, bits in [(0, 8), (4, 4), (8, 8), (24, 8), (28, 4)]:
+        m = 1 << (shift + bits)
+        n = 3 * m + 12345 if m < (1 << 20) else 100_000
+        keys = np.arange(n, dtype=np.uint64).astype(np.uint32)
+        h = oracle.radix_histogram(keys, shift, bits, lib=lib)
+        want = np.zeros(1 << bits, dtype=np.int64)
+        q, r = divmod(n, m)
+        want += q << shift                                # each full cycle hits every digit 2^shift times
+        for d in range(1 << bits):                        # the partial cycle 0..r-1
+            lo, hi = d << shift, (d + 1) << shift
+            want[d] += max(0, min(hi, r) - lo)
+        assert np.array_equal(h, want), (shift, bits)
+    top = np.array([0xFFFFFFFF, 0x80000000, 0x7FFFFFFF, 0], dtype=np.uint32)
+    assert oracle.radix_histogram(top, 24, 8, lib=lib)[[0x00, 0x7F, 0x80, 0xFF]].tolist() == [1, 1, 1, 1]
+
+
+def pin_radix_partition_properties(lib):
+    """Permutation, digits non-decreasing, partitions contiguous at the histogram's
+    prefix, stable (payload = input position), against a plain per-digit gather."""
+    rng = np.random.default_rng(17)
+    for n, shift, bits in [(0, 0, 8), (1, 0, 8), (1000, 3, 5), (50_000, 24, 8), (70_001, 0, 4)]:
+        keys = rng.integers(0, 2 ** 32, size=n, dtype=np.uint64).astype(np.uint32)
+        if n > 100:
+            keys[: n // 4] = keys[0]                      # many equal keys
+        vals = np.arange(n, dtype=np.uint32)
+        ok, ov = oracle.radix_partition(keys, vals, shift, bits, lib=lib)
+        dig = (ok.astype(np.uint64) >> shift) & ((1 << bits) - 1)
+        assert np.all(np.diff(dig.astype(np.int64)) >= 0)
+        assert np.array_equal(keys[ov], ok)                # values travel with their keys
+        assert np.array_equal(np.sort(ov), vals)           # a permutation
+        for d in np.unique(dig):
+            pos = ov[dig == d]
+            assert np.all(np.diff(pos.astype(np.int64)) > 0)   # stable
+        want = []
+        kd = (keys.astype(np.uint64) >> shift) & ((1 << bits) - 1)
+        for d in range(1 << bits):
+            want.extend(np.nonzero(kd == d)[0].tolist())
+        assert ov.tolist() == want
+
+
+def pin_sort_pairs(lib):
+    rng = np.random.default_rng(19)
+    n = 30_000
+    keys = rng.integers(0, 2 ** 32, size=n, dtype=np.uint64).astype(np.uint32)
+    keys[::3] = keys[5]
+    vals = np.arange(n, dtype=np.uint32)
+    ok, ov = oracle.sort_pairs(keys, vals, lib=lib)
+    assert np.all(ok[:-1] <= ok[1:])
+    assert np.array_equal(keys[ov], ok)
+    same = ok == keys[5]
+    assert np.all(np.diff(ov[same].astype(np.int64)) > 0)    # equal keys keep input order
+    rev = np.arange(1000, 0, -1, dtype=np.uint32)
+    rk, rv = oracle.sort_pairs(rev, np.arange(1000, dtype=np.uint32), lib=lib)
+    assert rk.tolist() == list(range(1, 1001)) and rv.tolist() == list(range(999, -1, -1))
+    big = np.array([0x80000000, 1, 0xFFFFFFFF, 0], dtype=np.uint32)      # unsigned order
+    assert oracle.sort_pairs(big, np.zeros(4, np.uint32), lib=lib)[0].tolist() == [0, 1, 0x80000000, 0xFFFFFFFF]
+
+
 ALL_PINS = [
     pin_select_closed_form, pin_select_extremes, pin_select_tile_example, pin_select_bruteforce,
     pin_project_exact, pin_project_rational, pin_project_sigmoid,
     pin_join_closed_form, pin_join_misses_and_width, pin_join_bruteforce,
     pin_groupby_closed_form, pin_groupby_bruteforce,
     pin_star_q11_factorial, pin_star_factorial, pin_star_bruteforce,
+    pin_radix_histogram_closed_form, pin_radix_partition_properties, pin_sort_pairs,
 ]

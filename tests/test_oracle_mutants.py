@@ -51,6 +51,11 @@ MUTANTS = {
                                    "if (f < p->dim_flo[j] || f >= p->dim_fhi[j] + (f > 0)) { pass = 0; break; }"),
     "star_ignores_dim_filter": ("if (p->dim_filter[j]) {", "if (0 && p->dim_filter[j]) {"),
     "star_inner_join_keeps_misses": ("if (r < 0) { pass = 0; break; }", "if (r < 0) { continue; }"),
+    "radix_digit_drops_top_bit": ("return (key >> shift) & ((1u << bits) - 1u);",
+                                  "return (key >> shift) & ((1u << (bits - 1)) - 1u);"),
+    "radix_inclusive_prefix": ("        next[d] = run;\n        run += c;", "        run += c;\n        next[d] = run;"),
+    "sort_unstable_ties": ("return (a > b) - (a < b); /* equal keys keep input order */",
+                           "return (a < b) - (a > b); /* equal keys keep input order */"),
 }
 
 RUNNER = textwrap.dedent("""
