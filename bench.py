@@ -33,11 +33,14 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=5)
-    p.add_argument("--workload", default="star", choices=["star", "q11", "select", "project", "join", "copy", "serve"])
+    p.add_argument("--workload", default="star", choices=["star", "q11", "select", "project", "join", "copy", "serve",
+                                                              "partition", "sort"])
     p.add_argument("--rows", type=int, default=0, help="override the fact/column length")
     p.add_argument("--sigma", type=float, default=0.5, help="select selectivity")
     p.add_argument("--dim", type=int, default=1 << 20, help="join build size D")
     p.add_argument("--kind", default="linear", choices=["linear", "direct"])
+    p.add_argument("--bits", type=int, default=8, help="partition: radix bits")
+    p.add_argument("--shift", type=int, default=0, help="partition: start bit")
     p.add_argument("--order", default="1,0,2,3", help="star join order")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-graph", action="store_true", help="star: launch eagerly instead of replaying HIP graphs")
@@ -249,7 +252,8 @@ def main():
         sys.exit(3)
     cx.load()
     kernel_id = {"star": cx.K_STAR, "q11": cx.K_STAR, "select": cx.K_SELECT, "project": cx.K_PROJECT,
-                 "join": cx.K_HT_PROBE, "copy": cx.K_SELECT, "serve": cx.K_SHARED_SCAN}[args.workload]
+                 "join": cx.K_HT_PROBE, "copy": cx.K_SELECT, "serve": cx.K_SHARED_SCAN,
+                 "partition": cx.K_RADIX, "sort": cx.K_RADIX}[args.workload]
     if args.tune:
         b, i, g = (int(x) for x in args.tune.split(","))
         cx.tune_set(kernel_id, b, i, g)
@@ -487,6 +491,56 @@ def main():
 
     elif args.workload == "serve":
         result.update(serve(args, torch, cx, datagen, queries, roof))
+
+    elif args.workload in ("partition", "sort"):
+        # section 4.4: 2^28 pairs of 32-bit keys and 32-bit values
+        n = args.rows or (1 << 28)
+        kh, vh = datagen.radix_pairs(n)
+        keys, vals = queries.to_dev(kh), queries.to_dev(vh)
+        ok, ov = torch.empty_like(keys), torch.empty_like(vals)
+        if args.workload == "partition":
+            offs = torch.empty((1 << args.bits) + 1, dtype=torch.int32, device="cuda")
+            scratch = torch.empty(cx.load().crystal_radix_partition_scratch_bytes(n), dtype=torch.uint8,
+                                  device="cuda")
+            call = lambda: cx.radix_partition(keys, args.shift, args.bits, vals=vals, out_keys=ok, out_vals=ov,
+                                              part_offsets=offs, scratch=scratch)
+            passes = 1
+        else:
+            scratch = torch.empty(cx.load().crystal_sort_pairs_scratch_bytes(n, 1), dtype=torch.uint8,
+                                  device="cuda")
+            call = lambda: cx.sort_pairs(keys, vals, out_keys=ok, out_vals=ov, scratch=scratch)
+            passes = 4
+        for _ in range(W):
+            call()
+        torch.cuda.synchronize()
+        timer = Timer(torch)
+        t0 = time.perf_counter()
+        for _ in range(K):
+            timer.run(call)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        kern_ms = timer.mean_ms()
+        # per pass: the histogram reads the keys (4n), the shuffle reads keys and
+        # values (8n) and writes them (8n)
+        b = passes * 20 * n
+        what = (f"radix partition of 2^{n.bit_length() - 1} key/value pairs on {args.bits} bits at bit {args.shift}"
+                if args.workload == "partition" else f"radix sort of {n} 32-bit key/value pairs")
+        result.update(metric="pairs/s", value=n * K / elapsed, unit="pairs/s", ms_per_step=elapsed / K * 1e3,
+                      dtype="u32", config={"workload": what, "pairs": n, "passes": passes,
+                                           "tile": list(cx.tune_get(cx.K_RADIX, n))})
+        roof.update(kernel="crystal radix pass (histogram + scan + shuffle)", achieved=b / (kern_ms * 1e-3) / 1e9,
+                    algorithmic_bytes=b, kernel_ms=kern_ms)
+        if not args.no_cpu_baseline and args.workload == "sort":
+            import oracle
+            m = 1 << 22
+            t1 = time.perf_counter()
+            reps = 0
+            while time.perf_counter() - t1 < args.cpu_seconds or reps == 0:
+                oracle.sort_pairs(kh[:m].view(np.uint32), vh[:m].view(np.uint32))
+                reps += 1
+            cpu_s = time.perf_counter() - t1
+            cpu = {"value": m * reps / cpu_s, "unit": "pairs/s", "cores": 1, "kind": "oracle",
+                   "sample": f"{reps} stable sorts of the first 2^22 pairs"}
 
     roof["frac"] = roof["achieved"] / roof["peak"]
     result["roofline"] = roof

@@ -58,7 +58,7 @@ typedef struct crystal_range {
 const char *crystal_status_string(int32_t status);
 
 /* ABI version of this header (incremented on any layout change). */
-#define CRYSTAL_ABI_VERSION 2
+#define CRYSTAL_ABI_VERSION 3
 int32_t crystal_abi_version(void);
 
 /* sizeof of the ABI structs as compiled into the library, so a binding can
@@ -385,6 +385,47 @@ crystal_status crystal_graph_launch(crystal_graph *g, void *stream);
 crystal_status crystal_graph_destroy(crystal_graph *g);
 
 /* ------------------------------------------------------------------------ */
+/* Radix partitioning and sort (section 4.4).                               */
+/*                                                                          */
+/* Keys and values are 32-bit words in device memory; keys are ordered as   */
+/* unsigned integers (flip bit 31 of a signed key to sort it as signed).    */
+/* A pass with radix `bits` (1..8) and start bit `shift` (shift + bits <=   */
+/* 32) uses the digit (key >> shift) & (2^bits - 1).  n must be below 2^32. */
+/* Inputs are never modified; outputs must not overlap the inputs.          */
+/* ------------------------------------------------------------------------ */
+
+/* Histogram phase: hist[d] (device, 2^bits words, overwritten) = number of  */
+/* keys whose digit is d.                                                    */
+crystal_status crystal_radix_histogram(const uint32_t *keys, int64_t n, int32_t shift, int32_t bits,
+                                       uint32_t *hist, void *stream);
+
+/* Scratch (device, 256-byte aligned) of one partition pass over n keys     */
+/* with the current tuning: the per-workgroup digit counts and their        */
+/* prefix sums.                                                             */
+size_t crystal_radix_partition_scratch_bytes(int64_t n);
+
+/* One partition pass: histogram + shuffle.  Writes the pairs into 2^bits   */
+/* contiguous partitions in digit order, stably (pairs with equal digits    */
+/* keep their input order).  vals / out_vals: both null (keys only) or both */
+/* device arrays of n words.  part_offsets: null, or device array of        */
+/* 2^bits + 1 words that receives the start of each partition and n.        */
+/* Scratch too small: CRYSTAL_ESCRATCH.  Calls sharing scratch race.        */
+crystal_status crystal_radix_partition(const uint32_t *keys, const uint32_t *vals, int64_t n, int32_t shift,
+                                       int32_t bits, uint32_t *out_keys, uint32_t *out_vals,
+                                       uint32_t *part_offsets, void *scratch, size_t scratch_bytes,
+                                       void *stream);
+
+/* Scratch (device, 256-byte aligned) of crystal_sort_pairs: one ping-pong  */
+/* copy of the keys (and of the values when with_values) plus one pass's    */
+/* scratch.                                                                 */
+size_t crystal_sort_pairs_scratch_bytes(int64_t n, int32_t with_values);
+
+/* Stable sort of n (key, value) pairs by unsigned key: four stable 8-bit   */
+/* partition passes from the low byte up.  vals / out_vals as above.        */
+crystal_status crystal_sort_pairs(const uint32_t *keys, const uint32_t *vals, int64_t n, uint32_t *out_keys,
+                                  uint32_t *out_vals, void *scratch, size_t scratch_bytes, void *stream);
+
+/* ------------------------------------------------------------------------ */
 /* Tile-size tuning (section 3.3: the tile is BLOCK threads x IPT items per */
 /* thread; the best shape depends on the kernel and the input).  The table  */
 /* maps (kernel, size bucket = floor(log2 n)) to a compiled variant.  A     */
@@ -398,7 +439,8 @@ enum {
     CRYSTAL_K_GROUPBY = 3,
     CRYSTAL_K_STAR = 4,
     CRYSTAL_K_SHARED_SCAN = 5,
-    CRYSTAL_K_COUNT = 6
+    CRYSTAL_K_RADIX = 6,
+    CRYSTAL_K_COUNT = 7
 };
 
 /* Number of compiled (block, ipt) variants of `kernel`; fills up to `max`. */

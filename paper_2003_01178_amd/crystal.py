@@ -20,7 +20,7 @@ LIB_PATH = os.environ.get("CRYSTAL_LIB", DEFAULT_LIB)
 OK, EINVAL, ESCRATCH, EFULL, EDUPKEY, EHIP, EBUSY, ERANGE = range(8)
 HT_LINEAR, HT_DIRECT = 0, 1
 AGG_SUM, AGG_SUM_PRODUCT, AGG_SUM_DIFF, AGG_COUNT = 0, 1, 2, 3
-K_SELECT, K_PROJECT, K_HT_PROBE, K_GROUPBY, K_STAR, K_SHARED_SCAN = range(6)
+K_SELECT, K_PROJECT, K_HT_PROBE, K_GROUPBY, K_STAR, K_SHARED_SCAN, K_RADIX = range(7)
 MAX_COLS, MAX_PREDS, MAX_JOINS = 16, 4, 4
 I32_MIN, I32_MAX = -(2 ** 31), 2 ** 31 - 1
 
@@ -129,6 +129,12 @@ def _declare(lib):
         "crystal_graph_end": (c_i32, [c_vp, P(c_vp)]),
         "crystal_graph_launch": (c_i32, [c_vp, c_vp]),
         "crystal_graph_destroy": (c_i32, [c_vp]),
+        "crystal_radix_histogram": (c_i32, [c_vp, c_i64, c_i32, c_i32, c_vp, c_vp]),
+        "crystal_radix_partition_scratch_bytes": (ctypes.c_size_t, [c_i64]),
+        "crystal_radix_partition": (c_i32, [c_vp, c_vp, c_i64, c_i32, c_i32, c_vp, c_vp, c_vp, c_vp,
+                                            ctypes.c_size_t, c_vp]),
+        "crystal_sort_pairs_scratch_bytes": (ctypes.c_size_t, [c_i64, c_i32]),
+        "crystal_sort_pairs": (c_i32, [c_vp, c_vp, c_i64, c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp]),
         "crystal_tune_variants": (c_i32, [c_i32, P(c_i32), P(c_i32), c_i32]),
         "crystal_tune_set": (c_i32, [c_i32, c_i32, c_i32, c_i32, c_i32, c_i32]),
         "crystal_tune_get": (c_i32, [c_i32, c_i64, P(c_i32), P(c_i32), P(c_i32)]),
@@ -557,6 +563,70 @@ class Server:
 
 
 # ----------------------------------------------------------------- tuning --
+def _words(t, n, what):
+    """A device tensor of 32-bit words (int32 holding unsigned bits) with n items."""
+    if t is None:
+        return None
+    if t.dtype != torch.int32:
+        raise TypeError(f"{what}: expected int32 words, got {t.dtype}")
+    if t.numel() < n:
+        raise ValueError(f"{what}: {t.numel()} words, need {n}")
+    return _ptr(t)
+
+
+def _scratch(nbytes, scratch, device):
+    if scratch is None or scratch.numel() < nbytes:
+        scratch = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+    return scratch
+
+
+def radix_histogram(keys, shift, bits, hist=None, stream=None):
+    """Section 4.4 histogram phase: counts of digit (key >> shift) & (2^bits - 1)."""
+    lib = load()
+    n = keys.numel()
+    hist = torch.empty(1 << int(bits), dtype=torch.int32, device=keys.device) if hist is None else hist
+    _check(lib.crystal_radix_histogram(_words(keys, n, "keys"), n, int(shift), int(bits),
+                                       _words(hist, 1 << int(bits), "hist"), _stream(stream)),
+           "crystal_radix_histogram")
+    return hist
+
+
+def radix_partition(keys, shift, bits, vals=None, out_keys=None, out_vals=None, part_offsets=None,
+                    scratch=None, stream=None):
+    """Section 4.4 partition pass (histogram + stable shuffle) on one digit.
+
+    Returns (out_keys, out_vals or None, part_offsets[2^bits + 1])."""
+    lib = load()
+    n = keys.numel()
+    dev = keys.device
+    out_keys = torch.empty(max(n, 1), dtype=torch.int32, device=dev) if out_keys is None else out_keys
+    if vals is not None and out_vals is None:
+        out_vals = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    nb = (1 << int(bits)) + 1
+    part_offsets = torch.empty(nb, dtype=torch.int32, device=dev) if part_offsets is None else part_offsets
+    scratch = _scratch(lib.crystal_radix_partition_scratch_bytes(n), scratch, dev)
+    _check(lib.crystal_radix_partition(_words(keys, n, "keys"), _words(vals, n, "vals"), n, int(shift), int(bits),
+                                       _words(out_keys, n, "out_keys"), _words(out_vals, n, "out_vals"),
+                                       _words(part_offsets, nb, "part_offsets"), _ptr(scratch), scratch.numel(),
+                                       _stream(stream)), "crystal_radix_partition")
+    return out_keys, out_vals, part_offsets
+
+
+def sort_pairs(keys, vals=None, out_keys=None, out_vals=None, scratch=None, stream=None):
+    """Section 4.4 sort: stable sort of (key, value) pairs by unsigned 32-bit key."""
+    lib = load()
+    n = keys.numel()
+    dev = keys.device
+    out_keys = torch.empty(max(n, 1), dtype=torch.int32, device=dev) if out_keys is None else out_keys
+    if vals is not None and out_vals is None:
+        out_vals = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    scratch = _scratch(lib.crystal_sort_pairs_scratch_bytes(n, int(vals is not None)), scratch, dev)
+    _check(lib.crystal_sort_pairs(_words(keys, n, "keys"), _words(vals, n, "vals"), n,
+                                  _words(out_keys, n, "out_keys"), _words(out_vals, n, "out_vals"), _ptr(scratch),
+                                  scratch.numel(), _stream(stream)), "crystal_sort_pairs")
+    return out_keys, out_vals
+
+
 def tune_variants(kernel):
     lib = load()
     n = lib.crystal_tune_variants(int(kernel), None, None, 0)

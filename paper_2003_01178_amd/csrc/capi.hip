@@ -76,6 +76,7 @@ static LaunchCfg default_cfg(int kernel) {
     case CRYSTAL_K_GROUPBY: return {256, 16, 0};
     case CRYSTAL_K_STAR: return {256, 16, 0};
     case CRYSTAL_K_SHARED_SCAN: return {256, 8, 0};
+    case CRYSTAL_K_RADIX: return {256, 16, 0};
     default: return {256, 16, 0};
     }
 }
@@ -96,6 +97,14 @@ LaunchCfg tune_lookup(int kernel, int64_t n) {
 
 static bool variant_exists(int kernel, int block, int ipt) {
     const int key = CRYSTAL_VARIANT_KEY(block, ipt);
+    if (kernel == CRYSTAL_K_RADIX) {
+        switch (key) {
+#define X(B, I) case CRYSTAL_VARIANT_KEY(B, I): return true;
+            CRYSTAL_VARIANTS_RADIX(X)
+#undef X
+        default: return false;
+        }
+    }
     if (kernel == CRYSTAL_K_SELECT) {
         switch (key) {
 #define X(B, I) case CRYSTAL_VARIANT_KEY(B, I): return true;
@@ -450,6 +459,88 @@ crystal_status crystal_graph_destroy(crystal_graph *g) {
     return (e1 == hipSuccess && e2 == hipSuccess) ? CRYSTAL_OK : CRYSTAL_EHIP;
 }
 
+// ------------------------------------------------------------------ radix --
+static bool radix_args_ok(const uint32_t *keys, const uint32_t *vals, int64_t n, const uint32_t *ok,
+                          const uint32_t *ov) {
+    if (n < 0 || n > (int64_t)UINT32_MAX - 1) return false;
+    if ((vals == nullptr) != (ov == nullptr)) return false;
+    if (n == 0) return true;
+    if (!keys || !ok || ((uintptr_t)keys & 3u) || ((uintptr_t)ok & 3u)) return false;
+    if (vals && (((uintptr_t)vals & 3u) || ((uintptr_t)ov & 3u))) return false;
+    // outputs must not overlap inputs
+    auto overlap = [n](const void *a, const void *b) {
+        const char *x = (const char *)a, *y = (const char *)b;
+        return x < y + n * 4 && y < x + n * 4;
+    };
+    if (overlap(keys, ok) || (vals && (overlap(vals, ov) || overlap(keys, ov) || overlap(vals, ok) ||
+                                      overlap(ok, ov))))
+        return false;
+    return true;
+}
+
+crystal_status crystal_radix_histogram(const uint32_t *keys, int64_t n, int32_t shift, int32_t bits,
+                                       uint32_t *hist, void *stream) {
+    if (bits < 1 || bits > 8 || shift < 0 || shift + bits > 32 || !hist || n < 0 || n > (int64_t)UINT32_MAX - 1 ||
+        (n > 0 && (!keys || ((uintptr_t)keys & 3u))))
+        return CRYSTAL_EINVAL;
+    const LaunchCfg cfg = tune_lookup(CRYSTAL_K_RADIX, n);
+    return from_hip(launch_radix_histogram(cfg, keys, n, shift, bits, hist, as_stream(stream)));
+}
+
+size_t crystal_radix_partition_scratch_bytes(int64_t n) {
+    return (size_t)radix_pass_scratch_bytes(tune_lookup(CRYSTAL_K_RADIX, n), n);
+}
+
+crystal_status crystal_radix_partition(const uint32_t *keys, const uint32_t *vals, int64_t n, int32_t shift,
+                                       int32_t bits, uint32_t *out_keys, uint32_t *out_vals,
+                                       uint32_t *part_offsets, void *scratch, size_t scratch_bytes,
+                                       void *stream) {
+    if (bits < 1 || bits > 8 || shift < 0 || shift + bits > 32 || !radix_args_ok(keys, vals, n, out_keys, out_vals))
+        return CRYSTAL_EINVAL;
+    const LaunchCfg cfg = tune_lookup(CRYSTAL_K_RADIX, n);
+    if (!radix_variant_fits(cfg.block, cfg.ipt)) return CRYSTAL_EINVAL;
+    if (n > 0) {
+        if (!scratch || ((uintptr_t)scratch & 255u)) return scratch ? CRYSTAL_EINVAL : CRYSTAL_ESCRATCH;
+        if (scratch_bytes < (size_t)radix_pass_scratch_bytes(cfg, n)) return CRYSTAL_ESCRATCH;
+    }
+    return from_hip(launch_radix_partition(cfg, keys, vals, n, shift, bits, out_keys, out_vals, part_offsets,
+                                           scratch, as_stream(stream)));
+}
+
+static int64_t round256(int64_t b) { return (b + 255) / 256 * 256; }
+
+size_t crystal_sort_pairs_scratch_bytes(int64_t n, int32_t with_values) {
+    if (n <= 0) return 256;
+    const int64_t copy = round256(n * 4);
+    return (size_t)(copy * (with_values ? 2 : 1) +
+                    radix_pass_scratch_bytes(tune_lookup(CRYSTAL_K_RADIX, n), n));
+}
+
+crystal_status crystal_sort_pairs(const uint32_t *keys, const uint32_t *vals, int64_t n, uint32_t *out_keys,
+                                  uint32_t *out_vals, void *scratch, size_t scratch_bytes, void *stream) {
+    if (!radix_args_ok(keys, vals, n, out_keys, out_vals)) return CRYSTAL_EINVAL;
+    if (n == 0) return CRYSTAL_OK;
+    const LaunchCfg cfg = tune_lookup(CRYSTAL_K_RADIX, n);
+    if (!radix_variant_fits(cfg.block, cfg.ipt)) return CRYSTAL_EINVAL;
+    if (!scratch || ((uintptr_t)scratch & 255u)) return scratch ? CRYSTAL_EINVAL : CRYSTAL_ESCRATCH;
+    if (scratch_bytes < crystal_sort_pairs_scratch_bytes(n, vals != nullptr)) return CRYSTAL_ESCRATCH;
+    const int64_t copy = round256(n * 4);
+    uint32_t *tk = (uint32_t *)scratch;
+    uint32_t *tv = vals ? (uint32_t *)((char *)scratch + copy) : nullptr;
+    void *pass = (char *)scratch + copy * (vals ? 2 : 1);
+    // in -> tmp -> out -> tmp -> out, 8 bits per pass from the low byte up
+    const uint32_t *ik[4] = {keys, tk, out_keys, tk};
+    const uint32_t *iv[4] = {vals, tv, out_vals, tv};
+    uint32_t *ok[4] = {tk, out_keys, tk, out_keys};
+    uint32_t *ov[4] = {tv, out_vals, tv, out_vals};
+    for (int p = 0; p < 4; ++p) {
+        hipError_t e = launch_radix_partition(cfg, ik[p], iv[p], n, 8 * p, 8, ok[p], ov[p], nullptr, pass,
+                                              as_stream(stream));
+        if (e != hipSuccess) return CRYSTAL_EHIP;
+    }
+    return CRYSTAL_OK;
+}
+
 // ----------------------------------------------------------------- tuning --
 int32_t crystal_tune_variants(int32_t kernel, int32_t *blocks, int32_t *ipts, int32_t max) {
     if (kernel < 0 || kernel >= CRYSTAL_K_COUNT) return 0;
@@ -464,6 +555,10 @@ int32_t crystal_tune_variants(int32_t kernel, int32_t *blocks, int32_t *ipts, in
     if (kernel == CRYSTAL_K_SELECT) {
 #define X(B, I) add(B, I);
         CRYSTAL_VARIANTS_ALL(X)
+#undef X
+    } else if (kernel == CRYSTAL_K_RADIX) {
+#define X(B, I) add(B, I);
+        CRYSTAL_VARIANTS_RADIX(X)
 #undef X
     } else {
 #define X(B, I) add(B, I);

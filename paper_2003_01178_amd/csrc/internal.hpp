@@ -143,4 +143,15 @@ hipError_t launch_shared_scan(const LaunchCfg &cfg, const BatchDev &b, int32_t *
 hipError_t launch_star(const LaunchCfg &cfg, const StarPlanDev &plan, uint64_t *out,
                        int32_t *status, uint64_t *partials, hipStream_t s);
 
+// ----------------------------------------------------------------- radix --
+// Scratch of one partition pass (count matrix + digit totals) under cfg.
+int64_t radix_pass_scratch_bytes(const LaunchCfg &cfg, int64_t n);
+// Whether the (block, ipt) shuffle variant exists and its LDS fits a workgroup.
+bool radix_variant_fits(int block, int ipt);
+hipError_t launch_radix_histogram(const LaunchCfg &cfg, const uint32_t *keys, int64_t n, int shift, int bits,
+                                  uint32_t *hist, hipStream_t s);
+hipError_t launch_radix_partition(const LaunchCfg &cfg, const uint32_t *keys, const uint32_t *vals, int64_t n,
+                                  int shift, int bits, uint32_t *out_keys, uint32_t *out_vals,
+                                  uint32_t *part_offsets, void *scratch, hipStream_t s);
+
 }  // namespace crystal

@@ -17,4 +17,10 @@
     X(512, 4) X(512, 8) X(512, 16)                                               \
     X(1024, 4) X(1024, 8) X(1024, 16)
 
+// Radix partitioning: one thread per digit, so at least 256 threads.
+#define CRYSTAL_VARIANTS_RADIX(X)                                                \
+    X(256, 4) X(256, 8) X(256, 16)                                               \
+    X(512, 4) X(512, 8) X(512, 16)                                               \
+    X(1024, 4) X(1024, 8) X(1024, 16)
+
 #define CRYSTAL_VARIANT_KEY(B, I) ((B) * 1000 + (I))

@@ -104,6 +104,15 @@ def project_columns(n: int = 1 << 29, workload: int = 11):
     return (g1.random(int(n), dtype=np.float32), g2.random(int(n), dtype=np.float32))
 
 
+def radix_pairs(n: int = 1 << 28, workload: int = 12, key_bits: int = 32):
+    """(keys, values) of the sort workload: uniform unsigned keys over
+    [0, 2^key_bits) and uniform 32-bit values, both as int32 bit patterns."""
+    gk, gv = streams(workload, 2)
+    keys = gk.integers(0, 1 << int(key_bits), size=int(n), dtype=np.uint64).astype(np.uint32)
+    vals = gv.integers(0, 1 << 32, size=int(n), dtype=np.uint64).astype(np.uint32)
+    return keys.view(np.int32), vals.view(np.int32)
+
+
 @dataclass
 class JoinTables:
     dim_key: np.ndarray

@@ -34,7 +34,7 @@ def test_every_declared_symbol_is_exported(cx):
 
 def test_struct_layout_matches_binding(cx):
     lib = cx.load()
-    assert lib.crystal_abi_version() == 2
+    assert lib.crystal_abi_version() == 3
     for which, ty in enumerate((cx.Range, cx.HT, cx.Pred, cx.Join, cx.StarQueryC, cx.QmaskTableC,
                                 cx.BatchQueryC, cx.BatchC, cx.ServerTemplateC, cx.ServerConfigC,
                                 cx.ServerStatsC)):
@@ -126,4 +126,32 @@ def test_tuning_table(cx, tmp_path):
     assert cx.tune_get(cx.K_STAR, 120_000_000) == d
     cx.tune_load(p)
     assert cx.tune_get(cx.K_STAR, 120_000_000) == (512, 8, 2)
+    cx.tune_reset()
+
+
+def test_radix_host_errors(cx):
+    """Argument errors of the radix calls are caught on the host, before any
+    device work (the pointers below are never dereferenced)."""
+    lib = cx.load()
+    fake_a, fake_b = ctypes.c_void_p(1 << 20), ctypes.c_void_p(1 << 30)
+    for shift, bits in [(0, 0), (0, 9), (25, 8), (-1, 4), (31, 2)]:
+        assert lib.crystal_radix_partition(fake_a, None, 100, shift, bits, fake_b, None, None, None, 0,
+                                           None) == cx.EINVAL
+        assert lib.crystal_radix_histogram(fake_a, 100, shift, bits, fake_b, None) == cx.EINVAL
+    # values without an output for them, overlapping output, n out of range
+    assert lib.crystal_radix_partition(fake_a, fake_a, 100, 0, 8, fake_b, None, None, None, 0, None) == cx.EINVAL
+    assert lib.crystal_radix_partition(fake_a, None, 100, 0, 8, ctypes.c_void_p((1 << 20) + 64), None, None,
+                                       None, 0, None) == cx.EINVAL
+    assert lib.crystal_sort_pairs(fake_a, None, -1, fake_b, None, None, 0, None) == cx.EINVAL
+    assert lib.crystal_sort_pairs(fake_a, None, 1 << 32, fake_b, None, None, 0, None) == cx.EINVAL
+    assert lib.crystal_sort_pairs(None, None, 0, None, None, None, 0, None) == cx.OK
+    assert lib.crystal_radix_histogram(fake_a, 100, 0, 8, None, None) == cx.EINVAL
+
+
+def test_radix_tuning_variants(cx):
+    lib = cx.load()
+    n = cx.tune_variants(cx.K_RADIX)
+    assert (256, 16) in n and all(b >= 256 for b, _ in n)
+    assert lib.crystal_tune_set(cx.K_RADIX, -1, -1, 128, 16, 0) == cx.EINVAL
+    assert lib.crystal_tune_set(cx.K_RADIX, -1, -1, 1024, 8, 2) == cx.OK
     cx.tune_reset()

@@ -1,0 +1,168 @@
+"""GPU parity of radix histogram, radix partition and the radix sort
+(section 4.4) against the CPU oracle, through the C ABI.  The partition is
+stable, so its output is unique and compared element by element."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from helpers import announce
+from paper_2003_01178_amd import crystal as cx
+from paper_2003_01178_amd import datagen
+
+pytestmark = pytest.mark.gpu
+SIZES = [0, 1, 63, 64, 4096, 4097, 3 * 4096 + 17, 100_003, 1_000_003]
+DIGITS = [(0, 8), (8, 8), (24, 8), (4, 4), (28, 4), (0, 1), (31, 1), (13, 7)]
+
+
+@pytest.fixture(autouse=True)
+def _reset_tuning():
+    cx.tune_reset()
+    yield
+    cx.tune_reset()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def u32(t, n):
+    return t[:n].cpu().numpy().view(np.uint32)
+
+
+def pairs(n, workload, key_bits=32):
+    k, v = datagen.radix_pairs(n, workload=workload, key_bits=key_bits)
+    return k.view(np.uint32), v.view(np.uint32)
+
+
+# --------------------------------------------------------------- histogram --
+@pytest.mark.parametrize("n", SIZES)
+@pytest.mark.parametrize("shift,bits", DIGITS)
+def test_histogram_matches_oracle(n, shift, bits):
+    announce("radix histogram", n, shift, bits)
+    k, _ = pairs(n, 500 + n)
+    got = cx.radix_histogram(dev(k.view(np.int32)), shift, bits).cpu().numpy().view(np.uint32)
+    want = oracle.radix_histogram(k, shift, bits)
+    assert np.array_equal(got.astype(np.int64), want)
+
+
+# --------------------------------------------------------------- partition --
+def check_partition(k, v, shift, bits, with_vals, key_dev=None):
+    n = k.size
+    kd = dev(k.view(np.int32)) if key_dev is None else key_dev
+    vd = dev(v.view(np.int32)) if with_vals else None
+    ok, ov, offs = cx.radix_partition(kd, shift, bits, vals=vd)
+    wk, wv = oracle.radix_partition(k, v, shift, bits)
+    assert np.array_equal(u32(ok, n), wk)
+    if with_vals:
+        assert np.array_equal(u32(ov, n), wv)
+    h = oracle.radix_histogram(k, shift, bits)
+    want_offs = np.concatenate([[0], np.cumsum(h)])
+    assert np.array_equal(offs.cpu().numpy().astype(np.int64), want_offs)
+
+
+@pytest.mark.parametrize("n", SIZES)
+@pytest.mark.parametrize("shift,bits", DIGITS)
+def test_partition_matches_oracle(n, shift, bits):
+    announce("radix partition", n, shift, bits)
+    k, v = pairs(n, 600 + n)
+    check_partition(k, v, shift, bits, with_vals=True)
+
+
+@pytest.mark.parametrize("n", [4097, 1_000_003])
+def test_partition_keys_only(n):
+    announce("radix partition keys only", n)
+    k, v = pairs(n, 700 + n)
+    check_partition(k, v, 8, 8, with_vals=False)
+
+
+@pytest.mark.parametrize("case", ["all_equal", "two_values", "narrow", "sorted", "reversed"])
+def test_partition_skewed(case):
+    """Degenerate digit distributions: one digit for every key (a whole wave
+    of equal digits), two digits, keys from a small domain, presorted input."""
+    announce("radix partition skewed", case)
+    n = 300_007
+    rng = np.random.default_rng(3)
+    if case == "all_equal":
+        k = np.full(n, 0xABCDEF12, dtype=np.uint32)
+    elif case == "two_values":
+        k = np.where(rng.random(n) < 0.5, 0x00000005, 0xFF000005).astype(np.uint32)
+    elif case == "narrow":
+        k = rng.integers(0, 5, size=n, dtype=np.uint64).astype(np.uint32) << np.uint32(8)
+    elif case == "sorted":
+        k = np.arange(n, dtype=np.uint32) * np.uint32(7919)
+        k.sort()
+    else:
+        k = (np.arange(n, dtype=np.uint64)[::-1] * 12345).astype(np.uint32)
+    v = np.arange(n, dtype=np.uint32)
+    for shift in (0, 8, 24):
+        check_partition(k, v, shift, 8, with_vals=True)
+
+
+@pytest.mark.parametrize("block,ipt", [(256, 4), (256, 8), (512, 16), (1024, 4), (1024, 8), (1024, 16)])
+@pytest.mark.parametrize("gpc", [0, 1, 3])
+def test_partition_tile_shapes(block, ipt, gpc):
+    announce("radix partition shape", block, ipt, gpc)
+    cx.tune_set(cx.K_RADIX, block, ipt, gpc)
+    for n in (block * ipt * 5 + 3, 777_777):
+        k, v = pairs(n, 800 + n)
+        check_partition(k, v, 0, 8, with_vals=True)
+
+
+def test_partition_errors():
+    announce("radix partition errors")
+    k = dev(np.arange(1000, dtype=np.int32))
+    lib = cx.load()
+    for shift, bits in [(0, 0), (0, 9), (25, 8), (-1, 4)]:
+        with pytest.raises(cx.CrystalError) as e:
+            cx.radix_partition(k, shift, bits)
+        assert e.value.code == cx.EINVAL
+    with pytest.raises(cx.CrystalError) as e:      # output overlapping the input
+        cx.radix_partition(k, 0, 8, out_keys=k)
+    assert e.value.code == cx.EINVAL
+    out = torch.empty_like(k)
+    small = torch.empty(16, dtype=torch.uint8, device="cuda")
+    rc = lib.crystal_radix_partition(cx._ptr(k), None, 1000, 0, 8, cx._ptr(out), None, None, cx._ptr(small), 16,
+                                     cx._stream())
+    assert rc == cx.ESCRATCH
+    rc = lib.crystal_sort_pairs(cx._ptr(k), None, 1000, cx._ptr(out), None, cx._ptr(small), 16, cx._stream())
+    assert rc == cx.ESCRATCH
+    torch.cuda.synchronize()
+
+
+# -------------------------------------------------------------------- sort --
+@pytest.mark.parametrize("n", SIZES)
+@pytest.mark.parametrize("key_bits", [32, 12])
+def test_sort_matches_oracle(n, key_bits):
+    """12-bit keys make long runs of equal keys: stability decides the values."""
+    announce("radix sort", n, key_bits)
+    k, v = pairs(n, 900 + n, key_bits=key_bits)
+    ok, ov = cx.sort_pairs(dev(k.view(np.int32)), dev(v.view(np.int32)))
+    wk, wv = oracle.sort_pairs(k, v)
+    assert np.array_equal(u32(ok, n), wk)
+    assert np.array_equal(u32(ov, n), wv)
+
+
+def test_sort_keys_only_and_tile_shape():
+    announce("radix sort keys only")
+    n = 1_000_003
+    k, _ = pairs(n, 77)
+    want = np.sort(k)
+    ok, ov = cx.sort_pairs(dev(k.view(np.int32)))
+    assert ov is None and np.array_equal(u32(ok, n), want)
+    cx.tune_set(cx.K_RADIX, 1024, 8, 1)
+    ok, _ = cx.sort_pairs(dev(k.view(np.int32)))
+    assert np.array_equal(u32(ok, n), want)
+
+
+def test_sort_repeated_calls_share_scratch():
+    """Two sorts through one scratch buffer, the second smaller."""
+    announce("radix sort scratch reuse")
+    lib = cx.load()
+    n1, n2 = 500_001, 4097
+    scratch = torch.empty(lib.crystal_sort_pairs_scratch_bytes(n1, 1), dtype=torch.uint8, device="cuda")
+    for n in (n1, n2):
+        k, v = pairs(n, 1000 + n)
+        ok, ov = cx.sort_pairs(dev(k.view(np.int32)), dev(v.view(np.int32)), scratch=scratch)
+        wk, wv = oracle.sort_pairs(k, v)
+        assert np.array_equal(u32(ok, n), wk) and np.array_equal(u32(ov, n), wv)
