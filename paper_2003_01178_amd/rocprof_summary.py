@@ -19,14 +19,24 @@ import os
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-STAR_SOURCES = ("csrc/star.hip", "csrc/block.hpp", "csrc/internal.hpp")
+STAR_SOURCES = ("csrc/star.hip", "csrc/block.hpp")
+# the part of internal.hpp that the star kernel compiles against
+STAR_DECLS = ("csrc/internal.hpp", b"// Device form of a star query", b"// ----------------------------------------------------------- shared scan")
 
 
-def source_hash(files=STAR_SOURCES):
+def source_hash(files=STAR_SOURCES, decls=STAR_DECLS):
+    """Hash of the sources the star kernel is built from."""
     h = hashlib.sha256()
     for f in files:
         with open(os.path.join(HERE, f), "rb") as fh:
             h.update(fh.read())
+    path, begin, end = decls
+    with open(os.path.join(HERE, path), "rb") as fh:
+        text = fh.read()
+    i, j = text.find(begin), text.find(end)
+    if i < 0 or j < i:
+        raise ValueError(f"star declarations not found in {path}")
+    h.update(text[i:j])
     return h.hexdigest()[:16]
 
 

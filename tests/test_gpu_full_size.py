@@ -97,3 +97,58 @@ def test_join_2pow28_probes_exact(d):
     cx.check_status(st)
     assert tuple(res) == oracle.join_sum(t.dim_key, t.dim_val, t.fk)
     assert res[1] == 1 << 28
+
+
+def _is_permutation(idx, n):
+    seen = np.zeros(n, dtype=bool)
+    seen[idx] = True
+    return bool(seen.all())
+
+
+def test_partition_2pow28_properties():
+    """2^28 pairs, 8 bits at bit 24, values = input positions.  A stable
+    partition is unique: partition bounds equal the digit histogram's prefix,
+    every key sits in its digit's partition, the values are a permutation
+    that carries each key along, and increase within every partition."""
+    announce("full radix partition 2^28")
+    n = 1 << 28
+    k, _ = datagen.radix_pairs(n)
+    k = k.view(np.uint32)
+    v = np.arange(n, dtype=np.uint32)
+    ok, ov, offs = cx.radix_partition(dev(k.view(np.int32)), 24, 8, vals=dev(v.view(np.int32)))
+    torch.cuda.synchronize()
+    ok, ov, offs = ok.cpu().numpy().view(np.uint32), ov.cpu().numpy().view(np.uint32), offs.cpu().numpy()
+    hist = np.bincount(k >> np.uint32(24), minlength=256)
+    assert np.array_equal(offs.astype(np.int64), np.concatenate([[0], np.cumsum(hist)]))
+    assert _is_permutation(ov, n)
+    assert np.array_equal(k[ov], ok)
+    dig = (ok >> np.uint32(24)).astype(np.int64)
+    assert np.all(np.diff(dig) >= 0)
+    same = dig[1:] == dig[:-1]
+    assert np.all(ov[1:][same] > ov[:-1][same])
+
+
+def test_sort_2pow28_properties():
+    """2^28 pairs sorted: keys non-decreasing, values (input positions) a
+    permutation that carries each key along, equal keys in input order --
+    which characterises the stable sort the oracle defines.  A sample of
+    2^20 pairs is also sorted by the oracle and compared exactly."""
+    announce("full radix sort 2^28")
+    n = 1 << 28
+    k, _ = datagen.radix_pairs(n)
+    k = k.view(np.uint32)
+    v = np.arange(n, dtype=np.uint32)
+    ok, ov = cx.sort_pairs(dev(k.view(np.int32)), dev(v.view(np.int32)))
+    torch.cuda.synchronize()
+    ok, ov = ok.cpu().numpy().view(np.uint32), ov.cpu().numpy().view(np.uint32)
+    assert np.all(ok[1:] >= ok[:-1])
+    assert _is_permutation(ov, n)
+    assert np.array_equal(k[ov], ok)
+    same = ok[1:] == ok[:-1]
+    assert same.sum() > 0
+    assert np.all(ov[1:][same] > ov[:-1][same])
+    m = 1 << 20
+    sk, sv = cx.sort_pairs(dev(k[:m].view(np.int32)), dev(v[:m].view(np.int32)))
+    wk, wv = oracle.sort_pairs(k[:m], v[:m])
+    assert np.array_equal(sk.cpu().numpy().view(np.uint32), wk)
+    assert np.array_equal(sv.cpu().numpy().view(np.uint32), wv)
