@@ -315,12 +315,13 @@ def main():
                 step()
             torch.cuda.synchronize()
             elapsed = time.perf_counter() - t0
-            # the kernel's own duration: HIP events on its stream around each eager
-            # crystal_run_star_query (a 56 KB clear of the group array + the fused kernel);
-            # graph launches would add their launch overhead to the bracket
+            # the kernel's own duration: HIP events on its stream around each eager launch of
+            # the fused kernel alone (the group array is cleared before the bracket and the
+            # query accumulates into it); a graph launch would add its overhead to the bracket
             timer = Timer(torch)
             for _ in range(K):
-                timer.run(lambda: plan.run(out=out, status=status, stream=stream), stream)
+                out.zero_()
+                timer.run(lambda: plan.run(out=out, status=status, stream=stream, accumulate=True), stream)
             torch.cuda.synchronize()
         cx.check_status(status)
         cx.check_status(s.status)

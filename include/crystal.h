@@ -257,6 +257,15 @@ crystal_status crystal_run_star_query(const crystal_star_query *q, int64_t *out,
                                       int32_t *status, void *scratch, size_t scratch_bytes,
                                       void *stream);
 
+/* Same as crystal_run_star_query, but adds the query's result into out
+ * instead of overwriting it (wrapping modulo 2^64), so one query can be
+ * answered over successive row ranges (plans whose cols point at each range
+ * in turn) or a caller can clear out itself.  Nothing else is launched
+ * besides the query kernel and, for a scalar result, its finalize kernel. */
+crystal_status crystal_run_star_query_accumulate(const crystal_star_query *q, int64_t *out,
+                                                 int32_t *status, void *scratch, size_t scratch_bytes,
+                                                 void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Shared-scan batches: up to CRYSTAL_MAX_BATCH queries of one star-query    */
 /* template (same columns, predicate columns, joins, group spec, aggregate;  */

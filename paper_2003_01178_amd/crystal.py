@@ -116,6 +116,7 @@ def _declare(lib):
         "crystal_groupby_agg": (c_i32, [c_vp, c_vp, c_i64, c_i64, c_vp, c_vp, c_vp]),
         "crystal_star_query_scratch_bytes": (ctypes.c_size_t, [P(StarQueryC)]),
         "crystal_run_star_query": (c_i32, [P(StarQueryC), c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp]),
+        "crystal_run_star_query_accumulate": (c_i32, [P(StarQueryC), c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp]),
         "crystal_qmask_bytes": (ctypes.c_size_t, [c_i64]),
         "crystal_qmask_build": (c_i32, [P(QmaskTableC), c_vp, c_vp, c_i64, P(Range), c_i32, c_vp, c_vp]),
         "crystal_run_shared_scan": (c_i32, [P(BatchC), c_vp, c_vp]),
@@ -355,13 +356,16 @@ class StarQuery:
         self.scratch = torch.empty(max(16, nbytes), dtype=torch.uint8, device=dev) if nbytes else None
         self.scratch_bytes = nbytes
 
-    def run(self, out=None, status=None, stream=None):
+    def run(self, out=None, status=None, stream=None, accumulate=False):
+        """Run the query into out (overwritten), or add into out with accumulate=True."""
         lib = load()
         dev = self.cols[0].device if self.cols else "cuda"
-        out = torch.empty(self.n_groups, dtype=torch.int64, device=dev) if out is None else out
+        if out is None:
+            out = (torch.zeros if accumulate else torch.empty)(self.n_groups, dtype=torch.int64, device=dev)
         status = new_status(dev) if status is None else status
-        _check(lib.crystal_run_star_query(ctypes.byref(self.c), _ptr(out), _ptr(status), _ptr(self.scratch),
-                                          self.scratch_bytes, _stream(stream)), "crystal_run_star_query")
+        fn = lib.crystal_run_star_query_accumulate if accumulate else lib.crystal_run_star_query
+        _check(fn(ctypes.byref(self.c), _ptr(out), _ptr(status), _ptr(self.scratch), self.scratch_bytes,
+                  _stream(stream)), "crystal_run_star_query")
         return out, status
 
 

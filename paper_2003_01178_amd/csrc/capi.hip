@@ -354,8 +354,8 @@ size_t crystal_star_query_scratch_bytes(const crystal_star_query *q) {
     return (size_t)star_max_grid(q->n_rows) * 8;
 }
 
-crystal_status crystal_run_star_query(const crystal_star_query *q, int64_t *out, int32_t *status,
-                                      void *scratch, size_t scratch_bytes, void *stream) {
+static crystal_status run_star(const crystal_star_query *q, int64_t *out, int32_t *status, void *scratch,
+                               size_t scratch_bytes, void *stream, bool accumulate) {
     if (!q || !out || !status) return CRYSTAL_EINVAL;
     StarPlanDev d;
     crystal_status st = star_plan_to_dev(*q, d);
@@ -365,7 +365,17 @@ crystal_status crystal_run_star_query(const crystal_star_query *q, int64_t *out,
         if (scratch_bytes < (size_t)star_max_grid(q->n_rows) * 8) return CRYSTAL_ESCRATCH;
     }
     return from_hip(launch_star(tune_lookup(CRYSTAL_K_STAR, q->n_rows), d, (uint64_t *)out, status,
-                                (uint64_t *)scratch, as_stream(stream)));
+                                (uint64_t *)scratch, accumulate, as_stream(stream)));
+}
+
+crystal_status crystal_run_star_query(const crystal_star_query *q, int64_t *out, int32_t *status,
+                                      void *scratch, size_t scratch_bytes, void *stream) {
+    return run_star(q, out, status, scratch, scratch_bytes, stream, false);
+}
+
+crystal_status crystal_run_star_query_accumulate(const crystal_star_query *q, int64_t *out, int32_t *status,
+                                                 void *scratch, size_t scratch_bytes, void *stream) {
+    return run_star(q, out, status, scratch, scratch_bytes, stream, true);
 }
 
 // ------------------------------------------------------------ shared scan --
@@ -463,8 +473,8 @@ crystal_status crystal_graph_destroy(crystal_graph *g) {
 static bool radix_args_ok(const uint32_t *keys, const uint32_t *vals, int64_t n, const uint32_t *ok,
                           const uint32_t *ov) {
     if (n < 0 || n > (int64_t)UINT32_MAX - 1) return false;
+    if (n == 0) return true;  // nothing is read or written
     if ((vals == nullptr) != (ov == nullptr)) return false;
-    if (n == 0) return true;
     if (!keys || !ok || ((uintptr_t)keys & 3u) || ((uintptr_t)ok & 3u)) return false;
     if (vals && (((uintptr_t)vals & 3u) || ((uintptr_t)ov & 3u))) return false;
     // outputs must not overlap inputs

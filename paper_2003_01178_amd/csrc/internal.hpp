@@ -140,8 +140,9 @@ hipError_t launch_qmask_build(uint16_t *table, int64_t span, int32_t key_min, co
                               const int32_t *filter_col, int64_t n, const QmaskRanges &r, int32_t *status,
                               hipStream_t s);
 hipError_t launch_shared_scan(const LaunchCfg &cfg, const BatchDev &b, int32_t *status, hipStream_t s);
+// accumulate: add into out instead of overwriting it
 hipError_t launch_star(const LaunchCfg &cfg, const StarPlanDev &plan, uint64_t *out,
-                       int32_t *status, uint64_t *partials, hipStream_t s);
+                       int32_t *status, uint64_t *partials, bool accumulate, hipStream_t s);
 
 // ----------------------------------------------------------------- radix --
 // Scratch of one partition pass (count matrix + digit totals) under cfg.

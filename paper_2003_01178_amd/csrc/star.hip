@@ -351,12 +351,12 @@ __global__ __launch_bounds__(BLOCK) void star_kernel(const StarPlanDev p, uint64
 
 // Sum of the per-workgroup partials of a scalar query.
 __global__ __launch_bounds__(256) void star_finalize_kernel(const uint64_t *__restrict__ partials, int64_t n,
-                                                            uint64_t *__restrict__ out) {
+                                                            uint64_t *__restrict__ out, int accumulate) {
     __shared__ uint64_t red[4];
     uint64_t s = 0;
     for (int64_t i = threadIdx.x; i < n; i += 256) s += partials[i];
     s = block_sum_u64<256>(s, red);
-    if (threadIdx.x == 0) out[0] = s;
+    if (threadIdx.x == 0) out[0] = accumulate ? out[0] + s : s;
 }
 
 // ------------------------------------------------------------------ host ---
@@ -374,7 +374,7 @@ int64_t star_max_grid(int64_t n_rows) {
 
 template <int BLOCK, int IPT>
 static hipError_t star_t(const LaunchCfg &cfg, StarPlanDev p, uint64_t *out, int32_t *status,
-                         uint64_t *partials, hipStream_t s) {
+                         uint64_t *partials, bool accumulate, hipStream_t s) {
     using T = TileShape<BLOCK, IPT>;
     const int64_t n_tiles = (p.n_rows + T::ITEMS - 1) / T::ITEMS;
     // LDS: staged bitmaps of presence-only direct joins among the dense steps, then the queue
@@ -417,19 +417,20 @@ static hipError_t star_t(const LaunchCfg &cfg, StarPlanDev p, uint64_t *out, int
                        partials);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !p.scalar) return e;
-    hipLaunchKernelGGL(star_finalize_kernel, dim3(1), dim3(256), 0, s, partials, grid, out);
+    hipLaunchKernelGGL(star_finalize_kernel, dim3(1), dim3(256), 0, s, partials, grid, out, accumulate ? 1 : 0);
     return hipGetLastError();
 }
 
 hipError_t launch_star(const LaunchCfg &cfg, const StarPlanDev &plan, uint64_t *out, int32_t *status,
-                       uint64_t *partials, hipStream_t s) {
-    if (!plan.scalar) {
+                       uint64_t *partials, bool accumulate, hipStream_t s) {
+    if (!plan.scalar && !accumulate) {
         hipError_t e = fill_u64(out, plan.n_groups, 0ull, s);
         if (e != hipSuccess) return e;
     }
-    if (plan.n_rows == 0) return plan.scalar ? fill_u64(out, 1, 0ull, s) : hipSuccess;
+    if (plan.n_rows == 0) return plan.scalar && !accumulate ? fill_u64(out, 1, 0ull, s) : hipSuccess;
     switch (CRYSTAL_VARIANT_KEY(cfg.block, cfg.ipt)) {
-#define X(B, I) case CRYSTAL_VARIANT_KEY(B, I): return star_t<B, I>(cfg, plan, out, status, partials, s);
+#define X(B, I) \
+    case CRYSTAL_VARIANT_KEY(B, I): return star_t<B, I>(cfg, plan, out, status, partials, accumulate, s);
         CRYSTAL_VARIANTS_VEC(X)
 #undef X
     default: return hipErrorInvalidValue;

@@ -43,8 +43,8 @@ class Q11Plan:
             preds=[(0, lo, hi), (1, disc[0], disc[1]), (2, cx.I32_MIN, qty_max)],
             agg=cx.AGG_SUM_PRODUCT, agg_cols=(3, 1))
 
-    def run(self, out=None, status=None, stream=None):
-        return self.query.run(out=out, status=status, stream=stream)
+    def run(self, out=None, status=None, stream=None, accumulate=False):
+        return self.query.run(out=out, status=status, stream=stream, accumulate=accumulate)
 
 
 class StarSchema:

@@ -72,6 +72,40 @@ def test_star_matches_oracle(star_small, order):
     assert np.array_equal(out.cpu().numpy(), want)
 
 
+def test_star_accumulate_over_row_ranges(star_small):
+    """crystal_run_star_query_accumulate: the query over three row ranges,
+    each a plan on column slices, adds up to the whole query; a second run
+    into the same output doubles it (modulo 2^64)."""
+    announce("star accumulate")
+    t, s = star_small
+    want, _ = star_oracle(t)
+    s.status.zero_()
+    s.build()
+    full = s.plan()
+    cuts = [0, 400_000, 400_004 + 4 * 30_001, t.n]
+    out = torch.zeros(STAR_GROUPS, dtype=torch.int64, device="cuda")
+    status = cx.new_status()
+    for a, b in zip(cuts[:-1], cuts[1:]):
+        part = cx.StarQuery([c[a:b] for c in full.cols], n_groups=STAR_GROUPS, joins=full.joins,
+                            agg=cx.AGG_SUM, agg_cols=(4, 0))
+        part.run(out=out, status=status, accumulate=True)
+    cx.check_status(status)
+    assert np.array_equal(out.cpu().numpy(), want)
+    full.run(out=out, status=status, accumulate=True)
+    cx.check_status(status)
+    assert np.array_equal(out.cpu().numpy(), (want.astype(np.uint64) * np.uint64(2)).astype(np.int64))
+
+
+def test_q11_accumulate():
+    announce("q11 accumulate")
+    f = datagen.q11_fact(300_001, workload=43)
+    plan = queries.Q11Plan(*q11_dev(f))
+    out = torch.full((1,), 5, dtype=torch.int64, device="cuda")
+    plan.run(out=out, accumulate=True)
+    plan.run(out=out, accumulate=True)
+    assert int(out.item()) == 5 + 2 * q11_oracle(f)
+
+
 def test_star_random_constants(star_small):
     t, s = star_small
     rng = np.random.default_rng(8)
