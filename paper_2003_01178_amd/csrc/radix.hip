@@ -60,9 +60,10 @@ __device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t x) {
 }
 
 // Exclusive prefix of x over threads 0 .. BLOCK-1 in thread order; `tmp` holds
-// one word per wave.  Every thread calls it; it ends with a barrier, after
-// which tmp may be reused.
-template <int BLOCK>
+// one word per wave.  Every thread calls it.  With TRAIL it ends with a
+// barrier, after which tmp may be reused; without, the caller must pass a
+// barrier before tmp is written again.
+template <int BLOCK, bool TRAIL = true>
 __device__ __forceinline__ uint32_t block_exclusive_scan_u32(uint32_t x, uint32_t *tmp, uint32_t &total) {
     constexpr int W = BLOCK / kWave;
     const uint32_t inc = wave_inclusive_scan(x);
@@ -77,7 +78,7 @@ __device__ __forceinline__ uint32_t block_exclusive_scan_u32(uint32_t x, uint32_
         tot += t;
     }
     total = tot;
-    __syncthreads();
+    if (TRAIL) __syncthreads();
     return before + inc - x;
 }
 
@@ -181,22 +182,31 @@ struct ShuffleLds {
     static constexpr size_t BYTES = (size_t)WORDS * 4;
 };
 
+// The tile starting at `base`: slot k of this lane is item off0 + 64 k.  The
+// tile's base pointers are made opaque to the compiler so that it addresses
+// every item from one scalar base and one lane offset, instead of carrying a
+// 64-bit address per item from tile to tile.
 template <int BLOCK, int IPT, bool VALS>
 __device__ __forceinline__ void load_tile(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ vals,
-                                          int64_t base, int64_t n, uint32_t (&key)[IPT], uint32_t (&val)[IPT]) {
+                                          int64_t base, int rem, int off0, uint32_t (&key)[IPT],
+                                          uint32_t (&val)[IPT]) {
     using RT = RadixTile<BLOCK, IPT>;
-    if (base + RT::ITEMS <= n) {
+    const uint32_t *kb = keys + base;
+    const uint32_t *vb = VALS ? vals + base : nullptr;
+    asm volatile("" : "+s"(kb));
+    if (VALS) asm volatile("" : "+s"(vb));
+    if (rem >= RT::ITEMS) {
 #pragma unroll
         for (int k = 0; k < IPT; ++k) {
-            key[k] = __builtin_nontemporal_load(keys + base + RT::offset(k));
-            if (VALS) val[k] = __builtin_nontemporal_load(vals + base + RT::offset(k));
+            key[k] = __builtin_nontemporal_load(kb + off0 + k * kWave);
+            if (VALS) val[k] = __builtin_nontemporal_load(vb + off0 + k * kWave);
         }
     } else {
 #pragma unroll
         for (int k = 0; k < IPT; ++k) {
-            const int64_t i = base + RT::offset(k);
-            key[k] = i < n ? keys[i] : 0u;
-            if (VALS) val[k] = i < n ? vals[i] : 0u;
+            const int i = off0 + k * kWave;
+            key[k] = i < rem ? kb[i] : 0u;
+            if (VALS) val[k] = i < rem ? vb[i] : 0u;
         }
     }
 }
@@ -243,24 +253,31 @@ __global__ __launch_bounds__(BLOCK) void radix_shuffle_kernel(
     if (t1 > n_tiles) t1 = n_tiles;
     if (t0 >= t1) return;
 
+    // slot k of this lane sits at tile offset off0 + 64 k
+    const int off0 = RT::offset(0);
+    auto items_from = [&](int64_t b) { return n - b >= RT::ITEMS ? RT::ITEMS : (int)(n - b); };
     uint32_t key[IPT], val[IPT];
-    load_tile<BLOCK, IPT, VALS>(keys, vals, t0 * RT::ITEMS, n, key, val);
+    load_tile<BLOCK, IPT, VALS>(keys, vals, t0 * RT::ITEMS, items_from(t0 * RT::ITEMS), off0, key, val);
     for (int64_t t = t0; t < t1; ++t) {
         const int64_t base = t * RT::ITEMS;
-        const bool full = base + RT::ITEMS <= n;
+        const int rem = items_from(base);  // items in this tile
+        int tidv = tid;                    // opaque: keeps per-item offsets out of registers
+        asm volatile("" : "+v"(tidv));
         // 1. rank every item among the wave's earlier items of its digit
         uint32_t rank[IPT];
 #pragma unroll
         for (int k = 0; k < IPT; ++k) {
-            const bool valid = full || base + RT::offset(k) < n;
+            const bool valid = off0 + k * kWave < rem;
             const uint32_t d = digit_of(key[k], shift, mask);
-            uint64_t peers = ballot(valid);
+            // lanes whose digit differs from this lane's in some bit
+            uint64_t diff = 0;
 #pragma unroll
             for (int b = 0; b < 8; ++b) {
                 const bool bit = (d >> b) & 1u;
                 const uint64_t m = ballot(bit);
-                peers &= bit ? m : ~m;
+                diff |= bit ? ~m : m;
             }
+            const uint64_t peers = ballot(valid) & ~diff;
             const uint32_t below = count_below(peers);
             const uint32_t same = (uint32_t)__popcll(peers);
             rank[k] = 0;
@@ -269,6 +286,9 @@ __global__ __launch_bounds__(BLOCK) void radix_shuffle_kernel(
                 rank[k] = c + below;
                 if (below + 1 == same) my_wc[d] = c + same;
             }
+            // one slot at a time: interleaving slots only raises register pressure,
+            // since each slot waits for the previous slot's counter update anyway
+            __builtin_amdgcn_sched_barrier(0);
         }
         __syncthreads();
         // 2. per digit: offsets of each wave's run inside the tile's run of
@@ -282,7 +302,8 @@ __global__ __launch_bounds__(BLOCK) void radix_shuffle_kernel(
                 cnt += c;
             }
         }
-        const uint32_t tstart = block_exclusive_scan_u32<BLOCK>(cnt, s_tmp, unused);
+        // no trailing barrier: s_tmp is next written after this tile's later barriers
+        const uint32_t tstart = block_exclusive_scan_u32<BLOCK, false>(cnt, s_tmp, unused);
         if (tid < kBins) {
 #pragma unroll
             for (int i = 0; i < RT::W; ++i) s_wc[i * kBins + tid] += tstart;
@@ -294,8 +315,7 @@ __global__ __launch_bounds__(BLOCK) void radix_shuffle_kernel(
         // 3. the tile, sorted by digit (stable), into LDS
 #pragma unroll
         for (int k = 0; k < IPT; ++k) {
-            const bool valid = full || base + RT::offset(k) < n;
-            if (valid) {
+            if (off0 + k * kWave < rem) {
                 const uint32_t p = my_wc[digit_of(key[k], shift, mask)] + rank[k];
                 s_keys[p] = key[k];
                 if (VALS) s_vals[p] = val[k];
@@ -303,21 +323,22 @@ __global__ __launch_bounds__(BLOCK) void radix_shuffle_kernel(
         }
         __syncthreads();
         // 4. next tile's loads go out while this one is written
-        if (t + 1 < t1) load_tile<BLOCK, IPT, VALS>(keys, vals, base + RT::ITEMS, n, key, val);
+        if (t + 1 < t1)
+            load_tile<BLOCK, IPT, VALS>(keys, vals, base + RT::ITEMS, items_from(base + RT::ITEMS), off0, key, val);
         if (tid < kBins) {
 #pragma unroll
             for (int i = 0; i < RT::W; ++i) s_wc[i * kBins + tid] = 0u;
         }
-        const int tile_n = full ? RT::ITEMS : (int)(n - base);
 #pragma unroll
         for (int j = 0; j < IPT; ++j) {
-            const int p = j * BLOCK + tid;
-            if (p < tile_n) {
+            const int p = j * BLOCK + tidv;
+            if (p < rem) {
                 const uint32_t k = s_keys[p];
-                const int64_t g = (int64_t)s_gbase[digit_of(k, shift, mask)] + p;
-                __builtin_nontemporal_store(k, out_keys + g);
-                if (VALS) __builtin_nontemporal_store(s_vals[p], out_vals + g);
+                const uint32_t g = s_gbase[digit_of(k, shift, mask)] + (uint32_t)p;  // < n < 2^32
+                out_keys[g] = k;
+                if (VALS) out_vals[g] = s_vals[p];
             }
+            if (j % 4 == 3) __builtin_amdgcn_sched_barrier(0);
         }
         __syncthreads();
     }
