@@ -165,9 +165,7 @@ def serve(args, torch, cx, datagen, queries, roof):
     single_qps = 64 / (time.perf_counter() - t0)
     seg = (n // args.segments + 3) // 4 * 4
     order = queries.DEFAULT_JOIN_ORDER
-    d = sv.s.dims
-    star = dict(plan=sv.star_template, dims=[(d[j]["key"], d[j]["filter"], d[j]["n"], sv.masks[j]) for j in order])
-    srv = cx.Server([star, dict(plan=sv.q11_template)], slots=16, segment_rows=seg, max_queue=1 << 16, inflight=2)
+    srv = cx.Server(sv.server_templates(), slots=16, segment_rows=seg, max_queue=1 << 16, inflight=2)
     per_rate = []
     checks = mismatches = 0
     try:
@@ -185,7 +183,7 @@ def serve(args, torch, cx, datagen, queries, roof):
                     if tp == 0:
                         tk = srv.submit(0, filters=[(c[j], c[j]) for j in order])
                     else:
-                        tk = srv.submit(1, preds=sv.q11_preds(*c))
+                        tk = srv.submit(1, **sv.q11_request(*c))
                     if tk is not None:
                         pending[tk] = (tp, c)
                         submitted += 1
@@ -217,7 +215,7 @@ def serve(args, torch, cx, datagen, queries, roof):
         for k in range(256):
             tp, c = draw(k)
             tk = srv.submit(0, filters=[(c[j], c[j]) for j in order]) if tp == 0 else srv.submit(
-                1, preds=sv.q11_preds(*c))
+                1, **sv.q11_request(*c))
             tks.append((tk, tp))
         left = dict(tks)
         while left:

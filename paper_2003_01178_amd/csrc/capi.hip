@@ -75,7 +75,7 @@ static LaunchCfg default_cfg(int kernel) {
     case CRYSTAL_K_HT_PROBE: return {256, 16, 8};
     case CRYSTAL_K_GROUPBY: return {256, 16, 0};
     case CRYSTAL_K_STAR: return {256, 16, 0};
-    case CRYSTAL_K_SHARED_SCAN: return {256, 8, 0};
+    case CRYSTAL_K_SHARED_SCAN: return {512, 16, 0};
     case CRYSTAL_K_RADIX: return {1024, 16, 0};
     default: return {256, 16, 0};
     }

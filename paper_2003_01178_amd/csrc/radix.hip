@@ -101,32 +101,44 @@ __device__ __forceinline__ Chunk chunk_of(int64_t col, int sub, int64_t tiles_pe
 
 // ------------------------------------------------------------- histogram --
 // Column c of the count matrix counts the digits of sub-chunk c (sub-chunks
-// split each shuffle workgroup's chunk `sub` ways, in order).  MATRIX: write
-// counts[d * cols + c]; otherwise add into the global histogram counts[d].
-template <int BLOCK, int IPT, bool MATRIX>
-__global__ __launch_bounds__(BLOCK) void radix_hist_kernel(const uint32_t *__restrict__ keys, int64_t n,
-                                                           int shift, uint32_t mask, int64_t n_tiles,
-                                                           int64_t tiles_per_block, int sub,
-                                                           uint32_t *__restrict__ counts, int64_t cols) {
-    using RT = RadixTile<BLOCK, IPT>;
-    __shared__ uint32_t h[RT::W][kBins];
-    for (int i = threadIdx.x; i < RT::W * kBins; i += BLOCK) (&h[0][0])[i] = 0u;
+// split each shuffle workgroup's chunk `sub` ways, in order; chunks are whole
+// shuffle tiles of tile_items items).  MATRIX: write counts[d * cols + c];
+// otherwise add into the global histogram counts[d].  The counting workgroup
+// has its own shape: kHistBlock threads reading kHistIpt coalesced words each
+// per step, with one LDS digit histogram per wave.
+constexpr int kHistBlock = 256;
+constexpr int kHistIpt = 16;
+
+template <bool MATRIX>
+__global__ __launch_bounds__(kHistBlock) void radix_hist_kernel(const uint32_t *__restrict__ keys, int64_t n,
+                                                                int shift, uint32_t mask, int64_t tile_items,
+                                                                int64_t n_tiles, int64_t tiles_per_block, int sub,
+                                                                uint32_t *__restrict__ counts, int64_t cols) {
+    constexpr int W = kHistBlock / kWave;
+    constexpr int STEP = kHistBlock * kHistIpt;
+    __shared__ uint32_t h[W][kBins];
+    for (int i = threadIdx.x; i < W * kBins; i += kHistBlock) (&h[0][0])[i] = 0u;
     __syncthreads();
     const int w = threadIdx.x / kWave;
     const Chunk ch = chunk_of(blockIdx.x, sub, tiles_per_block, n_tiles);
-    for (int64_t t = ch.t0; t < ch.t1; ++t) {
-        const int64_t base = t * RT::ITEMS;
-        uint32_t v[IPT];
-        if (base + RT::ITEMS <= n) {
+    const int64_t i0 = ch.t0 * tile_items;
+    int64_t i1 = ch.t1 * tile_items;
+    if (i1 > n) i1 = n;
+    for (int64_t b = i0; b < i1; b += STEP) {
+        const uint32_t *kb = keys + b;
+        asm volatile("" : "+s"(kb));
+        const int64_t left = i1 - b;
+        if (left >= STEP) {
+            uint32_t v[kHistIpt];
 #pragma unroll
-            for (int k = 0; k < IPT; ++k) v[k] = keys[base + RT::offset(k)];
+            for (int k = 0; k < kHistIpt; ++k) v[k] = __builtin_nontemporal_load(kb + k * kHistBlock + threadIdx.x);
 #pragma unroll
-            for (int k = 0; k < IPT; ++k) atomicAdd(&h[w][digit_of(v[k], shift, mask)], 1u);
+            for (int k = 0; k < kHistIpt; ++k) atomicAdd(&h[w][digit_of(v[k], shift, mask)], 1u);
         } else {
 #pragma unroll
-            for (int k = 0; k < IPT; ++k) {
-                const int64_t i = base + RT::offset(k);
-                if (i < n) atomicAdd(&h[w][digit_of(keys[i], shift, mask)], 1u);
+            for (int k = 0; k < kHistIpt; ++k) {
+                const int i = k * kHistBlock + (int)threadIdx.x;
+                if (i < left) atomicAdd(&h[w][digit_of(kb[i], shift, mask)], 1u);
             }
         }
     }
@@ -135,7 +147,7 @@ __global__ __launch_bounds__(BLOCK) void radix_hist_kernel(const uint32_t *__res
     if (d < kBins && (uint32_t)d <= mask) {
         uint32_t s = 0;
 #pragma unroll
-        for (int i = 0; i < RT::W; ++i) s += h[i][d];
+        for (int i = 0; i < W; ++i) s += h[i][d];
         if (MATRIX)
             counts[(int64_t)d * cols + blockIdx.x] = s;
         else if (s)
@@ -374,12 +386,13 @@ struct RadixKernels {
 
     static hipError_t histogram(const uint32_t *keys, int64_t n, int shift, uint32_t mask, const RadixGeom &g,
                                 uint32_t *counts, bool matrix, hipStream_t s) {
-        const dim3 grid((unsigned)(g.grid * g.sub)), block(BLOCK);
+        const dim3 grid((unsigned)(g.grid * g.sub)), block(kHistBlock);
+        const int64_t items = (int64_t)BLOCK * IPT;
         if (matrix)
-            hipLaunchKernelGGL((radix_hist_kernel<BLOCK, IPT, true>), grid, block, 0, s, keys, n, shift, mask,
+            hipLaunchKernelGGL((radix_hist_kernel<true>), grid, block, 0, s, keys, n, shift, mask, items,
                                g.n_tiles, g.tiles_per_block, g.sub, counts, g.cols);
         else
-            hipLaunchKernelGGL((radix_hist_kernel<BLOCK, IPT, false>), grid, block, 0, s, keys, n, shift, mask,
+            hipLaunchKernelGGL((radix_hist_kernel<false>), grid, block, 0, s, keys, n, shift, mask, items,
                                g.n_tiles, g.tiles_per_block, g.sub, counts, g.cols);
         return hipGetLastError();
     }

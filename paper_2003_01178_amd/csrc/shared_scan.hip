@@ -58,37 +58,46 @@ hipError_t launch_qmask_build(uint16_t *table, int64_t span, int32_t key_min, co
 }
 
 // ---------------------------------------------------------- shared scan ----
-__device__ __forceinline__ int shared_step_col(const StarPlanDev &p, int s) {
-    return s < p.n_preds ? p.pred_col[s] : p.joins[s - p.n_preds].fk_col;
+// The VEC rows from row0 of a column, read as one vector when one of them is
+// flagged in `sel` (items past row_end are never read).
+template <int VEC>
+__device__ __forceinline__ void load_vec_sel(const int32_t *__restrict__ col, int64_t row0, int64_t row_end,
+                                             uint32_t sel, int32_t (&dst)[VEC]) {
+    if (!sel) return;
+    if (row0 + VEC <= row_end) {
+        load_vec<VEC, true>(col + row0, dst);
+    } else {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e)
+            if ((sel >> e) & 1u) dst[e] = col[row0 + e];
+    }
 }
 
-// Group index of one surviving row from the template's dimension payloads.
-__device__ __forceinline__ int64_t shared_group(const StarPlanDev &p, int64_t row) {
-    int64_t g = 0;
-    for (int jj = 0; jj < p.n_joins; ++jj) {
-        const StarJoinDev &j = p.joins[jj];
-        if (j.g_bits == 0) continue;
-        const int32_t key = p.cols[j.fk_col][row];
-        int32_t pay = 0;
-        if (j.kind == CRYSTAL_HT_DIRECT) {
-            const uint32_t off = (uint32_t)key - (uint32_t)j.key_min;
-            if ((int64_t)off < j.span && j.payload) pay = j.payload[off];
-        } else if (key != kEmptyKey) {
-            probe_linear((const v2i *)j.slots, j.mask, j.shift, key, pay);
-        }
-        g += ((int64_t)payload_field(pay, j.g_shift, j.g_mask, j.g_bits) - (int64_t)j.g_base) * j.g_stride;
-    }
-    return g;
+__device__ __forceinline__ int shared_step_col(const StarPlanDev &p, int s) {
+    return s < p.n_preds ? p.pred_col[s] : p.joins[s - p.n_preds].fk_col;
 }
 
 template <int BLOCK, int IPT>
 __global__ __launch_bounds__(BLOCK) void shared_scan_kernel(const BatchDev b, int32_t *status, int64_t n_tiles) {
     using T = TileShape<BLOCK, IPT>;
-    __shared__ uint64_t acc[kMaxBatch];
+    // scalar results: one private LDS accumulator per (query, thread), so that
+    // survivors add without atomics; reduced once per workgroup at the end
+    // dynamic LDS: b.n_queries * BLOCK words for a scalar plan, then the
+    // staged mask table of the first join (see BatchDev::stage_off)
+    extern __shared__ uint64_t dyn[];
+    uint64_t(*acc)[BLOCK] = reinterpret_cast<uint64_t(*)[BLOCK]>(dyn);
+    uint32_t *stage_words = reinterpret_cast<uint32_t *>(dyn + b.stage_off);
+    const uint16_t *stage = reinterpret_cast<const uint16_t *>(dyn + b.stage_off);
+    __shared__ uint64_t red[BLOCK / kWave];
     const StarPlanDev &p = b.plan;
     const int n_steps = p.n_preds + p.n_joins;
     if (p.scalar) {
-        if (threadIdx.x < kMaxBatch) acc[threadIdx.x] = 0;
+        for (int q = 0; q < b.n_queries; ++q) acc[q][threadIdx.x] = 0;
+    }
+    const bool staged = b.stage_words > 0;
+    if (staged) {
+        const uint32_t *src = reinterpret_cast<const uint32_t *>(b.mask[0]);
+        for (int64_t i = threadIdx.x; i < b.stage_words; i += BLOCK) stage_words[i] = src[i];
         __syncthreads();
     }
     bool bad_group = false;
@@ -111,74 +120,161 @@ __global__ __launch_bounds__(BLOCK) void shared_scan_kernel(const BatchDev b, in
                 block_load_sel<BLOCK, IPT, true>(p.cols[col], base, b.row_end, any, v);
             }
             if (s < p.n_preds) {
+                // queries outer, items inner: each query's bounds are uniform, and
+                // a query no row of the wave is still alive for is skipped
+                uint32_t lane_live = 0, m[IPT];
 #pragma unroll
                 for (int k = 0; k < IPT; ++k) {
-                    uint32_t m = 0;
-                    for (int q = 0; q < b.n_queries; ++q)
-                        m |= (uint32_t)in_range(v[k], b.pred_lo[q][s], b.pred_hi[q][s]) << q;
-                    qm[k] &= m;
+                    lane_live |= qm[k];
+                    m[k] = 0;
                 }
+                for (int q = 0; q < b.n_queries; ++q) {
+                    const uint32_t bit = 1u << q;
+                    if (ballot((lane_live & bit) != 0u) == 0) continue;
+                    const int32_t lo = b.pred_lo[q][s], hi = b.pred_hi[q][s];
+#pragma unroll
+                    for (int k = 0; k < IPT; ++k) m[k] |= in_range(v[k], lo, hi) ? bit : 0u;
+                }
+#pragma unroll
+                for (int k = 0; k < IPT; ++k) qm[k] &= m[k];
             } else {
                 const int j = s - p.n_preds;
-                const uint16_t *mt = b.mask[j];
                 const uint32_t last = (uint32_t)(b.mask_span[j] - 1);
                 const int32_t kmin = b.mask_kmin[j];
+                if (j == 0 && staged) {
+                    // LDS-typed path (a pointer that may also address global
+                    // memory would compile to flat loads)
 #pragma unroll
-                for (int k = 0; k < IPT; ++k) {
-                    const uint32_t off = (uint32_t)v[k] - (uint32_t)kmin;
-                    const bool in = qm[k] != 0u && off <= last;
-                    qm[k] &= in ? (uint32_t)mt[off] : 0u;
+                    for (int k = 0; k < IPT; ++k) {
+                        const uint32_t off = (uint32_t)v[k] - (uint32_t)kmin;
+                        const bool in = qm[k] != 0u && off <= last;
+                        qm[k] &= in ? (uint32_t)stage[off] : 0u;
+                    }
+                } else {
+                    const uint16_t *mt = b.mask[j];
+#pragma unroll
+                    for (int k = 0; k < IPT; ++k) {
+                        const uint32_t off = (uint32_t)v[k] - (uint32_t)kmin;
+                        const bool in = qm[k] != 0u && off <= last;
+                        qm[k] &= in ? (uint32_t)mt[off] : 0u;
+                    }
                 }
             }
         }
-        // survivors: group index and measure once, then every query that kept the row
+        // survivors: the measure and group index once per row, then every query
+        // that kept the row.  A vector of VEC rows is handled at a time: its
+        // loads (measures, then group keys, then their payloads) are issued
+        // together whenever one of its rows survives, so a vector pays one
+        // memory round trip per load step instead of one per surviving row,
+        // and only one vector's values are live at a time.
+        uint32_t surv = 0;
 #pragma unroll
-        for (int k = 0; k < IPT; ++k) {
-            uint32_t m = qm[k];
-            if (!m) continue;
-            const int64_t row = T::index(base, k / T::VEC, k % T::VEC);
-            const int64_t g = p.scalar ? 0 : shared_group(p, row);
-            uint64_t val = 1;
-            if (p.agg != CRYSTAL_AGG_COUNT) {
-                const int64_t a = p.cols[p.agg_col0][row];
-                if (p.agg == CRYSTAL_AGG_SUM) {
-                    val = (uint64_t)a;
-                } else {
-                    const int64_t c = p.cols[p.agg_col1][row];
-                    val = p.agg == CRYSTAL_AGG_SUM_PRODUCT ? (uint64_t)(a * c) : (uint64_t)(a - c);
+        for (int k = 0; k < IPT; ++k) surv |= (uint32_t)(qm[k] != 0u) << k;
+        if (ballot(surv != 0u) == 0) continue;
+#pragma unroll
+        for (int ch = 0; ch < T::CHUNKS; ++ch) {
+            const uint32_t sc = (surv >> (ch * T::VEC)) & T::VMASK;
+            if (ballot(sc != 0u) == 0) continue;
+            const int64_t row0 = T::index(base, ch, 0);
+            int32_t a[T::VEC], c[T::VEC];
+            int64_t g[T::VEC];
+#pragma unroll
+            for (int e = 0; e < T::VEC; ++e) g[e] = 0;
+            if (p.agg != CRYSTAL_AGG_COUNT) load_vec_sel<T::VEC>(p.cols[p.agg_col0], row0, b.row_end, sc, a);
+            if (p.agg == CRYSTAL_AGG_SUM_PRODUCT || p.agg == CRYSTAL_AGG_SUM_DIFF)
+                load_vec_sel<T::VEC>(p.cols[p.agg_col1], row0, b.row_end, sc, c);
+            if (!p.scalar) {
+                for (int jj = 0; jj < p.n_joins; ++jj) {
+                    const StarJoinDev &j = p.joins[jj];
+                    if (j.g_bits == 0) continue;
+                    int32_t fk[T::VEC], pay[T::VEC];
+                    load_vec_sel<T::VEC>(p.cols[j.fk_col], row0, b.row_end, sc, fk);
+#pragma unroll
+                    for (int e = 0; e < T::VEC; ++e) {
+                        pay[e] = 0;
+                        if (!((sc >> e) & 1u)) continue;
+                        if (j.kind == CRYSTAL_HT_DIRECT) {
+                            const uint32_t off = (uint32_t)fk[e] - (uint32_t)j.key_min;
+                            if ((int64_t)off < j.span && j.payload) pay[e] = j.payload[off];
+                        } else if (fk[e] != kEmptyKey) {
+                            probe_linear((const v2i *)j.slots, j.mask, j.shift, fk[e], pay[e]);
+                        }
+                    }
+#pragma unroll
+                    for (int e = 0; e < T::VEC; ++e)
+                        g[e] += ((int64_t)payload_field(pay[e], j.g_shift, j.g_mask, j.g_bits) - (int64_t)j.g_base) *
+                                j.g_stride;
                 }
             }
-            if (!p.scalar && (uint64_t)g >= (uint64_t)p.n_groups) {
-                bad_group = true;
-                continue;
+#pragma unroll
+            for (int e = 0; e < T::VEC; ++e) {
+                uint32_t m = qm[ch * T::VEC + e];
+                if (!m) continue;
+                uint64_t val = 1;
+                if (p.agg == CRYSTAL_AGG_SUM)
+                    val = (uint64_t)(int64_t)a[e];
+                else if (p.agg == CRYSTAL_AGG_SUM_PRODUCT)
+                    val = (uint64_t)((int64_t)a[e] * (int64_t)c[e]);
+                else if (p.agg == CRYSTAL_AGG_SUM_DIFF)
+                    val = (uint64_t)((int64_t)a[e] - (int64_t)c[e]);
+                if (!p.scalar && (uint64_t)g[e] >= (uint64_t)p.n_groups) {
+                    bad_group = true;
+                    continue;
+                }
+                while (m) {
+                    const int q = __builtin_ctz(m);
+                    m &= m - 1u;
+                    if (p.scalar)
+                        acc[q][threadIdx.x] += val;
+                    else
+                        atomic_add_u64(b.out[q] + g[e], val);
+                }
             }
-            while (m) {
-                const int q = __builtin_ctz(m);
-                m &= m - 1u;
-                if (p.scalar)
-                    atomicAdd((unsigned long long *)&acc[q], (unsigned long long)val);
-                else
-                    atomic_add_u64(b.out[q] + g, val);
-            }
+            __builtin_amdgcn_sched_barrier(0);
         }
     }
     if (bad_group) set_status(status, CRYSTAL_ERANGE);
     if (p.scalar) {
-        __syncthreads();
-        if (threadIdx.x < b.n_queries && acc[threadIdx.x]) atomic_add_u64(b.out[threadIdx.x], acc[threadIdx.x]);
+        for (int q = 0; q < b.n_queries; ++q) {
+            const uint64_t t = block_sum_u64<BLOCK>(acc[q][threadIdx.x], red);
+            if (threadIdx.x == 0 && t) atomic_add_u64(b.out[q], t);
+            __syncthreads();  // red is reused by the next query's sum
+        }
     }
 }
 
 template <int BLOCK, int IPT>
-static hipError_t shared_t(const LaunchCfg &cfg_in, const BatchDev &b, int32_t *status, hipStream_t s) {
+static hipError_t shared_t(const LaunchCfg &cfg_in, const BatchDev &b_in, int32_t *status, hipStream_t s) {
     using T = TileShape<BLOCK, IPT>;
+    BatchDev b = b_in;
     const int64_t rows = b.row_end - b.row_begin;
     const int64_t n_tiles = (rows + T::ITEMS - 1) / T::ITEMS;
     LaunchCfg cfg = cfg_in;
     if (cfg.grid_per_cu <= 0) cfg.grid_per_cu = (2048 / BLOCK) > 0 ? (2048 / BLOCK) : 1;
+    // LDS: the scalar accumulators, then the first join's mask table when it
+    // fits beside them without dropping below 8 waves per CU
+    const int64_t acc_words = b.plan.scalar ? (int64_t)b.n_queries * BLOCK : 0;
+    b.stage_off = acc_words;
+    b.stage_words = 0;
+    if (b.plan.n_joins > 0) {
+        const int64_t words = (b.mask_span[0] + 1) / 2;
+        const int64_t bytes = acc_words * 8 + words * 4;
+        const int64_t min_blocks = (8 * kWave + BLOCK - 1) / BLOCK;
+        const int64_t fit = device_lds_per_cu() / (bytes + 1024);
+        if (bytes + 1024 <= device_lds_per_block() && fit >= min_blocks) {
+            b.stage_words = words;
+            if (cfg.grid_per_cu > fit) cfg.grid_per_cu = (int)fit;
+        }
+    }
     const int64_t grid = grid_for(n_tiles, cfg);
     if (grid == 0) return hipSuccess;
-    hipLaunchKernelGGL((shared_scan_kernel<BLOCK, IPT>), dim3((unsigned)grid), dim3(BLOCK), 0, s, b, status,
+    const size_t lds = (size_t)(acc_words * 8 + b.stage_words * 4);
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void *)shared_scan_kernel<BLOCK, IPT>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((shared_scan_kernel<BLOCK, IPT>), dim3((unsigned)grid), dim3(BLOCK), lds, s, b, status,
                        n_tiles);
     return hipGetLastError();
 }

@@ -137,10 +137,53 @@ class ServingTemplates:
         self.star_template = cx.StarQuery(self.cols, n_groups=STAR_GROUPS, joins=joins, agg=cx.AGG_SUM,
                                           agg_cols=(4, 0))
         self.star_scan = cx.SharedScan(self.star_template, [self.masks[j] for j in DEFAULT_JOIN_ORDER])
-        self.q11_template = cx.StarQuery(self.cols, n_groups=1,
-                                         preds=[(0, 0, 0), (6, 0, 0), (7, 0, 0)],
+        # The Q1.1 template's three range predicates (datekey, discount,
+        # quantity) run as lookups into per-batch value -> query-mask tables
+        # over each column's value domain: a presence table over the domain
+        # and a query mask per value, built like a dimension's.  A row passes
+        # query q's range on a column iff its value's mask has bit q, which
+        # is the range test itself for every value of the domain.
+        date = schema.dims[0]
+        self.q11_domains = [
+            dict(key=date["key"], filter=date["key"], n=date["n"], key_min=date["key_min"],
+                 key_max=date["key_max"], fk_col=0),
+            self._domain(0, 10, 6, dev),                     # discount U{0..10}
+            self._domain(1, 50, 7, dev),                     # quantity U{1..50}
+        ]
+        q11_joins = []
+        for dm in self.q11_domains:
+            ht = cx.HashTable(cx.HT_DIRECT, dm["n"], dm["key_min"], dm["key_max"], has_payload=False, device=dev)
+            ht.build(dm["key"], status=self.status)
+            dm["table"] = ht
+            dm["mask"] = cx.QueryMask(dm["key_min"], dm["key_max"], device=dev)
+            q11_joins.append(dict(table=ht, fk_col=dm["fk_col"]))
+        self.q11_template = cx.StarQuery(self.cols, n_groups=1, joins=q11_joins,
                                          agg=cx.AGG_SUM_PRODUCT, agg_cols=(8, 6))
-        self.q11_scan = cx.SharedScan(self.q11_template, [])
+        self.q11_scan = cx.SharedScan(self.q11_template, [dm["mask"] for dm in self.q11_domains])
+
+    @staticmethod
+    def _domain(lo, hi, fk_col, dev):
+        keys = torch.arange(lo, hi + 1, dtype=torch.int32, device=dev)
+        return dict(key=keys, filter=keys, n=hi - lo + 1, key_min=lo, key_max=hi, fk_col=fk_col)
+
+    def server_templates(self):
+        """Template descriptions for cx.Server: 0 the star query, 1 Q1.1."""
+        d = self.s.dims
+        star = dict(plan=self.star_template,
+                    dims=[(d[j]["key"], d[j]["filter"], d[j]["n"], self.masks[j]) for j in DEFAULT_JOIN_ORDER])
+        q11 = dict(plan=self.q11_template,
+                   dims=[(dm["key"], dm["filter"], dm["n"], dm["mask"]) for dm in self.q11_domains])
+        return [star, q11]
+
+    @staticmethod
+    def star_request(consts):
+        """Keyword arguments of Server.submit for a star query (template 0)."""
+        return dict(filters=[(consts[j], consts[j]) for j in DEFAULT_JOIN_ORDER])
+
+    @classmethod
+    def q11_request(cls, year, disc_lo, qty_max):
+        """Keyword arguments of Server.submit for a Q1.1 query (template 1)."""
+        return dict(filters=cls.q11_preds(year, disc_lo, qty_max))
 
     @property
     def n_rows(self):
@@ -160,9 +203,14 @@ class ServingTemplates:
     def run_star_batch(self, outs, row_begin=0, row_end=None, status=None, stream=None):
         return self.star_scan.run([[] for _ in outs], outs, row_begin, row_end, status=status, stream=stream)
 
+    def build_q11_masks(self, consts_per_query, stream=None):
+        ranges = [self.q11_preds(*c) for c in consts_per_query]
+        for i, dm in enumerate(self.q11_domains):
+            dm["mask"].build(dm["key"], dm["filter"], [r[i] for r in ranges], status=self.status, stream=stream)
+
     def run_q11_batch(self, consts, outs, row_begin=0, row_end=None, status=None, stream=None):
-        preds = [self.q11_preds(*c) for c in consts]
-        return self.q11_scan.run(preds, outs, row_begin, row_end, status=status, stream=stream)
+        self.build_q11_masks(consts, stream=stream)
+        return self.q11_scan.run([[] for _ in outs], outs, row_begin, row_end, status=status, stream=stream)
 
     def single_star(self, consts):
         """The same star query as one plain launch (filtered builds)."""

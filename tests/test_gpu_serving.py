@@ -23,12 +23,8 @@ def setup():
 
 
 def make_server(sv, segment_rows=262_144, slots=16, inflight=2):
-    order = queries.DEFAULT_JOIN_ORDER
-    d = sv.s.dims
-    star = dict(plan=sv.star_template,
-                dims=[(d[j]["key"], d[j]["filter"], d[j]["n"], sv.masks[j]) for j in order])
-    return cx.Server([star, dict(plan=sv.q11_template)], slots=slots, segment_rows=segment_rows,
-                     max_queue=4096, inflight=inflight)
+    return cx.Server(sv.server_templates(), slots=slots, segment_rows=segment_rows, max_queue=4096,
+                     inflight=inflight)
 
 
 def wait_all(srv, tickets, timeout=60):
@@ -81,7 +77,7 @@ def test_mixed_queries_match_single_launch_and_oracle(setup):
                 submitted.append((tk, 0, c))
             else:
                 c = datagen.random_q11_constants(rng)
-                tk = srv.submit(1, preds=sv.q11_preds(*c))
+                tk = srv.submit(1, **sv.q11_request(*c))
                 submitted.append((tk, 1, c))
             if k % 8 == 7:
                 time.sleep(0.003)                # later requests arrive while earlier ones run
