@@ -136,6 +136,63 @@ class Timer:
         return float(np.mean([s.elapsed_time(e) for s, e in self.pairs])) if self.pairs else 0.0
 
 
+def shared_pass_bytes(torch, mask_steps, agg_cols, reread_cols, n, line=FETCH_BYTES):
+    """Algorithmic bytes of one shared-scan pass over rows [0, n): each join
+    step reads its key column at the lines holding a row still alive for some
+    query, the survivors' measure and group-key columns are read at their
+    lines.  mask_steps: (key column, mask table as int16, key_min) per step."""
+    per = line // 4
+    def lines(alive):
+        pad = (-n) % per
+        a = torch.nn.functional.pad(alive, (0, pad)) if pad else alive
+        return int(a.view(-1, per).any(dim=1).sum().item())
+    qm = torch.full((n,), -1, dtype=torch.int32, device="cuda")        # all queries alive
+    total = 0
+    for col, table, kmin in mask_steps:
+        total += lines(qm != 0) * line
+        off = col[:n].to(torch.int64) - kmin
+        ok = (off >= 0) & (off < table.numel())
+        m = torch.zeros(n, dtype=torch.int32, device="cuda")
+        m[ok] = table[off[ok]].to(torch.int32) & 0xFFFF
+        qm &= m
+    surv = lines(qm != 0) * line
+    return total + surv * (len(agg_cols) + len(reread_cols)), int((qm != 0).sum().item())
+
+
+def shared_scan_roofline(torch, cx, datagen, queries, sv, seg, rng, reps):
+    """Time one 16-query shared-scan pass per template over one clock
+    segment with HIP events on its stream, beside its algorithmic bytes."""
+    star_c = [datagen.random_star_constants(rng) for _ in range(16)]
+    q11_c = [datagen.random_q11_constants(rng) for _ in range(16)]
+    sv.build_star_masks(star_c)
+    sv.build_q11_masks(q11_c)
+    torch.cuda.synchronize()
+    d = sv.s.dims
+    def table(qmask):
+        return qmask.mem[: ((qmask.c.span + 1) // 2) * 4].view(torch.int16)[: qmask.c.span]
+    star_steps = [(sv.cols[j], table(sv.masks[j]), d[j]["key_min"]) for j in queries.DEFAULT_JOIN_ORDER]
+    q11_steps = [(sv.cols[dm["fk_col"]], table(dm["mask"]), dm["key_min"]) for dm in sv.q11_domains]
+    b_star, s_star = shared_pass_bytes(torch, star_steps, [4], [0, 2], seg)
+    b_q11, s_q11 = shared_pass_bytes(torch, q11_steps, [8, 6], [], seg)
+    res = {}
+    for name, scan, ng in (("star", sv.star_scan, queries.STAR_GROUPS), ("q11", sv.q11_scan, 1)):
+        outs = [torch.zeros(ng, dtype=torch.int64, device="cuda") for _ in range(16)]
+        stream = torch.cuda.current_stream()
+        for _ in range(2):
+            scan.run([[] for _ in outs], outs, 0, seg, stream=stream)
+        timer = Timer(torch)
+        for _ in range(max(3, reps)):
+            timer.run(lambda: scan.run([[] for _ in outs], outs, 0, seg, stream=stream), stream)
+        torch.cuda.synchronize()
+        res[name] = timer.mean_ms()
+    b = b_star + b_q11
+    ms = res["star"] + res["q11"]
+    return dict(kernel="crystal::shared_scan_kernel", achieved=b / (ms * 1e-3) / 1e9, algorithmic_bytes=b,
+                kernel_ms=ms, passes={"rows": seg, "queries_per_pass": 16,
+                                      "star": {"ms": res["star"], "bytes": b_star, "survivors": s_star},
+                                      "q11": {"ms": res["q11"], "bytes": b_q11, "survivors": s_q11}})
+
+
 def serve(args, torch, cx, datagen, queries, roof):
     """Served mixed workload: Poisson arrivals of star-template and Q1.1-template
     queries with seeded constants, answered by the continuous-batching server
@@ -227,7 +284,7 @@ def serve(args, torch, cx, datagen, queries, roof):
     finally:
         srv.close()
     best = max(per_rate, key=lambda r: r["served_qps"])
-    roof.update(kernel="crystal::shared_scan_kernel", achieved=0.0, kernel_ms=0.0)
+    roof.update(shared_scan_roofline(torch, cx, datagen, queries, sv, seg, rng, args.steps))
     return dict(metric="served queries/s + p99 latency (shared-scan continuous batching)",
                 value=burst_qps, unit="queries/s", ms_per_step=1e3 / burst_qps, dtype="int32",
                 config={"workload": f"served mix: fact {n} rows x 9 int32 columns, 50/50 star-join / Q1.1 "
