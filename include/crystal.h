@@ -65,7 +65,8 @@ int32_t crystal_abi_version(void);
  * check its own layout: 0 crystal_range, 1 crystal_ht, 2 crystal_pred,
  * 3 crystal_join, 4 crystal_star_query, 5 crystal_qmask_table,
  * 6 crystal_batch_query, 7 crystal_batch, 8 crystal_server_template,
- * 9 crystal_server_config, 10 crystal_server_stats.  0 for any other value. */
+ * 9 crystal_server_config, 10 crystal_server_stats, 11 crystal_ht_build_item.
+ * 0 for any other value. */
 size_t crystal_struct_size(int32_t which);
 
 /* ------------------------------------------------------------------------ */
@@ -164,6 +165,25 @@ crystal_status crystal_ht_build(const crystal_ht *ht, const int32_t *keys,
  *                probe_payload[i] when probe_payload is not NULL (wraps mod 2^64)
  *   *out_matches device int64: number of probe rows that found their key
  * Tables that fit the workgroup's LDS are staged there once per workgroup. */
+/* Build several tables in one call (section 5.3: the build phase of a star
+ * query builds one table per dimension before the single probe kernel).
+ * Same result, per item, as crystal_ht_build on it; the tables are cleared
+ * by one kernel and built by a second one whose workgroups are split among
+ * them, instead of two launches per table.  Items must use distinct table
+ * memory; n_items <= CRYSTAL_MAX_BUILD_BATCH.  `ht` points to a host
+ * descriptor; the other pointers are device memory as in crystal_ht_build. */
+#define CRYSTAL_MAX_BUILD_BATCH 8
+typedef struct {
+    const crystal_ht *ht;
+    const int32_t *keys;
+    const int32_t *payload;    /* NULL unless ht->has_payload */
+    const int32_t *filter_col; /* NULL: no build filter */
+    crystal_range filter;
+    int64_t n;
+} crystal_ht_build_item;
+crystal_status crystal_ht_build_batch(const crystal_ht_build_item *items, int32_t n_items, int32_t *status,
+                                      void *stream);
+
 crystal_status crystal_ht_probe(const crystal_ht *ht, const int32_t *fk,
                                 const int32_t *probe_payload, int64_t n,
                                 int64_t *out_sum, int64_t *out_matches, void *stream);

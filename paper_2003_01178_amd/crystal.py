@@ -46,6 +46,14 @@ class Join(ctypes.Structure):
                 ("group_base", c_i32), ("reserved", c_i32), ("group_stride", c_i64)]
 
 
+class BuildItemC(ctypes.Structure):
+    _fields_ = [("ht", ctypes.POINTER(HT)), ("keys", c_vp), ("payload", c_vp), ("filter_col", c_vp),
+                ("filter", Range), ("n", c_i64)]
+
+
+MAX_BUILD_BATCH = 8
+
+
 class StarQueryC(ctypes.Structure):
     _fields_ = [("cols", c_vp * MAX_COLS), ("n_rows", c_i64), ("n_cols", c_i32), ("n_preds", c_i32),
                 ("preds", Pred * MAX_PREDS), ("n_joins", c_i32), ("agg", c_i32), ("agg_col0", c_i32),
@@ -112,6 +120,7 @@ def _declare(lib):
         "crystal_ht_init": (c_i32, [P(HT), c_i32, c_i64, c_i32, c_i32, c_i32]),
         "crystal_ht_bytes": (ctypes.c_size_t, [P(HT)]),
         "crystal_ht_build": (c_i32, [P(HT), c_vp, c_vp, c_vp, Range, c_i64, c_vp, c_vp]),
+        "crystal_ht_build_batch": (c_i32, [P(BuildItemC), c_i32, c_vp, c_vp]),
         "crystal_ht_probe": (c_i32, [P(HT), c_vp, c_vp, c_i64, c_vp, c_vp, c_vp]),
         "crystal_groupby_agg": (c_i32, [c_vp, c_vp, c_i64, c_i64, c_vp, c_vp, c_vp]),
         "crystal_star_query_scratch_bytes": (ctypes.c_size_t, [P(StarQueryC)]),
@@ -165,7 +174,7 @@ def load(path: str = LIB_PATH):
             raise ImportError(f"libcrystal.so is missing and could not be built: {e}") from e
     lib = _declare(ctypes.CDLL(path))
     for which, ty in enumerate((Range, HT, Pred, Join, StarQueryC, QmaskTableC, BatchQueryC, BatchC,
-                                ServerTemplateC, ServerConfigC, ServerStatsC)):
+                                ServerTemplateC, ServerConfigC, ServerStatsC, BuildItemC)):
         if lib.crystal_struct_size(which) != ctypes.sizeof(ty):
             raise ImportError(f"ABI layout mismatch for {ty.__name__}")
     _lib = lib
@@ -297,6 +306,34 @@ class HashTable:
                                     fk.numel(), c_vp(base), c_vp(base + 8), _stream(stream)),
                "crystal_ht_probe")
         return out
+
+
+def build_tables(items, status=None, stream=None):
+    """Build several tables with one clear launch and one build launch.
+
+    items: (HashTable, keys, payload or None, filter_col or None, (lo, hi)) per table."""
+    lib = load()
+    if not items:
+        return status
+    if len(items) > MAX_BUILD_BATCH:
+        raise ValueError("at most 8 tables per batch")
+    arr = (BuildItemC * len(items))()
+    keep = []
+    for i, (ht, keys, payload, filter_col, rng) in enumerate(items):
+        for extra in (payload, filter_col):
+            if extra is not None and extra.numel() != keys.numel():
+                raise ValueError("build columns differ in length")
+        arr[i].ht = ctypes.pointer(ht.desc)
+        arr[i].keys = _col(keys)
+        arr[i].payload = _col(payload) if payload is not None else None
+        arr[i].filter_col = _col(filter_col) if filter_col is not None else None
+        arr[i].filter = Range(int(rng[0]), int(rng[1]))
+        arr[i].n = keys.numel()
+        keep.append(ht)
+    dev = items[0][1].device
+    status = new_status(dev) if status is None else status
+    _check(lib.crystal_ht_build_batch(arr, len(items), _ptr(status), _stream(stream)), "crystal_ht_build_batch")
+    return status
 
 
 def groupby_agg(group, value, n_groups, out=None, status=None, stream=None):

@@ -241,6 +241,7 @@ size_t crystal_struct_size(int32_t which) {
     case 8: return sizeof(crystal_server_template);
     case 9: return sizeof(crystal_server_config);
     case 10: return sizeof(crystal_server_stats);
+    case 11: return sizeof(crystal_ht_build_item);
     default: return 0;
     }
 }
@@ -327,6 +328,21 @@ crystal_status crystal_ht_build(const crystal_ht *ht, const int32_t *keys, const
         return CRYSTAL_EINVAL;
     return from_hip(launch_ht_build(*ht, keys, ht->has_payload ? payload : nullptr, filter_col,
                                     filter.lo, filter.hi, n, status, as_stream(stream)));
+}
+
+crystal_status crystal_ht_build_batch(const crystal_ht_build_item *items, int32_t n_items, int32_t *status,
+                                      void *stream) {
+    if (!items || !status || n_items < 0 || n_items > CRYSTAL_MAX_BUILD_BATCH) return CRYSTAL_EINVAL;
+    for (int i = 0; i < n_items; ++i) {
+        const crystal_ht_build_item &it = items[i];
+        if (!it.ht || !ht_valid(*it.ht) || it.n < 0 || (it.n > 0 && !it.keys) ||
+            (it.ht->has_payload && it.n > 0 && !it.payload))
+            return CRYSTAL_EINVAL;
+        for (int j = 0; j < i; ++j)
+            if (items[j].ht->mem == it.ht->mem) return CRYSTAL_EINVAL;
+    }
+    if (n_items == 0) return CRYSTAL_OK;
+    return from_hip(launch_ht_build_batch(items, n_items, status, as_stream(stream)));
 }
 
 crystal_status crystal_ht_probe(const crystal_ht *ht, const int32_t *fk, const int32_t *probe_payload,

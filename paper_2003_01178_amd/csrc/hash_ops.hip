@@ -42,55 +42,150 @@ hipError_t launch_ht_clear(const crystal_ht &ht, hipStream_t s) {
 // {EMPTY, 0} -> {key, payload} (linear probing), or an atomic OR sets the
 // key's presence bit and the payload is stored (direct table).
 template <int KIND>
+__device__ __forceinline__ void build_row(const DevTable &t, const int32_t *__restrict__ keys,
+                                          const int32_t *__restrict__ payload,
+                                          const int32_t *__restrict__ filter_col, int32_t flo, int32_t fhi,
+                                          int64_t i, int32_t *status) {
+    if (filter_col && !in_range(filter_col[i], flo, fhi)) return;
+    const int32_t k = keys[i];
+    const int32_t v = payload ? payload[i] : 0;
+    if constexpr (KIND == CRYSTAL_HT_DIRECT) {
+        const uint32_t off = (uint32_t)k - (uint32_t)t.key_min;
+        if ((int64_t)off >= t.span) {
+            set_status(status, CRYSTAL_ERANGE);
+            return;
+        }
+        const uint32_t bit = 1u << (off & 31u);
+        const uint32_t old = atomicOr(const_cast<uint32_t *>(t.bitmap) + (off >> 5), bit);
+        if (old & bit) {
+            set_status(status, CRYSTAL_EDUPKEY);
+            return;
+        }
+        if (t.payload) const_cast<int32_t *>(t.payload)[off] = v;
+    } else {
+        if (k == kEmptyKey) {
+            set_status(status, CRYSTAL_EINVAL);
+            return;
+        }
+        unsigned long long *slots = (unsigned long long *)const_cast<v2i *>(t.slots);
+        const unsigned long long want = (unsigned long long)(uint32_t)k | ((unsigned long long)(uint32_t)v << 32);
+        uint32_t sl = hash_slot(k, t.shift);
+        for (uint32_t step = 0; step <= t.mask; ++step) {
+            const unsigned long long old = atomicCAS(slots + sl, (unsigned long long)kEmptySlot, want);
+            if (old == kEmptySlot) return;
+            if ((int32_t)(uint32_t)old == k) {
+                set_status(status, CRYSTAL_EDUPKEY);
+                return;
+            }
+            sl = (sl + 1u) & t.mask;
+        }
+        set_status(status, CRYSTAL_EFULL);
+    }
+}
+
+template <int KIND>
 __global__ __launch_bounds__(256) void ht_build_kernel(DevTable t, const int32_t *__restrict__ keys,
                                                        const int32_t *__restrict__ payload,
                                                        const int32_t *__restrict__ filter_col,
                                                        int32_t flo, int32_t fhi, int64_t n,
                                                        int32_t *status) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        if (filter_col && !in_range(filter_col[i], flo, fhi)) continue;
-        const int32_t k = keys[i];
-        const int32_t v = payload ? payload[i] : 0;
-        if constexpr (KIND == CRYSTAL_HT_DIRECT) {
-            const uint32_t off = (uint32_t)k - (uint32_t)t.key_min;
-            if ((int64_t)off >= t.span) {
-                set_status(status, CRYSTAL_ERANGE);
-                continue;
-            }
-            const uint32_t bit = 1u << (off & 31u);
-            const uint32_t old = atomicOr(const_cast<uint32_t *>(t.bitmap) + (off >> 5), bit);
-            if (old & bit) {
-                set_status(status, CRYSTAL_EDUPKEY);
-                continue;
-            }
-            if (t.payload) const_cast<int32_t *>(t.payload)[off] = v;
-        } else {
-            if (k == kEmptyKey) {
-                set_status(status, CRYSTAL_EINVAL);
-                continue;
-            }
-            unsigned long long *slots = (unsigned long long *)const_cast<v2i *>(t.slots);
-            const unsigned long long want = (unsigned long long)(uint32_t)k |
-                                            ((unsigned long long)(uint32_t)v << 32);
-            uint32_t sl = hash_slot(k, t.shift);
-            bool placed = false;
-            for (uint32_t step = 0; step <= t.mask; ++step) {
-                const unsigned long long old = atomicCAS(slots + sl, (unsigned long long)kEmptySlot, want);
-                if (old == kEmptySlot) {
-                    placed = true;
-                    break;
-                }
-                if ((int32_t)(uint32_t)old == k) {
-                    set_status(status, CRYSTAL_EDUPKEY);
-                    placed = true;
-                    break;
-                }
-                sl = (sl + 1u) & t.mask;
-            }
-            if (!placed) set_status(status, CRYSTAL_EFULL);
-        }
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        build_row<KIND>(t, keys, payload, filter_col, flo, fhi, i, status);
+}
+
+// ------------------------------------------------------------ batch build --
+// Several tables in two launches: one clear of every table's memory, then
+// one build kernel whose workgroups are split between the tables (a range of
+// workgroups per table, each striding over that table's rows).
+struct ClearRange {
+    uint64_t *p;
+    int64_t n;        // 64-bit words
+    uint64_t value;
+};
+
+struct ClearBatch {
+    int32_t count;
+    ClearRange r[kMaxBuildBatch];
+};
+
+__global__ __launch_bounds__(256) void clear_batch_kernel(ClearBatch b) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int r = 0; r < b.count; ++r)
+        for (int64_t i = g0; i < b.r[r].n; i += stride) b.r[r].p[i] = b.r[r].value;
+}
+
+struct BuildItemDev {
+    DevTable t;
+    const int32_t *keys;
+    const int32_t *payload;
+    const int32_t *filter;
+    int32_t flo, fhi;
+    int64_t n;
+    int64_t block0, blocks;
+};
+
+struct BuildBatch {
+    int32_t count;
+    BuildItemDev it[kMaxBuildBatch];
+};
+
+__global__ __launch_bounds__(256) void build_batch_kernel(BuildBatch b, int32_t *status) {
+    int r = 0;
+    while (r + 1 < b.count && (int64_t)blockIdx.x >= b.it[r + 1].block0) ++r;
+    const BuildItemDev &it = b.it[r];
+    const int64_t stride = it.blocks * blockDim.x;
+    for (int64_t i = ((int64_t)blockIdx.x - it.block0) * blockDim.x + threadIdx.x; i < it.n; i += stride) {
+        if (it.t.kind == CRYSTAL_HT_DIRECT)
+            build_row<CRYSTAL_HT_DIRECT>(it.t, it.keys, it.payload, it.filter, it.flo, it.fhi, i, status);
+        else
+            build_row<CRYSTAL_HT_LINEAR>(it.t, it.keys, it.payload, it.filter, it.flo, it.fhi, i, status);
     }
+}
+
+hipError_t launch_ht_build_batch(const crystal_ht_build_item *items, int n_items, int32_t *status,
+                                 hipStream_t s) {
+    ClearBatch cb = {};
+    BuildBatch bb = {};
+    int64_t clear_words = 0, blocks = 0;
+    const int64_t cap = (int64_t)device_cu_count() * 32;
+    for (int i = 0; i < n_items; ++i) {
+        const crystal_ht &ht = *items[i].ht;
+        ClearRange &c = cb.r[cb.count++];
+        c.p = (uint64_t *)ht.mem;
+        if (ht.kind == CRYSTAL_HT_DIRECT) {
+            c.n = direct_bitmap_words(ht.capacity) / 2;  // an even number of 32-bit words
+            c.value = 0;
+        } else {
+            c.n = ht.capacity;
+            c.value = kEmptySlot;
+        }
+        clear_words = c.n > clear_words ? c.n : clear_words;
+        if (items[i].n == 0) continue;
+        BuildItemDev &d = bb.it[bb.count++];
+        d.t = to_dev(ht);
+        d.keys = items[i].keys;
+        d.payload = ht.has_payload ? items[i].payload : nullptr;
+        d.filter = items[i].filter_col;
+        d.flo = items[i].filter.lo;
+        d.fhi = items[i].filter.hi;
+        d.n = items[i].n;
+        int64_t nb = (items[i].n + 255) / 256;
+        if (nb > cap) nb = cap;
+        d.block0 = blocks;
+        d.blocks = nb;
+        blocks += nb;
+    }
+    if (cb.count == 0) return hipSuccess;
+    int64_t cgrid = (clear_words + 255) / 256;
+    if (cgrid > cap) cgrid = cap;
+    if (cgrid < 1) cgrid = 1;
+    hipLaunchKernelGGL(clear_batch_kernel, dim3((unsigned)cgrid), dim3(256), 0, s, cb);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || bb.count == 0) return e;
+    hipLaunchKernelGGL(build_batch_kernel, dim3((unsigned)blocks), dim3(256), 0, s, bb, status);
+    return hipGetLastError();
 }
 
 hipError_t launch_ht_build(const crystal_ht &ht, const int32_t *keys, const int32_t *payload,

@@ -57,6 +57,10 @@ hipError_t launch_ht_clear(const crystal_ht &ht, hipStream_t s);
 hipError_t launch_ht_build(const crystal_ht &ht, const int32_t *keys, const int32_t *payload,
                            const int32_t *filter_col, int32_t flo, int32_t fhi, int64_t n,
                            int32_t *status, hipStream_t s);
+// Clear and build up to kMaxBuildBatch tables in two launches (arguments checked).
+constexpr int kMaxBuildBatch = CRYSTAL_MAX_BUILD_BATCH;
+hipError_t launch_ht_build_batch(const crystal_ht_build_item *items, int n_items, int32_t *status,
+                                 hipStream_t s);
 hipError_t launch_ht_probe(const LaunchCfg &cfg, const crystal_ht &ht, const int32_t *fk,
                            const int32_t *probe_payload, int64_t n, uint64_t *sum, uint64_t *count,
                            hipStream_t s);

@@ -75,13 +75,19 @@ class StarSchema:
     def fact_cols(self):
         return [*self.fk, self.m1, self.m2]
 
-    def build(self, consts=None, stream=None):
-        """Filtered builds: dimension j keeps rows with filter == consts[j]."""
+    def build(self, consts=None, stream=None, batched=True):
+        """Filtered builds: dimension j keeps rows with filter == consts[j].
+        batched: all four tables in one clear and one build launch."""
         consts = self.consts if consts is None else consts
+        items = []
         for j, d in enumerate(self.dims):
             payload = d["year"] if j == 0 else (d["group"] if j == 2 else None)
-            self.tables[j].build(d["key"], payload=payload, filter_col=d["filter"],
-                                 filter=(consts[j], consts[j]), status=self.status, stream=stream)
+            items.append((self.tables[j], d["key"], payload, d["filter"], (consts[j], consts[j])))
+        if batched:
+            cx.build_tables(items, status=self.status, stream=stream)
+        else:
+            for ht, keys, payload, filt, rng in items:
+                ht.build(keys, payload=payload, filter_col=filt, filter=rng, status=self.status, stream=stream)
         return self.tables
 
     def plan(self, order=DEFAULT_JOIN_ORDER):
@@ -95,6 +101,86 @@ class StarSchema:
             joins.append(jj)
         return cx.StarQuery(self.fact_cols, n_groups=STAR_GROUPS, joins=joins,
                             agg=cx.AGG_SUM, agg_cols=(4, 0))
+
+
+# ------------------------------------------------------------ flight shapes --
+def q1x_consts(flight, year=1994, month=1, day=6):
+    """Fact-side predicates of the SSB flight-1 shapes (section 5.1 runs the
+    SSB flights) on (datekey, discount, quantity): Q1.1 a year, discount 1..3,
+    quantity < 25; Q1.2 a month, discount 4..6, quantity 26..35; Q1.3 seven
+    consecutive days, discount 5..7, quantity 26..35."""
+    if flight == 1:
+        lo, hi = datagen.q11_year_range(year)
+        return (lo, hi), (1, 3), (cx.I32_MIN, 24)
+    if flight == 2:
+        return (year * 10000 + month * 100 + 1, year * 10000 + month * 100 + 31), (4, 6), (26, 35)
+    if flight == 3:
+        d0 = year * 10000 + month * 100 + day
+        return (d0, d0 + 6), (5, 7), (26, 35)
+    raise ValueError("flight 1 has queries 1, 2 and 3")
+
+
+def q1x_plan(cols, flight, **kw):
+    """SUM(price * discount) under the flight-1 predicates; cols = (datekey,
+    discount, quantity, price)."""
+    d, disc, qty = q1x_consts(flight, **kw)
+    return cx.StarQuery(list(cols), n_groups=1, preds=[(0, *d), (1, *disc), (2, *qty)],
+                        agg=cx.AGG_SUM_PRODUCT, agg_cols=(3, 1))
+
+
+# Packed dimension payload of the flight templates: bits 0..9 the group
+# attribute (dim0: year - 1992), bits 16..20 the filter attribute.
+PACK_FILTER_SHIFT = 16
+
+
+class FlightTemplates:
+    """More star-query shapes over one star schema (the SSB flights 3 and 4
+    pattern: joins filtered by ranges, several group attributes, SUM(m1) or
+    SUM(m1 - m2)).  Dimension tables are built once, unfiltered, with packed
+    payloads, so every template and constant set reads its filters and group
+    fields from the payload at probe time (no per-query build)."""
+
+    def __init__(self, schema: StarSchema):
+        self.s = schema
+        self.status = cx.new_status(schema.device)
+        self.tables = []
+        for j, d in enumerate(schema.dims):
+            grp = d["year"] - datagen.FIRST_YEAR if j == 0 else d["group"]
+            packed = (d["filter"] << PACK_FILTER_SHIFT) | grp
+            ht = cx.HashTable(cx.HT_DIRECT, d["n"], d["key_min"], d["key_max"], has_payload=True,
+                              device=schema.device)
+            ht.build(d["key"], payload=packed.contiguous(), status=self.status)
+            self.tables.append(ht)
+
+    def _join(self, j, filt=None, year=None, group=None):
+        jj = dict(table=self.tables[j], fk_col=j)
+        if filt is not None:
+            jj["filter"] = (5, PACK_FILTER_SHIFT, filt[0], filt[1])
+        if year is not None:                       # dim0: filter on the year field
+            jj["filter"] = (10, 0, year[0] - datagen.FIRST_YEAR, year[1] - datagen.FIRST_YEAR)
+        if group is not None:
+            jj["group"] = group                    # (bits, shift, base, stride)
+        return jj
+
+    def q3(self, c1, c3, years=(1992, 1997)):
+        """Flight-3 shape: three joins, dim1.filter = c1, dim3.filter in
+        [c3, c3 + 4], year in `years`; group by (year, dim2.group, dim1.group
+        mod 8); SUM(m1).  7 x 1000 x 8 = 56,000 groups."""
+        joins = [self._join(1, filt=(c1, c1), group=(3, 0, 0, 1)),
+                 self._join(3, filt=(c3, c3 + 4)),
+                 self._join(0, year=years, group=(10, 0, 0, 8000)),
+                 self._join(2, group=(10, 0, 0, 8))]
+        return cx.StarQuery(self.s.fact_cols, n_groups=56_000, joins=joins, agg=cx.AGG_SUM, agg_cols=(4, 0))
+
+    def q4(self, c1, c2, years=(1997, 1998)):
+        """Flight-4 shape: four joins, year in `years`, dim1.filter in
+        [c1, c1 + 2], dim2.filter = c2, dim3.filter <= 12; group by (year,
+        dim1.group mod 16); SUM(m1 - m2).  7 x 16 = 112 groups."""
+        joins = [self._join(1, filt=(c1, c1 + 2), group=(4, 0, 0, 1)),
+                 self._join(0, year=years, group=(10, 0, 0, 16)),
+                 self._join(2, filt=(c2, c2)),
+                 self._join(3, filt=(0, 12))]
+        return cx.StarQuery(self.s.fact_cols, n_groups=112, joins=joins, agg=cx.AGG_SUM_DIFF, agg_cols=(4, 5))
 
 
 # ------------------------------------------------------------ serving forms --

@@ -37,7 +37,7 @@ def test_struct_layout_matches_binding(cx):
     assert lib.crystal_abi_version() == 3
     for which, ty in enumerate((cx.Range, cx.HT, cx.Pred, cx.Join, cx.StarQueryC, cx.QmaskTableC,
                                 cx.BatchQueryC, cx.BatchC, cx.ServerTemplateC, cx.ServerConfigC,
-                                cx.ServerStatsC)):
+                                cx.ServerStatsC, cx.BuildItemC)):
         assert lib.crystal_struct_size(which) == ctypes.sizeof(ty), ty.__name__
     assert lib.crystal_struct_size(99) == 0
 

@@ -232,3 +232,56 @@ def test_groupby_lds_path_and_range_error():
     want = oracle.groupby(g, v, groups)
     want[0] -= 123                                 # the skipped row (v = 123, group 0 in g)
     assert np.array_equal(sums.cpu().numpy(), want)
+
+
+# ------------------------------------------------------------ batch build --
+def test_build_batch_matches_single_builds():
+    """crystal_ht_build_batch leaves every table byte-identical to its own
+    crystal_ht_build (direct tables with and without payload and filter, and
+    linear-probing tables), including a table with zero build rows."""
+    announce("build batch")
+    rng = np.random.default_rng(11)
+    specs = []
+    for kind, n, span, payload, filt in [(cx.HT_DIRECT, 2556, 5000, True, True),
+                                         (cx.HT_DIRECT, 40_000, 40_000, False, True),
+                                         (cx.HT_LINEAR, 200_000, 0, True, False),
+                                         (cx.HT_LINEAR, 3_000, 0, False, True),
+                                         (cx.HT_DIRECT, 0, 64, True, False)]:
+        if kind == cx.HT_DIRECT:
+            keys = rng.permutation(span)[:n].astype(np.int32) + 17
+            lo, hi = 17, 17 + span - 1
+        else:
+            keys = rng.choice(2 ** 30, size=n, replace=False).astype(np.int32)
+            lo, hi = 0, 0
+        pay = rng.integers(-2 ** 31, 2 ** 31 - 1, size=n, dtype=np.int32) if payload else None
+        flt = rng.integers(0, 25, size=n, dtype=np.int32) if filt else None
+        specs.append((kind, keys, lo, hi, pay, flt))
+    singles, batch_tables, items = [], [], []
+    for kind, keys, lo, hi, pay, flt in specs:
+        a = cx.HashTable(kind, max(len(keys), 1), lo, hi, has_payload=pay is not None)
+        b = cx.HashTable(kind, max(len(keys), 1), lo, hi, has_payload=pay is not None)
+        a.mem.fill_(0x5A)
+        b.mem.fill_(0x5A)          # payload slots of absent keys are never written
+        kd = dev(keys)
+        pd = dev(pay) if pay is not None else None
+        fd = dev(flt) if flt is not None else None
+        rng_f = (3, 9) if flt is not None else (cx.I32_MIN, cx.I32_MAX)
+        st = a.build(kd, payload=pd, filter_col=fd, filter=rng_f)
+        cx.check_status(st)
+        singles.append(a)
+        batch_tables.append(b)
+        items.append((b, kd, pd, fd, rng_f))
+    st = cx.build_tables(items)
+    cx.check_status(st)
+    for a, b in zip(singles, batch_tables):
+        n = a.nbytes
+        if a.kind == cx.HT_DIRECT:
+            assert torch.equal(a.mem[:n], b.mem[:n])     # bitmap and payloads: one place per key
+        else:
+            # linear probing places colliding keys in arrival order: compare the
+            # set of occupied {key, payload} slots, which is unique
+            sa, sb = (t.mem[:n].view(torch.int32).view(-1, 2).cpu().numpy() for t in (a, b))
+            occ_a, occ_b = sa[sa[:, 0] != cx.I32_MIN], sb[sb[:, 0] != cx.I32_MIN]
+            assert np.array_equal(occ_a[np.argsort(occ_a[:, 0])], occ_b[np.argsort(occ_b[:, 0])])
+    with pytest.raises(cx.CrystalError):           # the same table twice
+        cx.build_tables([items[0], items[0]])
