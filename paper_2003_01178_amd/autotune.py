@@ -8,7 +8,8 @@ tuning table for the size buckets nearest to that size, and the table is
 saved as a text cache (``tune/gfx950.txt``) that ``crystal.load()`` reads.
 
 Usage: ``python -m paper_2003_01178_amd.autotune [--kernels star,select,...]
-[--out PATH] [--quick]``.  Prints a JSON report.
+[--out PATH] [--quick]``.  Prints a JSON report.  Entries of kernels that
+were not swept in this run are kept from the existing table file.
 """
 from __future__ import annotations
 
@@ -87,7 +88,7 @@ def assign(kernel, results):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--kernels", default="star,q11,select,project,probe,groupby")
+    ap.add_argument("--kernels", default="star,q11,select,project,probe,groupby,shared,radix")
     ap.add_argument("--out", default=DEFAULT_OUT)
     ap.add_argument("--quick", action="store_true", help="fewer candidates and sizes")
     ap.add_argument("--reps", type=int, default=10)
@@ -179,8 +180,57 @@ def main(argv=None):
         assign(cx.K_GROUPBY, [(n, rows[0][1:])])
         report["groupby_2^26_7000"] = rows[:8]
 
-    # the saved table holds only the winners, not every swept candidate
+    if "shared" in kernels:
+        # one 16-query pass per serving template over a 75M-row clock segment
+        n = 75_000_000
+        t = datagen.star_tables(n=n, workload=4, with_q11_columns=True)
+        sv = queries.ServingTemplates(queries.StarSchema(t))
+        del t
+        rng = np.random.default_rng(7)
+        sv.build_star_masks([datagen.random_star_constants(rng) for _ in range(16)])
+        sv.build_q11_masks([datagen.random_q11_constants(rng) for _ in range(16)])
+        outs_s = [torch.zeros(queries.STAR_GROUPS, dtype=torch.int64, device="cuda") for _ in range(16)]
+        outs_q = [torch.zeros(1, dtype=torch.int64, device="cuda") for _ in range(16)]
+
+        def passes():
+            for o in outs_s + outs_q:
+                o.zero_()
+            sv.star_scan.run([[] for _ in outs_s], outs_s, 0, n)
+            sv.q11_scan.run([[] for _ in outs_q], outs_q, 0, n)
+
+        rows = sweep(cx.K_SHARED_SCAN, n, passes, lambda: np.concatenate([o.cpu().numpy() for o in outs_s + outs_q]),
+                     candidates=quick_vec if args.quick else None, gpcs=(0, 1, 2, 4), reps=args.reps, log=log)
+        assign(cx.K_SHARED_SCAN, [(n, rows[0][1:])])
+        report["shared_75M_2x16"] = rows[:8]
+        del sv
+        torch.cuda.empty_cache()
+    if "radix" in kernels:
+        n = 1 << 28
+        kh, vh = datagen.radix_pairs(n)
+        keys, vals = queries.to_dev(kh), queries.to_dev(vh)
+        ok, ov = torch.empty_like(keys), torch.empty_like(vals)
+        scratch = torch.empty(cx.load().crystal_radix_partition_scratch_bytes(n) * 4, dtype=torch.uint8,
+                              device="cuda")
+        rows = sweep(cx.K_RADIX, n, lambda: cx.radix_partition(keys, 0, 8, vals=vals, out_keys=ok, out_vals=ov,
+                                                               scratch=scratch),
+                     lambda: ok[:: 1 << 12].cpu().numpy(), gpcs=(0, 1, 2), reps=args.reps, log=log)
+        assign(cx.K_RADIX, [(n, rows[0][1:])])
+        report["radix_partition_2^28"] = rows[:8]
+        del keys, vals, ok, ov
+        torch.cuda.empty_cache()
+
+    # the saved table holds only the winners, not every swept candidate; kernels
+    # not swept in this run keep their entries from the existing file
+    kept = []
+    if os.path.exists(args.out):
+        with open(args.out) as f:
+            for line in f:
+                parts = line.split()
+                if len(parts) == 6 and not line.startswith("#") and int(parts[0]) not in WINNERS:
+                    kept.append([int(x) for x in parts])
     cx.tune_reset()
+    for k, lo, hi, b, i, g in kept:
+        cx.tune_set(k, b, i, g, bucket_lo=lo, bucket_hi=hi)
     for kernel, results in WINNERS.items():
         assign(kernel, results)
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
