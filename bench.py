@@ -46,6 +46,8 @@ def parse():
     p.add_argument("--order", default="1,0,2,3", help="star join order")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-graph", action="store_true", help="star: launch eagerly instead of replaying HIP graphs")
+    p.add_argument("--narrow", action="store_true",
+                   help="star: store the two dense-phase foreign keys as 16-bit offsets (compressed columns)")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
     p.add_argument("--tune", default="", help="kernel block,ipt,grid_per_cu override, e.g. 256,16,0")
     p.add_argument("--rates", default="200,500,1000,2000", help="serve: Poisson arrival rates (q/s)")
@@ -77,14 +79,16 @@ def lines_touched(mask: np.ndarray, item_bytes: int = 4, line: int = FETCH_BYTES
     return int(mask.reshape(-1, per).any(axis=1).sum())
 
 
-def star_algorithmic_bytes(t, order, line=FETCH_BYTES):
+def star_algorithmic_bytes(t, order, line=FETCH_BYTES, widths=None):
     """Bytes the selective scan must fetch: column s is read at the lines that
-    hold an item still alive before step s; the measure at the survivors."""
+    hold an item still alive before step s; the measure at the survivors.
+    widths[j]: bytes per stored value of foreign-key column j (default 4)."""
     alive = np.ones(t.n, dtype=bool)
     total = 0
     for j in order:
         d = t.dims[j]
-        total += lines_touched(alive, line=line) * line
+        w = 4 if widths is None else widths[j]
+        total += lines_touched(alive, item_bytes=w, line=line) * line
         kmin = int(d.key.min())
         keep = np.zeros(int(d.key.max()) - kmin + 1, dtype=bool)
         keep[d.key[d.filter == t.consts[j]] - kmin] = True
@@ -333,6 +337,16 @@ def main():
         print(f"# generated {n} fact rows in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
         s = queries.StarSchema(t)
         plan = s.plan(order)
+        widths = None
+        if args.narrow:
+            # compressed layout: fk0 (date keys, span 61,130) and fk1 (0..39,999) as uint16 offsets
+            fk0, st0 = cx.pack_column(s.fk[0], int(t.dims[0].key.min()), 2)
+            fk1, st1 = cx.pack_column(s.fk[1], 0, 2)
+            cx.check_status(st0)
+            cx.check_status(st1)
+            plan = cx.StarQuery([fk0, fk1, s.fk[2], s.fk[3], s.m1, s.m2], n_groups=queries.STAR_GROUPS,
+                                joins=plan.joins, agg=cx.AGG_SUM, agg_cols=(4, 0))
+            widths = [2, 2, 4, 4]
         out = torch.empty(queries.STAR_GROUPS, dtype=torch.int64, device="cuda")
         status = cx.new_status()
         stream = torch.cuda.Stream()
@@ -382,8 +396,8 @@ def main():
         cx.check_status(status)
         cx.check_status(s.status)
         kern_ms = timer.mean_ms() / K
-        alg_bytes, survivors = star_algorithmic_bytes(t, order)
-        alg_bytes_c64, _ = star_algorithmic_bytes(t, order, line=64)
+        alg_bytes, survivors = star_algorithmic_bytes(t, order, widths=widths)
+        alg_bytes_c64, _ = star_algorithmic_bytes(t, order, line=64, widths=widths)
         gpu_out = out.cpu().numpy()
         result.update(metric="fact rows/s & % HBM peak (fused star query); served queries/s + p99 latency",
                       value=n * K / elapsed, unit="rows/s", ms_per_step=elapsed / K * 1e3, dtype="int32",
@@ -393,12 +407,13 @@ def main():
                               "fact_rows": n, "join_order": list(order), "survivors": survivors,
                               "tile": list(cx.tune_get(cx.K_STAR, n)),
                               "step": "4 filtered dimension builds + fused probe/aggregate kernel",
-                              "launch": "hip graphs" if use_graph else "eager"})
+                              "launch": "hip graphs" if use_graph else "eager",
+                              "columns": "fk0, fk1 uint16 offsets; others int32" if args.narrow else "int32"})
         roof.update(kernel="crystal::star_kernel", achieved=alg_bytes / (kern_ms * 1e-3) / 1e9,
                     algorithmic_bytes=alg_bytes, bytes_per_row=alg_bytes / n, kernel_ms=kern_ms,
                     kernel_rows_per_s=n / (kern_ms * 1e-3), algorithmic_bytes_c64=alg_bytes_c64,
                     frac_c64=alg_bytes_c64 / (kern_ms * 1e-3) / 1e9 / HBM_PEAK_GBS)
-        roof["traffic"] = measured_traffic(order, n)
+        roof["traffic"] = None if args.narrow else measured_traffic(order, n)
         if not args.no_cpu_baseline:
             import oracle
             from_cols = [*t.fk, t.m1, t.m2]

@@ -58,15 +58,15 @@ typedef struct crystal_range {
 const char *crystal_status_string(int32_t status);
 
 /* ABI version of this header (incremented on any layout change). */
-#define CRYSTAL_ABI_VERSION 3
+#define CRYSTAL_ABI_VERSION 4
 int32_t crystal_abi_version(void);
 
 /* sizeof of the ABI structs as compiled into the library, so a binding can
  * check its own layout: 0 crystal_range, 1 crystal_ht, 2 crystal_pred,
  * 3 crystal_join, 4 crystal_star_query, 5 crystal_qmask_table,
  * 6 crystal_batch_query, 7 crystal_batch, 8 crystal_server_template,
- * 9 crystal_server_config, 10 crystal_server_stats, 11 crystal_ht_build_item.
- * 0 for any other value. */
+ * 9 crystal_server_config, 10 crystal_server_stats, 11 crystal_ht_build_item,
+ * 12 crystal_col_format.  0 for any other value. */
 size_t crystal_struct_size(int32_t which);
 
 /* ------------------------------------------------------------------------ */
@@ -250,8 +250,18 @@ typedef struct crystal_join {
     int64_t group_stride;
 } crystal_join;
 
+/* Storage of one fact column (compressed columns, section 5.5's outlook:
+ * fewer HBM bytes for a little ALU).  width 0 or 4: int32 values; width 2
+ * or 1: uint16 or uint8 offsets from `base` (frame of reference), value =
+ * base + stored.  crystal_pack_column writes such a column. */
+typedef struct crystal_col_format {
+    int32_t width;
+    int32_t base;
+} crystal_col_format;
+
 typedef struct crystal_star_query {
-    const int32_t *cols[CRYSTAL_MAX_COLS]; /* fact columns (device)          */
+    const int32_t *cols[CRYSTAL_MAX_COLS]; /* fact columns (device; a narrow
+                                              column's pointer is cast)     */
     int64_t n_rows;
     int32_t n_cols;
     int32_t n_preds;
@@ -262,6 +272,7 @@ typedef struct crystal_star_query {
     int32_t agg_col1;
     int64_t n_groups;                      /* >= 1; 1 means a scalar result  */
     crystal_join joins[CRYSTAL_MAX_JOINS]; /* evaluated after the predicates */
+    crystal_col_format formats[CRYSTAL_MAX_COLS]; /* all zero: int32 columns */
 } crystal_star_query;
 
 /* Device scratch bytes a call needs: per-workgroup partial sums when the
@@ -285,6 +296,15 @@ crystal_status crystal_run_star_query(const crystal_star_query *q, int64_t *out,
 crystal_status crystal_run_star_query_accumulate(const crystal_star_query *q, int64_t *out,
                                                  int32_t *status, void *scratch, size_t scratch_bytes,
                                                  void *stream);
+
+/* Write a narrow column: out[i] = in[i] - base as a `width`-byte unsigned
+ * value (width 1 or 2).  in: device int32[n], 16-byte aligned; out: device,
+ * n * width bytes, 16-byte aligned.  A value outside [base, base + 2^(8 width)
+ * - 1] is stored truncated and sets *status (device) to CRYSTAL_ERANGE.
+ * Narrow columns are read by crystal_run_star_query(_accumulate); the
+ * shared-scan batch and the server take int32 columns only (CRYSTAL_EINVAL). */
+crystal_status crystal_pack_column(const int32_t *in, int64_t n, int32_t base, int32_t width, void *out,
+                                   int32_t *status, void *stream);
 
 /* ------------------------------------------------------------------------ */
 /* Shared-scan batches: up to CRYSTAL_MAX_BATCH queries of one star-query    */

@@ -54,10 +54,15 @@ class BuildItemC(ctypes.Structure):
 MAX_BUILD_BATCH = 8
 
 
+class ColFormatC(ctypes.Structure):
+    _fields_ = [("width", c_i32), ("base", c_i32)]
+
+
 class StarQueryC(ctypes.Structure):
     _fields_ = [("cols", c_vp * MAX_COLS), ("n_rows", c_i64), ("n_cols", c_i32), ("n_preds", c_i32),
                 ("preds", Pred * MAX_PREDS), ("n_joins", c_i32), ("agg", c_i32), ("agg_col0", c_i32),
-                ("agg_col1", c_i32), ("n_groups", c_i64), ("joins", Join * MAX_JOINS)]
+                ("agg_col1", c_i32), ("n_groups", c_i64), ("joins", Join * MAX_JOINS),
+                ("formats", ColFormatC * MAX_COLS)]
 
 
 MAX_BATCH = 16
@@ -126,6 +131,7 @@ def _declare(lib):
         "crystal_star_query_scratch_bytes": (ctypes.c_size_t, [P(StarQueryC)]),
         "crystal_run_star_query": (c_i32, [P(StarQueryC), c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp]),
         "crystal_run_star_query_accumulate": (c_i32, [P(StarQueryC), c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp]),
+        "crystal_pack_column": (c_i32, [c_vp, c_i64, c_i32, c_i32, c_vp, c_vp, c_vp]),
         "crystal_qmask_bytes": (ctypes.c_size_t, [c_i64]),
         "crystal_qmask_build": (c_i32, [P(QmaskTableC), c_vp, c_vp, c_i64, P(Range), c_i32, c_vp, c_vp]),
         "crystal_run_shared_scan": (c_i32, [P(BatchC), c_vp, c_vp]),
@@ -174,7 +180,7 @@ def load(path: str = LIB_PATH):
             raise ImportError(f"libcrystal.so is missing and could not be built: {e}") from e
     lib = _declare(ctypes.CDLL(path))
     for which, ty in enumerate((Range, HT, Pred, Join, StarQueryC, QmaskTableC, BatchQueryC, BatchC,
-                                ServerTemplateC, ServerConfigC, ServerStatsC, BuildItemC)):
+                                ServerTemplateC, ServerConfigC, ServerStatsC, BuildItemC, ColFormatC)):
         if lib.crystal_struct_size(which) != ctypes.sizeof(ty):
             raise ImportError(f"ABI layout mismatch for {ty.__name__}")
     _lib = lib
@@ -347,10 +353,36 @@ def groupby_agg(group, value, n_groups, out=None, status=None, stream=None):
     return out, status
 
 
+class Narrow:
+    """A narrow fact column: stored uint8 or uint16 offsets (a uint8 or int16
+    tensor holding the bits) from `base`."""
+
+    def __init__(self, data, base):
+        if data.dtype not in (torch.uint8, torch.int16):
+            raise TypeError("narrow columns hold uint8 or 16-bit data")
+        self.data, self.base = data, int(base)
+        self.width = 1 if data.dtype == torch.uint8 else 2
+
+    def numel(self):
+        return self.data.numel()
+
+
+def pack_column(x, base, width, status=None, stream=None):
+    """Narrow copy of an int32 column: offsets from `base` in `width` bytes.
+    Returns (Narrow, status); status is CRYSTAL_ERANGE if a value does not fit."""
+    lib = load()
+    n = x.numel()
+    data = torch.empty(max(n, 8), dtype=torch.uint8 if width == 1 else torch.int16, device=x.device)[:n]
+    status = new_status(x.device) if status is None else status
+    _check(lib.crystal_pack_column(_col(x), n, int(base), int(width), c_vp(data.data_ptr()), _ptr(status),
+                                   _stream(stream)), "crystal_pack_column")
+    return Narrow(data, base), status
+
+
 class StarQuery:
     """Plan of a fused star query (marshalled once into the C struct).
 
-    cols: list of int32 device tensors (the fact columns).
+    cols: list of fact columns: int32 device tensors, or Narrow columns.
     preds: list of (col, lo, hi).
     joins: list of dicts: ``table`` (HashTable), ``fk_col``, optional
         ``filter`` = (bits, shift, lo, hi), optional ``group`` = (bits, shift,
@@ -362,12 +394,17 @@ class StarQuery:
             raise ValueError("plan exceeds the ABI limits")
         n = cols[0].numel() if cols else 0
         for c in cols:
-            if c.dtype != torch.int32 or c.numel() != n or not c.is_cuda:
-                raise ValueError("fact columns must be int32 device tensors of equal length")
+            t = c.data if isinstance(c, Narrow) else c
+            if (not isinstance(c, Narrow) and t.dtype != torch.int32) or c.numel() != n or not t.is_cuda:
+                raise ValueError("fact columns must be int32 device tensors (or Narrow columns) of equal length")
         self.cols, self.joins = list(cols), list(joins)   # keep the memory alive
         q = StarQueryC()
         for i, c in enumerate(cols):
-            q.cols[i] = c.data_ptr()
+            if isinstance(c, Narrow):
+                q.cols[i] = c.data.data_ptr()
+                q.formats[i] = ColFormatC(c.width, c.base)
+            else:
+                q.cols[i] = c.data_ptr()
         q.n_rows, q.n_cols, q.n_preds, q.n_joins = n, len(cols), len(preds), len(joins)
         for i, (col, lo, hi) in enumerate(preds):
             q.preds[i] = Pred(int(col), Range(int(lo), int(hi)))
@@ -388,7 +425,8 @@ class StarQuery:
         self.c = q
         self.n_groups = int(n_groups)
         self.n_rows = n
-        dev = cols[0].device if cols else "cuda"
+        dev = (cols[0].data if isinstance(cols[0], Narrow) else cols[0]).device if cols else "cuda"
+        self.device = dev
         nbytes = load().crystal_star_query_scratch_bytes(ctypes.byref(q))
         self.scratch = torch.empty(max(16, nbytes), dtype=torch.uint8, device=dev) if nbytes else None
         self.scratch_bytes = nbytes
@@ -396,7 +434,7 @@ class StarQuery:
     def run(self, out=None, status=None, stream=None, accumulate=False):
         """Run the query into out (overwritten), or add into out with accumulate=True."""
         lib = load()
-        dev = self.cols[0].device if self.cols else "cuda"
+        dev = self.device
         if out is None:
             out = (torch.zeros if accumulate else torch.empty)(self.n_groups, dtype=torch.int64, device=dev)
         status = new_status(dev) if status is None else status

@@ -131,6 +131,59 @@ __device__ __forceinline__ void block_load_sel(const int32_t *__restrict__ col, 
     }
 }
 
+// Narrow (frame-of-reference) columns: stored values are unsigned E offsets
+// from cbase.  A thread's VEC consecutive items are one VEC * sizeof(E)-byte
+// load; values are widened to int32 in registers.
+template <typename E, int VEC, bool NT>
+__device__ __forceinline__ void load_narrow_vec(const E *__restrict__ p, int32_t cbase, int32_t *dst) {
+    if constexpr (VEC == 1) {
+        dst[0] = cbase + (int32_t)(NT ? __builtin_nontemporal_load(p) : *p);
+    } else {
+        typedef E V __attribute__((ext_vector_type(VEC)));
+        const V x = NT ? __builtin_nontemporal_load(reinterpret_cast<const V *>(p)) : *reinterpret_cast<const V *>(p);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) dst[e] = cbase + (int32_t)x[e];
+    }
+}
+
+template <int BLOCK, int IPT, typename E, bool NT>
+__device__ __forceinline__ void block_load_narrow(const E *__restrict__ col, int32_t cbase, int64_t base,
+                                                  int64_t n, int32_t (&v)[IPT]) {
+    using T = TileShape<BLOCK, IPT>;
+    if (base + T::ITEMS <= n) {
+#pragma unroll
+        for (int c = 0; c < T::CHUNKS; ++c)
+            load_narrow_vec<E, T::VEC, NT>(col + T::index(base, c, 0), cbase, &v[c * T::VEC]);
+    } else {
+#pragma unroll
+        for (int c = 0; c < T::CHUNKS; ++c)
+#pragma unroll
+            for (int e = 0; e < T::VEC; ++e) {
+                int64_t i = T::index(base, c, e);
+                v[c * T::VEC + e] = i < n ? cbase + (int32_t)col[i] : 0;
+            }
+    }
+}
+
+template <int BLOCK, int IPT, typename E, bool NT>
+__device__ __forceinline__ void block_load_sel_narrow(const E *__restrict__ col, int32_t cbase, int64_t base,
+                                                      int64_t n, uint32_t flags, int32_t (&v)[IPT]) {
+    using T = TileShape<BLOCK, IPT>;
+    const bool full = base + T::ITEMS <= n;
+#pragma unroll
+    for (int c = 0; c < T::CHUNKS; ++c) {
+        uint32_t m = (flags >> (c * T::VEC)) & T::VMASK;
+        if (!m) continue;
+        if (full) {
+            load_narrow_vec<E, T::VEC, NT>(col + T::index(base, c, 0), cbase, &v[c * T::VEC]);
+        } else {
+#pragma unroll
+            for (int e = 0; e < T::VEC; ++e)
+                if (m & (1u << e)) v[c * T::VEC + e] = cbase + (int32_t)col[T::index(base, c, e)];
+        }
+    }
+}
+
 // ---------------------------------------------------------- BlockPred ------
 __device__ __forceinline__ bool in_range(int32_t x, int32_t lo, int32_t hi) {
     return x >= lo && x <= hi;

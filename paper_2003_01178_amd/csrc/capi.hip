@@ -149,8 +149,13 @@ crystal_status star_plan_to_dev(const crystal_star_query &q, StarPlanDev &d) {
     };
     for (int c = 0; c < q.n_cols; ++c) {
         if (q.cols[c] && !aligned16(q.cols[c])) return CRYSTAL_EINVAL;
-        d.cols[c] = q.cols[c];
+        d.col[c].p = q.cols[c];
+        const int32_t w = q.formats[c].width;
+        if (w != 0 && w != 1 && w != 2 && w != 4) return CRYSTAL_EINVAL;
+        d.col[c].width = w == 0 ? 4 : w;
+        d.col[c].base = w == 1 || w == 2 ? q.formats[c].base : 0;
     }
+    for (int c = q.n_cols; c < CRYSTAL_MAX_COLS; ++c) d.col[c].width = 4;
     d.n_rows = q.n_rows;
     d.n_groups = q.n_groups;
     d.n_preds = q.n_preds;
@@ -242,6 +247,7 @@ size_t crystal_struct_size(int32_t which) {
     case 9: return sizeof(crystal_server_config);
     case 10: return sizeof(crystal_server_stats);
     case 11: return sizeof(crystal_ht_build_item);
+    case 12: return sizeof(crystal_col_format);
     default: return 0;
     }
 }
@@ -394,6 +400,14 @@ crystal_status crystal_run_star_query_accumulate(const crystal_star_query *q, in
     return run_star(q, out, status, scratch, scratch_bytes, stream, true);
 }
 
+crystal_status crystal_pack_column(const int32_t *in, int64_t n, int32_t base, int32_t width, void *out,
+                                   int32_t *status, void *stream) {
+    if (n < 0 || (width != 1 && width != 2) || !status || (n > 0 && (!in || !out || !aligned16(in) || !aligned16(out))))
+        return CRYSTAL_EINVAL;
+    if (n == 0) return CRYSTAL_OK;
+    return from_hip(launch_pack_column(in, n, base, width, out, status, as_stream(stream)));
+}
+
 // ------------------------------------------------------------ shared scan --
 size_t crystal_qmask_bytes(int64_t span) {
     if (span <= 0) return 0;
@@ -423,6 +437,8 @@ crystal_status crystal_run_shared_scan(const crystal_batch *b, int32_t *status, 
     memset(&d, 0, sizeof(d));
     crystal_status st = star_plan_to_dev(b->plan, d.plan);
     if (st != CRYSTAL_OK) return st;
+    for (int c = 0; c < CRYSTAL_MAX_COLS; ++c)
+        if (d.plan.col[c].width != 4) return CRYSTAL_EINVAL;  // the batch kernel reads int32 columns
     if (b->row_begin < 0 || b->row_end > b->plan.n_rows || (b->row_begin & 3)) return CRYSTAL_EINVAL;
     for (int j = 0; j < b->plan.n_joins; ++j) {
         const crystal_qmask_table &m = b->masks[j];

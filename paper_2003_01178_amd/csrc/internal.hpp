@@ -45,6 +45,8 @@ hipError_t fill_u32(uint32_t *p, int64_t n, uint32_t value, hipStream_t s);
 // Zero two separate 64-bit words with one launch.
 hipError_t zero_pair(uint64_t *a, uint64_t *b, hipStream_t s);
 
+hipError_t launch_pack_column(const int32_t *in, int64_t n, int32_t base, int32_t width, void *out,
+                              int32_t *status, hipStream_t s);
 hipError_t launch_select(const LaunchCfg &cfg, const int32_t *in, int64_t n, int32_t lo, int32_t hi,
                          int32_t *out, int64_t *count, uint64_t *status_words, bool stable, hipStream_t s);
 // Items per selection tile under cfg (status words needed: ceil(n / items)).
@@ -91,8 +93,18 @@ struct StarJoinDev {
     int64_t g_stride;
 };
 
+// One fact column: its storage, its width (4, 2 or 1 bytes per stored value)
+// and, for widths 2 and 1, the base the stored offsets add to.  (One array of
+// these, rather than parallel arrays, keeps dynamically indexed accesses to
+// the kernel argument in the kernel-argument segment.)
+struct ColDev {
+    const int32_t *p;
+    int32_t width;
+    int32_t base;
+};
+
 struct StarPlanDev {
-    const int32_t *cols[CRYSTAL_MAX_COLS];
+    ColDev col[CRYSTAL_MAX_COLS];
     int64_t n_rows;
     int64_t n_groups;
     int32_t n_preds;

@@ -350,4 +350,35 @@ hipError_t launch_project(const LaunchCfg &cfg, const float *x1, const float *x2
     }
 }
 
+// ------------------------------------------------------------ narrow columns --
+// out[i] = in[i] - base as an unsigned E; values that do not fit are stored
+// truncated and reported.
+template <typename E>
+__global__ __launch_bounds__(256) void pack_column_kernel(const int32_t *__restrict__ in, int64_t n, int32_t base,
+                                                          E *__restrict__ out, int32_t *status) {
+    constexpr uint32_t kMax = (uint32_t)(E)~(E)0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    bool bad = false;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const uint32_t d = (uint32_t)in[i] - (uint32_t)base;
+        bad |= in[i] < base || d > kMax;
+        out[i] = (E)d;
+    }
+    if (bad) set_status(status, CRYSTAL_ERANGE);
+}
+
+hipError_t launch_pack_column(const int32_t *in, int64_t n, int32_t base, int32_t width, void *out,
+                              int32_t *status, hipStream_t s) {
+    int64_t grid = (n + 255) / 256;
+    const int64_t cap = (int64_t)device_cu_count() * 16;
+    if (grid > cap) grid = cap;
+    if (width == 2)
+        hipLaunchKernelGGL(pack_column_kernel<uint16_t>, dim3((unsigned)grid), dim3(256), 0, s, in, n, base,
+                           (uint16_t *)out, status);
+    else
+        hipLaunchKernelGGL(pack_column_kernel<uint8_t>, dim3((unsigned)grid), dim3(256), 0, s, in, n, base,
+                           (uint8_t *)out, status);
+    return hipGetLastError();
+}
+
 }  // namespace crystal

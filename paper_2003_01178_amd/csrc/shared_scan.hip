@@ -114,10 +114,10 @@ __global__ __launch_bounds__(BLOCK) void shared_scan_kernel(const BatchDev b, in
             for (int k = 0; k < IPT; ++k) any |= (uint32_t)(qm[k] != 0u) << k;
             const int col = shared_step_col(p, s);
             if (s == 0) {
-                block_load<BLOCK, IPT, true>(p.cols[col], base, b.row_end, v);
+                block_load<BLOCK, IPT, true>(p.col[col].p, base, b.row_end, v);
             } else {
                 if (ballot(any != 0u) == 0) break;
-                block_load_sel<BLOCK, IPT, true>(p.cols[col], base, b.row_end, any, v);
+                block_load_sel<BLOCK, IPT, true>(p.col[col].p, base, b.row_end, any, v);
             }
             if (s < p.n_preds) {
                 // queries outer, items inner: each query's bounds are uniform, and
@@ -180,15 +180,15 @@ __global__ __launch_bounds__(BLOCK) void shared_scan_kernel(const BatchDev b, in
             int64_t g[T::VEC];
 #pragma unroll
             for (int e = 0; e < T::VEC; ++e) g[e] = 0;
-            if (p.agg != CRYSTAL_AGG_COUNT) load_vec_sel<T::VEC>(p.cols[p.agg_col0], row0, b.row_end, sc, a);
+            if (p.agg != CRYSTAL_AGG_COUNT) load_vec_sel<T::VEC>(p.col[p.agg_col0].p, row0, b.row_end, sc, a);
             if (p.agg == CRYSTAL_AGG_SUM_PRODUCT || p.agg == CRYSTAL_AGG_SUM_DIFF)
-                load_vec_sel<T::VEC>(p.cols[p.agg_col1], row0, b.row_end, sc, c);
+                load_vec_sel<T::VEC>(p.col[p.agg_col1].p, row0, b.row_end, sc, c);
             if (!p.scalar) {
                 for (int jj = 0; jj < p.n_joins; ++jj) {
                     const StarJoinDev &j = p.joins[jj];
                     if (j.g_bits == 0) continue;
                     int32_t fk[T::VEC], pay[T::VEC];
-                    load_vec_sel<T::VEC>(p.cols[j.fk_col], row0, b.row_end, sc, fk);
+                    load_vec_sel<T::VEC>(p.col[j.fk_col].p, row0, b.row_end, sc, fk);
 #pragma unroll
                     for (int e = 0; e < T::VEC; ++e) {
                         pay[e] = 0;

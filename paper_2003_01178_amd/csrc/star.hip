@@ -36,6 +36,55 @@ __device__ __forceinline__ int step_col(const StarPlanDev &p, int s) {
     return s < p.n_preds ? p.pred_col[s] : p.joins[s - p.n_preds].fk_col;
 }
 
+// Column access for int32 and narrow (uint16 / uint8 offset) columns; the
+// width is uniform, so the dispatch is a scalar branch.
+__device__ __forceinline__ int32_t col_value(const StarPlanDev &p, int c, int64_t row) {
+    const ColDev &cd = p.col[c];
+    if (cd.width == 2) return cd.base + (int32_t)reinterpret_cast<const uint16_t *>(cd.p)[row];
+    if (cd.width == 1) return cd.base + (int32_t)reinterpret_cast<const uint8_t *>(cd.p)[row];
+    return cd.p[row];
+}
+
+// Tile loads of a dense-phase column.  The descriptor is passed by value (read
+// once per kernel), which keeps the plan in the kernel-argument segment.
+// NARROW 0: int32 columns; 2: both dense columns uint16 offsets; 1: any
+// widths, dispatched at run time.  Separate kernel instances, so that the
+// common layouts carry no width dispatch in the pipelined loop.
+template <int BLOCK, int IPT, int NARROW>
+__device__ __forceinline__ void load_col_tile(const ColDev cd, int64_t n_rows, int64_t base, int32_t (&v)[IPT]) {
+    if constexpr (NARROW == 0)
+        block_load<BLOCK, IPT, true>(cd.p, base, n_rows, v);
+    else if constexpr (NARROW == 2)
+        block_load_narrow<BLOCK, IPT, uint16_t, true>(reinterpret_cast<const uint16_t *>(cd.p), cd.base, base,
+                                                      n_rows, v);
+    else if (cd.width == 2)
+        block_load_narrow<BLOCK, IPT, uint16_t, true>(reinterpret_cast<const uint16_t *>(cd.p), cd.base, base,
+                                                      n_rows, v);
+    else if (cd.width == 1)
+        block_load_narrow<BLOCK, IPT, uint8_t, true>(reinterpret_cast<const uint8_t *>(cd.p), cd.base, base,
+                                                     n_rows, v);
+    else
+        block_load<BLOCK, IPT, true>(cd.p, base, n_rows, v);
+}
+
+template <int BLOCK, int IPT, int NARROW>
+__device__ __forceinline__ void load_col_tile_sel(const ColDev cd, int64_t n_rows, int64_t base, uint32_t flags,
+                                                  int32_t (&v)[IPT]) {
+    if constexpr (NARROW == 0)
+        block_load_sel<BLOCK, IPT, true>(cd.p, base, n_rows, flags, v);
+    else if constexpr (NARROW == 2)
+        block_load_sel_narrow<BLOCK, IPT, uint16_t, true>(reinterpret_cast<const uint16_t *>(cd.p), cd.base, base,
+                                                          n_rows, flags, v);
+    else if (cd.width == 2)
+        block_load_sel_narrow<BLOCK, IPT, uint16_t, true>(reinterpret_cast<const uint16_t *>(cd.p), cd.base, base,
+                                                          n_rows, flags, v);
+    else if (cd.width == 1)
+        block_load_sel_narrow<BLOCK, IPT, uint8_t, true>(reinterpret_cast<const uint8_t *>(cd.p), cd.base, base,
+                                                         n_rows, flags, v);
+    else
+        block_load_sel<BLOCK, IPT, true>(cd.p, base, n_rows, flags, v);
+}
+
 __device__ __forceinline__ bool star_probe(const StarJoinDev &j, int32_t key, int32_t &payload) {
     if (j.kind == CRYSTAL_HT_DIRECT) {
         const uint32_t off = (uint32_t)key - (uint32_t)j.key_min;
@@ -111,27 +160,28 @@ __device__ __forceinline__ uint32_t probe_linear_tile(const StarJoinDev &j, cons
 // Presence test of a whole tile against a bitmap staged in LDS.  `lds` is the
 // workgroup's dynamic LDS, so every lookup is a ds_read (a pointer that might
 // also point to global memory would compile to flat loads through the vector
-// memory path).
+// memory path).  The staged copy is followed by one zero word: a key's word
+// index is clamped to it, so a key outside the table (or an item that is not
+// alive) reads a valid LDS word and is masked afterwards, and the test needs
+// no range compare.  The bit-field extract uses only the low five bits of its
+// offset, so the bit is extracted at off with no masking of off.
+__device__ __forceinline__ uint32_t staged_word_index(int32_t key, int32_t key_min, uint32_t words,
+                                                      uint32_t &off) {
+    off = (uint32_t)key - (uint32_t)key_min;
+    const uint32_t w = off >> 5;
+    return w < words ? w : words;
+}
+
 template <int IPT>
 __device__ __forceinline__ uint32_t probe_staged_tile(const uint32_t *lds, int32_t stage_off, int32_t key_min,
-                                                      int64_t span, const int32_t (&key)[IPT], uint32_t alive) {
-    uint32_t word[IPT];
-    uint32_t ok = 0;
-    const uint32_t last = (uint32_t)(span - 1);  // span >= 1: off is in the table iff off <= last
+                                                      uint32_t words, const int32_t (&key)[IPT], uint32_t alive) {
+    uint32_t word[IPT], off[IPT];
 #pragma unroll
-    for (int k = 0; k < IPT; ++k) {
-        const uint32_t off = (uint32_t)key[k] - (uint32_t)key_min;
-        const bool in = ((alive >> k) & 1u) && off <= last;
-        ok |= (uint32_t)in << k;
-        word[k] = lds[stage_off + (in ? (off >> 5) : 0u)];
-    }
+    for (int k = 0; k < IPT; ++k) word[k] = lds[stage_off + staged_word_index(key[k], key_min, words, off[k])];
     uint32_t hit = 0;
 #pragma unroll
-    for (int k = 0; k < IPT; ++k) {
-        const uint32_t off = (uint32_t)key[k] - (uint32_t)key_min;
-        hit |= ((word[k] >> (off & 31u)) & 1u) << k;
-    }
-    return hit & ok;
+    for (int k = 0; k < IPT; ++k) hit |= __builtin_amdgcn_ubfe(word[k], off[k], 1u) << k;  // bit off & 31
+    return hit & alive;
 }
 
 // The LDS-staged presence test split in two, so that the registers holding
@@ -141,28 +191,27 @@ __device__ __forceinline__ uint32_t probe_staged_tile(const uint32_t *lds, int32
 template <int IPT>
 struct StagedProbe {
     uint32_t word[IPT];
-    uint32_t bit[IPT];
-    uint32_t ok;
-    __device__ __forceinline__ void begin(const uint32_t *lds, int32_t stage_off, int32_t key_min, int64_t span,
-                                          const int32_t (&key)[IPT], uint32_t alive) {
-        const uint32_t last = (uint32_t)(span - 1);
-        ok = 0;
+    uint32_t off[IPT];
+    uint32_t alive;
+    __device__ __forceinline__ void begin(const uint32_t *lds, int32_t stage_off, int32_t key_min, uint32_t words,
+                                          const int32_t (&key)[IPT], uint32_t alive_in) {
+        alive = alive_in;
 #pragma unroll
-        for (int k = 0; k < IPT; ++k) {
-            const uint32_t off = (uint32_t)key[k] - (uint32_t)key_min;
-            const bool in = ((alive >> k) & 1u) && off <= last;
-            ok |= (uint32_t)in << k;
-            bit[k] = off & 31u;
-            word[k] = lds[stage_off + (in ? (off >> 5) : 0u)];
-        }
+        for (int k = 0; k < IPT; ++k) word[k] = lds[stage_off + staged_word_index(key[k], key_min, words, off[k])];
     }
     __device__ __forceinline__ uint32_t end() const {
         uint32_t hit = 0;
 #pragma unroll
-        for (int k = 0; k < IPT; ++k) hit |= ((word[k] >> bit[k]) & 1u) << k;
-        return hit & ok;
+        for (int k = 0; k < IPT; ++k) hit |= __builtin_amdgcn_ubfe(word[k], off[k], 1u) << k;  // bit off & 31
+        return hit & alive;
     }
 };
+
+// Words of a direct table's padded presence bitmap (the staged copy's zero
+// word sits at this index).
+__device__ __forceinline__ uint32_t bitmap_words_of(int64_t span) {
+    return (uint32_t)(((span + 31) / 32 + 63) / 64 * 64);
+}
 
 // One dense step over a tile: a predicate, or a probe of the LDS-staged
 // bitmap (stage_off >= 0), a direct table or a linear-probing table.
@@ -171,7 +220,7 @@ __device__ __forceinline__ uint32_t star_step_tile(const StarPlanDev &p, int s, 
                                                    int32_t stage_off, const int32_t (&v)[IPT], uint32_t alive) {
     if (s < p.n_preds) return block_pred_range<IPT>(v, alive, p.pred_lo[s], p.pred_hi[s]);
     const StarJoinDev &j = p.joins[s - p.n_preds];
-    if (stage_off >= 0) return probe_staged_tile<IPT>(lds, stage_off, j.key_min, j.span, v, alive);
+    if (stage_off >= 0) return probe_staged_tile<IPT>(lds, stage_off, j.key_min, bitmap_words_of(j.span), v, alive);
     if (j.kind == CRYSTAL_HT_DIRECT) return probe_direct_tile<IPT>(j, j.bitmap, v, alive);
     return probe_linear_tile<IPT>(j, v, alive);
 }
@@ -186,17 +235,17 @@ __device__ __forceinline__ void aggregate_row(const StarPlanDev &p, int64_t idx,
             const StarJoinDev &j = p.joins[jj];
             if (j.g_bits == 0) continue;
             int32_t pay = 0;
-            star_probe(j, p.cols[j.fk_col][idx], pay);
+            star_probe(j, col_value(p, j.fk_col, idx), pay);
             g += ((int64_t)payload_field(pay, j.g_shift, j.g_mask, j.g_bits) - (int64_t)j.g_base) * j.g_stride;
         }
     }
     uint64_t val = 1;
     if (p.agg != CRYSTAL_AGG_COUNT) {
-        const int64_t a = p.cols[p.agg_col0][idx];
+        const int64_t a = col_value(p, p.agg_col0, idx);
         if (p.agg == CRYSTAL_AGG_SUM) {
             val = (uint64_t)a;
         } else {
-            const int64_t b = p.cols[p.agg_col1][idx];
+            const int64_t b = col_value(p, p.agg_col1, idx);
             val = p.agg == CRYSTAL_AGG_SUM_PRODUCT ? (uint64_t)(a * b) : (uint64_t)(a - b);
         }
     }
@@ -213,11 +262,11 @@ __device__ __forceinline__ void finish_row(const StarPlanDev &p, int dense, int6
                                            uint64_t *__restrict__ out, uint64_t &scalar_acc, bool &bad_group) {
     const int n_steps = p.n_preds + p.n_joins;
     for (int s = dense; s < n_steps; ++s)
-        if (!star_step_row(p, s, p.cols[step_col(p, s)][row])) return;
+        if (!star_step_row(p, s, col_value(p, step_col(p, s), row))) return;
     aggregate_row(p, row, out, scalar_acc, bad_group);
 }
 
-template <int BLOCK, int IPT, int PF>
+template <int BLOCK, int IPT, int PF, int NARROW>
 __global__ __launch_bounds__(BLOCK) void star_kernel(const StarPlanDev p, uint64_t *__restrict__ out,
                                                      int32_t *status, int64_t n_tiles,
                                                      uint64_t *__restrict__ partials) {
@@ -236,9 +285,10 @@ __global__ __launch_bounds__(BLOCK) void star_kernel(const StarPlanDev p, uint64
         const int32_t so = d == 0 ? so0 : so1;
         if (so < 0) continue;
         const StarJoinDev &j = p.joins[d - p.n_preds];
-        const int64_t n16 = ((j.span + 31) / 32 + 63) / 64 * 16;
+        const int64_t n16 = bitmap_words_of(j.span) / 4;
         const v4i *src = reinterpret_cast<const v4i *>(j.bitmap);
         for (int64_t i = threadIdx.x; i < n16; i += BLOCK) lds_dyn[so / 4 + i] = src[i];
+        if (threadIdx.x == 0) lds_dyn[so / 4 + n16] = v4i{0, 0, 0, 0};  // the zero word after the bitmap
     }
     // one survivor queue per wave: rows are compacted with ballots inside the
     // wave, so waves never wait for each other
@@ -251,8 +301,8 @@ __global__ __launch_bounds__(BLOCK) void star_kernel(const StarPlanDev p, uint64
     bool bad_group = false;
     uint32_t head = 0, tail = 0;  // queue cursors, equal in every lane of the wave
     const int64_t stride = gridDim.x;
-    const int col0 = dense >= 1 ? step_col(p, 0) : 0;
-    const int col1 = dense >= 2 ? step_col(p, 1) : 0;
+    const ColDev cd0 = p.col[dense >= 1 ? step_col(p, 0) : 0];
+    const ColDev cd1 = p.col[dense >= 2 ? step_col(p, 1) : 0];
 
     // Pipeline over this workgroup's tiles t_0, t_1, ...: while tile t_k is
     // finished, the second-step loads of t_{k+1} and the first-step loads of
@@ -267,14 +317,14 @@ __global__ __launch_bounds__(BLOCK) void star_kernel(const StarPlanDev p, uint64
     if (t_cur < n_tiles) {
         alive_c = valid_mask<BLOCK, IPT>(t_cur * T::ITEMS, p.n_rows);
         if (dense >= 1) {
-            block_load<BLOCK, IPT, true>(p.cols[col0], t_cur * T::ITEMS, p.n_rows, a0);
+            load_col_tile<BLOCK, IPT, NARROW>(cd0, p.n_rows, t_cur * T::ITEMS, a0);
             alive_c = star_step_tile<IPT>(p, 0, lds, so0, a0, alive_c);
         }
-        if (dense >= 2) block_load_sel<BLOCK, IPT, true>(p.cols[col1], t_cur * T::ITEMS, p.n_rows, alive_c, b0);
+        if (dense >= 2) load_col_tile_sel<BLOCK, IPT, NARROW>(cd1, p.n_rows, t_cur * T::ITEMS, alive_c, b0);
         if (dense >= 1 && t_cur + stride < n_tiles)
-            block_load<BLOCK, IPT, true>(p.cols[col0], (t_cur + stride) * T::ITEMS, p.n_rows, a0);
+            load_col_tile<BLOCK, IPT, NARROW>(cd0, p.n_rows, (t_cur + stride) * T::ITEMS, a0);
         if (PF == 2 && dense >= 1 && t_cur + 2 * stride < n_tiles)
-            block_load<BLOCK, IPT, true>(p.cols[col0], (t_cur + 2 * stride) * T::ITEMS, p.n_rows, a1);
+            load_col_tile<BLOCK, IPT, NARROW>(cd0, p.n_rows, (t_cur + 2 * stride) * T::ITEMS, a1);
     }
 
     // One pipeline iteration.  `an` holds the first-step column of t_nxt;
@@ -290,15 +340,15 @@ __global__ __launch_bounds__(BLOCK) void star_kernel(const StarPlanDev p, uint64
                 // staged first step: issue its LDS reads, then reuse the key
                 // registers for the prefetch before testing the bits
                 StagedProbe<IPT> pr;
-                pr.begin(lds, so0, p.joins[0].key_min, p.joins[0].span, an, alive_n);
-                if (t_pf < n_tiles) block_load<BLOCK, IPT, true>(p.cols[col0], t_pf * T::ITEMS, p.n_rows, an);
+                pr.begin(lds, so0, p.joins[0].key_min, bitmap_words_of(p.joins[0].span), an, alive_n);
+                if (t_pf < n_tiles) load_col_tile<BLOCK, IPT, NARROW>(cd0, p.n_rows, t_pf * T::ITEMS, an);
                 alive_n = pr.end();
             } else {
                 if (dense >= 1) alive_n = star_step_tile<IPT>(p, 0, lds, so0, an, alive_n);
                 if (dense >= 1 && t_pf < n_tiles)
-                    block_load<BLOCK, IPT, true>(p.cols[col0], t_pf * T::ITEMS, p.n_rows, an);
+                    load_col_tile<BLOCK, IPT, NARROW>(cd0, p.n_rows, t_pf * T::ITEMS, an);
             }
-            if (dense >= 2) block_load_sel<BLOCK, IPT, true>(p.cols[col1], t_nxt * T::ITEMS, p.n_rows, alive_n, bn);
+            if (dense >= 2) load_col_tile_sel<BLOCK, IPT, NARROW>(cd1, p.n_rows, t_nxt * T::ITEMS, alive_n, bn);
         }
         if (dense >= 2) alive_c = star_step_tile<IPT>(p, 1, lds, so1, bc, alive_c);
 
@@ -387,7 +437,7 @@ static hipError_t star_t(const LaunchCfg &cfg, StarPlanDev p, uint64_t *out, int
         const StarJoinDev &j = p.joins[d - p.n_preds];
         if (j.kind != CRYSTAL_HT_DIRECT || j.f_bits != 0 || bitmap_bytes(j) > kStageBytesPerStep) continue;
         p.stage_off[d] = (int32_t)words;
-        words += bitmap_bytes(j) / 4;
+        words += bitmap_bytes(j) / 4 + 4;  // the bitmap, then one zero 16-byte chunk
     }
     // per-wave queue: up to one wave's tile share (64 * IPT rows) on top of
     // fewer than 64 rows left from earlier tiles
@@ -407,7 +457,14 @@ static hipError_t star_t(const LaunchCfg &cfg, StarPlanDev p, uint64_t *out, int
     if (grid > n_tiles) grid = n_tiles;
     if (grid < 1) grid = 1;
     // prefetch depth one tile (a second register buffer costs more waves than it gains)
-    auto fn = star_kernel<BLOCK, IPT, 1>;
+    int n4 = 0, n2 = 0;
+    for (int d = 0; d < dense; ++d) {
+        const int c = d < p.n_preds ? p.pred_col[d] : p.joins[d - p.n_preds].fk_col;
+        n4 += p.col[c].width == 4;
+        n2 += p.col[c].width == 2;
+    }
+    auto fn = n4 == dense ? star_kernel<BLOCK, IPT, 1, 0>
+                          : n2 == dense ? star_kernel<BLOCK, IPT, 1, 2> : star_kernel<BLOCK, IPT, 1, 1>;
     if (lds_bytes > 65536) {
         hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            (int)lds_bytes);

@@ -34,10 +34,10 @@ def test_every_declared_symbol_is_exported(cx):
 
 def test_struct_layout_matches_binding(cx):
     lib = cx.load()
-    assert lib.crystal_abi_version() == 3
+    assert lib.crystal_abi_version() == 4
     for which, ty in enumerate((cx.Range, cx.HT, cx.Pred, cx.Join, cx.StarQueryC, cx.QmaskTableC,
                                 cx.BatchQueryC, cx.BatchC, cx.ServerTemplateC, cx.ServerConfigC,
-                                cx.ServerStatsC, cx.BuildItemC)):
+                                cx.ServerStatsC, cx.BuildItemC, cx.ColFormatC)):
         assert lib.crystal_struct_size(which) == ctypes.sizeof(ty), ty.__name__
     assert lib.crystal_struct_size(99) == 0
 

@@ -145,6 +145,27 @@ def test_star_ragged_sizes():
         assert np.array_equal(out.cpu().numpy(), star_oracle(t)[0])
 
 
+@pytest.mark.parametrize("order", [(1, 0, 2, 3), (0, 1, 2, 3)])
+def test_star_foreign_keys_outside_the_tables(order):
+    """Fact keys below, above and far outside each dimension's key range (and
+    at the padding bits just past the last key) never match, whichever step
+    probes them, LDS-staged or not."""
+    announce("star outside keys", order)
+    t = datagen.star_tables(n=300_007, workload=66)
+    rng = np.random.default_rng(66)
+    for j, d in enumerate(t.dims):
+        lo, hi = int(d.key.min()), int(d.key.max())
+        bad = rng.random(t.n) < 0.2
+        choices = np.array([lo - 1, hi + 1, hi + 31, hi + 64 * 32 + 5, -(2 ** 31), 2 ** 31 - 1, lo - 4096],
+                           dtype=np.int64)
+        t.fk[j] = np.where(bad, choices[rng.integers(0, len(choices), size=t.n)], t.fk[j]).astype(np.int32)
+    s = queries.StarSchema(t)
+    s.build()
+    out, st = s.plan(order).run()
+    cx.check_status(st)
+    assert np.array_equal(out.cpu().numpy(), star_oracle(t)[0])
+
+
 def _pack(filter_attr, group_attr, gshift):
     return (filter_attr.astype(np.int64) | (group_attr.astype(np.int64) << gshift)).astype(np.int32)
 
