@@ -150,10 +150,11 @@ struct BatchDev {
     uint64_t *out[kMaxBatch];
     int64_t row_begin;
     int64_t row_end;
-    // set by the launcher: the first join's mask table is copied into LDS at
-    // 64-bit word stage_off of the dynamic LDS when stage_words (32-bit) > 0
-    int64_t stage_off;
-    int64_t stage_words;
+    // set by the launcher: join j's mask table is copied into the dynamic LDS
+    // at 32-bit word stage_off[j] (stage_words[j] words, then one zero word)
+    // when stage_words[j] > 0
+    int64_t stage_off[CRYSTAL_MAX_JOINS];
+    int64_t stage_words[CRYSTAL_MAX_JOINS];
 };
 
 hipError_t launch_qmask_build(uint16_t *table, int64_t span, int32_t key_min, const int32_t *keys,

@@ -81,85 +81,106 @@ template <int BLOCK, int IPT>
 __global__ __launch_bounds__(BLOCK) void shared_scan_kernel(const BatchDev b, int32_t *status, int64_t n_tiles) {
     using T = TileShape<BLOCK, IPT>;
     // scalar results: one private LDS accumulator per (query, thread), so that
-    // survivors add without atomics; reduced once per workgroup at the end
+    // adds never contend; reduced once per workgroup at the end
     // dynamic LDS: b.n_queries * BLOCK words for a scalar plan, then the
-    // staged mask table of the first join (see BatchDev::stage_off)
+    // staged mask tables (see BatchDev::stage_off)
     extern __shared__ uint64_t dyn[];
     uint64_t(*acc)[BLOCK] = reinterpret_cast<uint64_t(*)[BLOCK]>(dyn);
-    uint32_t *stage_words = reinterpret_cast<uint32_t *>(dyn + b.stage_off);
-    const uint16_t *stage = reinterpret_cast<const uint16_t *>(dyn + b.stage_off);
+    uint32_t *lds_words = reinterpret_cast<uint32_t *>(dyn);
     __shared__ uint64_t red[BLOCK / kWave];
     const StarPlanDev &p = b.plan;
     const int n_steps = p.n_preds + p.n_joins;
     if (p.scalar) {
         for (int q = 0; q < b.n_queries; ++q) acc[q][threadIdx.x] = 0;
     }
-    const bool staged = b.stage_words > 0;
-    if (staged) {
-        const uint32_t *src = reinterpret_cast<const uint32_t *>(b.mask[0]);
-        for (int64_t i = threadIdx.x; i < b.stage_words; i += BLOCK) stage_words[i] = src[i];
-        __syncthreads();
+    bool any_staged = false;
+    for (int j = 0; j < p.n_joins; ++j) {
+        if (b.stage_words[j] == 0) continue;
+        any_staged = true;
+        const uint32_t *src = reinterpret_cast<const uint32_t *>(b.mask[j]);
+        uint32_t *dst = lds_words + b.stage_off[j];
+        for (int64_t i = threadIdx.x; i < b.stage_words[j]; i += BLOCK) dst[i] = src[i];
+        if (threadIdx.x == 0) dst[b.stage_words[j]] = 0u;  // entries past the table read 0
     }
+    if (any_staged) __syncthreads();
     bool bad_group = false;
-    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+    uint32_t qm[IPT];
+
+    // One plan step over the tile's values x: range predicates per query, or a
+    // lookup of the join's query-mask table.
+    auto apply_step = [&](int s, const int32_t(&x)[IPT]) {
+        if (s < p.n_preds) {
+            // queries outer, items inner: each query's bounds are uniform, and
+            // a query no row of the wave is still alive for is skipped
+            uint32_t lane_live = 0, m[IPT];
+#pragma unroll
+            for (int k = 0; k < IPT; ++k) {
+                lane_live |= qm[k];
+                m[k] = 0;
+            }
+            for (int q = 0; q < b.n_queries; ++q) {
+                const uint32_t bit = 1u << q;
+                if (ballot((lane_live & bit) != 0u) == 0) continue;
+                const int32_t lo = b.pred_lo[q][s], hi = b.pred_hi[q][s];
+#pragma unroll
+                for (int k = 0; k < IPT; ++k) m[k] |= in_range(x[k], lo, hi) ? bit : 0u;
+            }
+#pragma unroll
+            for (int k = 0; k < IPT; ++k) qm[k] &= m[k];
+        } else {
+            const int j = s - p.n_preds;
+            const uint32_t last = (uint32_t)(b.mask_span[j] - 1);
+            const int32_t kmin = b.mask_kmin[j];
+            if (b.stage_words[j] > 0) {
+                // LDS-typed path (a pointer that may also address global
+                // memory would compile to flat loads).  Keys outside the
+                // table are clamped to the zero entry after it, so no range
+                // test is needed.
+                const uint16_t *stage = reinterpret_cast<const uint16_t *>(lds_words + b.stage_off[j]);
+                const uint32_t span = last + 1u;
+#pragma unroll
+                for (int k = 0; k < IPT; ++k) {
+                    const uint32_t off = (uint32_t)x[k] - (uint32_t)kmin;
+                    qm[k] &= (uint32_t)stage[off < span ? off : span];
+                }
+            } else {
+                const uint16_t *mt = b.mask[j];
+#pragma unroll
+                for (int k = 0; k < IPT; ++k) {
+                    const uint32_t off = (uint32_t)x[k] - (uint32_t)kmin;
+                    const bool in = qm[k] != 0u && off <= last;
+                    qm[k] &= in ? (uint32_t)mt[off] : 0u;
+                }
+            }
+        }
+    };
+
+    // One tile.  `cur` holds the first step's column of this tile (loaded one
+    // tile ahead); the same column of the workgroup's next tile is loaded into
+    // `nxt` before this tile's steps run, so that load overlaps them.
+    const int col0 = n_steps > 0 ? shared_step_col(p, 0) : 0;
+    auto run_tile = [&](int64_t tile, int32_t(&cur)[IPT], int32_t(&nxt)[IPT]) {
         const int64_t base = b.row_begin + tile * T::ITEMS;
         const uint32_t valid = valid_mask<BLOCK, IPT>(base, b.row_end);
-        uint32_t qm[IPT];
 #pragma unroll
         for (int k = 0; k < IPT; ++k) qm[k] = ((valid >> k) & 1u) ? b.all_queries : 0u;
-        int32_t v[IPT];
-        for (int s = 0; s < n_steps; ++s) {
+        // the second step's column is read in full together with the first
+        // (with up to 16 queries most of its vectors hold a live row anyway),
+        // so the two loads share one memory round trip
+        int32_t w[IPT];
+        if (n_steps > 1) block_load<BLOCK, IPT, true>(p.col[shared_step_col(p, 1)].p, base, b.row_end, w);
+        const int64_t tn = tile + gridDim.x;
+        if (n_steps > 0 && tn < n_tiles)
+            block_load<BLOCK, IPT, true>(p.col[col0].p, b.row_begin + tn * T::ITEMS, b.row_end, nxt);
+        if (n_steps > 0) apply_step(0, cur);
+        if (n_steps > 1) apply_step(1, w);
+        for (int s = 2; s < n_steps; ++s) {
             uint32_t any = 0;
 #pragma unroll
             for (int k = 0; k < IPT; ++k) any |= (uint32_t)(qm[k] != 0u) << k;
-            const int col = shared_step_col(p, s);
-            if (s == 0) {
-                block_load<BLOCK, IPT, true>(p.col[col].p, base, b.row_end, v);
-            } else {
-                if (ballot(any != 0u) == 0) break;
-                block_load_sel<BLOCK, IPT, true>(p.col[col].p, base, b.row_end, any, v);
-            }
-            if (s < p.n_preds) {
-                // queries outer, items inner: each query's bounds are uniform, and
-                // a query no row of the wave is still alive for is skipped
-                uint32_t lane_live = 0, m[IPT];
-#pragma unroll
-                for (int k = 0; k < IPT; ++k) {
-                    lane_live |= qm[k];
-                    m[k] = 0;
-                }
-                for (int q = 0; q < b.n_queries; ++q) {
-                    const uint32_t bit = 1u << q;
-                    if (ballot((lane_live & bit) != 0u) == 0) continue;
-                    const int32_t lo = b.pred_lo[q][s], hi = b.pred_hi[q][s];
-#pragma unroll
-                    for (int k = 0; k < IPT; ++k) m[k] |= in_range(v[k], lo, hi) ? bit : 0u;
-                }
-#pragma unroll
-                for (int k = 0; k < IPT; ++k) qm[k] &= m[k];
-            } else {
-                const int j = s - p.n_preds;
-                const uint32_t last = (uint32_t)(b.mask_span[j] - 1);
-                const int32_t kmin = b.mask_kmin[j];
-                if (j == 0 && staged) {
-                    // LDS-typed path (a pointer that may also address global
-                    // memory would compile to flat loads)
-#pragma unroll
-                    for (int k = 0; k < IPT; ++k) {
-                        const uint32_t off = (uint32_t)v[k] - (uint32_t)kmin;
-                        const bool in = qm[k] != 0u && off <= last;
-                        qm[k] &= in ? (uint32_t)stage[off] : 0u;
-                    }
-                } else {
-                    const uint16_t *mt = b.mask[j];
-#pragma unroll
-                    for (int k = 0; k < IPT; ++k) {
-                        const uint32_t off = (uint32_t)v[k] - (uint32_t)kmin;
-                        const bool in = qm[k] != 0u && off <= last;
-                        qm[k] &= in ? (uint32_t)mt[off] : 0u;
-                    }
-                }
-            }
+            if (ballot(any != 0u) == 0) break;
+            block_load_sel<BLOCK, IPT, true>(p.col[shared_step_col(p, s)].p, base, b.row_end, any, w);
+            apply_step(s, w);
         }
         // survivors: the measure and group index once per row, then every query
         // that kept the row.  A vector of VEC rows is handled at a time: its
@@ -170,7 +191,7 @@ __global__ __launch_bounds__(BLOCK) void shared_scan_kernel(const BatchDev b, in
         uint32_t surv = 0;
 #pragma unroll
         for (int k = 0; k < IPT; ++k) surv |= (uint32_t)(qm[k] != 0u) << k;
-        if (ballot(surv != 0u) == 0) continue;
+        if (ballot(surv != 0u) == 0) return;
 #pragma unroll
         for (int ch = 0; ch < T::CHUNKS; ++ch) {
             const uint32_t sc = (surv >> (ch * T::VEC)) & T::VMASK;
@@ -224,14 +245,28 @@ __global__ __launch_bounds__(BLOCK) void shared_scan_kernel(const BatchDev b, in
                 while (m) {
                     const int q = __builtin_ctz(m);
                     m &= m - 1u;
-                    if (p.scalar)
-                        acc[q][threadIdx.x] += val;
+                    if (p.scalar)  // private slot: an LDS add without return, no read-modify-write wait
+                        __hip_atomic_fetch_add((__attribute__((address_space(3))) uint64_t *)&acc[q][threadIdx.x],
+                                               val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                     else
                         atomic_add_u64(b.out[q] + g[e], val);
                 }
             }
             __builtin_amdgcn_sched_barrier(0);
         }
+    };
+
+    int32_t va[IPT], vb[IPT];
+    int64_t tile = blockIdx.x;
+    if (n_steps > 0 && tile < n_tiles)
+        block_load<BLOCK, IPT, true>(p.col[col0].p, b.row_begin + tile * T::ITEMS, b.row_end, va);
+    // unrolled by two so that the buffer receiving loads is never copied
+    while (tile < n_tiles) {
+        run_tile(tile, va, vb);
+        tile += gridDim.x;
+        if (tile >= n_tiles) break;
+        run_tile(tile, vb, va);
+        tile += gridDim.x;
     }
     if (bad_group) set_status(status, CRYSTAL_ERANGE);
     if (p.scalar) {
@@ -251,24 +286,31 @@ static hipError_t shared_t(const LaunchCfg &cfg_in, const BatchDev &b_in, int32_
     const int64_t n_tiles = (rows + T::ITEMS - 1) / T::ITEMS;
     LaunchCfg cfg = cfg_in;
     if (cfg.grid_per_cu <= 0) cfg.grid_per_cu = (2048 / BLOCK) > 0 ? (2048 / BLOCK) : 1;
-    // LDS: the scalar accumulators, then the first join's mask table when it
-    // fits beside them without dropping below 8 waves per CU
-    const int64_t acc_words = b.plan.scalar ? (int64_t)b.n_queries * BLOCK : 0;
-    b.stage_off = acc_words;
-    b.stage_words = 0;
-    if (b.plan.n_joins > 0) {
-        const int64_t words = (b.mask_span[0] + 1) / 2;
-        const int64_t bytes = acc_words * 8 + words * 4;
-        const int64_t min_blocks = (8 * kWave + BLOCK - 1) / BLOCK;
-        const int64_t fit = device_lds_per_cu() / (bytes + 1024);
-        if (bytes + 1024 <= device_lds_per_block() && fit >= min_blocks) {
-            b.stage_words = words;
-            if (cfg.grid_per_cu > fit) cfg.grid_per_cu = (int)fit;
-        }
+    // LDS: the scalar accumulators, then, in join order, every join's mask
+    // table (plus one zero word) that still fits without dropping below 8
+    // waves per CU
+    const int64_t acc_words32 = b.plan.scalar ? (int64_t)b.n_queries * BLOCK * 2 : 0;
+    const int64_t min_blocks = (8 * kWave + BLOCK - 1) / BLOCK;
+    int64_t words32 = acc_words32;
+    for (int j = 0; j < CRYSTAL_MAX_JOINS; ++j) {
+        b.stage_off[j] = 0;
+        b.stage_words[j] = 0;
+        if (j >= b.plan.n_joins) continue;
+        const int64_t w = (b.mask_span[j] + 1) / 2;
+        const int64_t bytes = (words32 + w + 1) * 4;
+        if (bytes + 1024 > device_lds_per_block() || device_lds_per_cu() / (bytes + 1024) < min_blocks) continue;
+        b.stage_off[j] = words32;
+        b.stage_words[j] = w;
+        words32 += w + 1;
+    }
+    const int64_t lds_bytes = words32 * 4;
+    if (words32 > acc_words32) {
+        const int64_t fit = device_lds_per_cu() / (lds_bytes + 1024);
+        if (cfg.grid_per_cu > fit) cfg.grid_per_cu = (int)fit;
     }
     const int64_t grid = grid_for(n_tiles, cfg);
     if (grid == 0) return hipSuccess;
-    const size_t lds = (size_t)(acc_words * 8 + b.stage_words * 4);
+    const size_t lds = (size_t)lds_bytes;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute((const void *)shared_scan_kernel<BLOCK, IPT>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
