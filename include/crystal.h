@@ -464,6 +464,15 @@ crystal_status crystal_radix_partition(const uint32_t *keys, const uint32_t *val
                                        uint32_t *part_offsets, void *scratch, size_t scratch_bytes,
                                        void *stream);
 
+/* The same pass with the unstable shuffle of section 4.4: the partitions,
+ * their bounds and the pairs in each partition are those of
+ * crystal_radix_partition, but pairs with equal digits may appear in any
+ * order within their partition.  Cheaper per item (no ballot ranking). */
+crystal_status crystal_radix_partition_unstable(const uint32_t *keys, const uint32_t *vals, int64_t n,
+                                                int32_t shift, int32_t bits, uint32_t *out_keys,
+                                                uint32_t *out_vals, uint32_t *part_offsets, void *scratch,
+                                                size_t scratch_bytes, void *stream);
+
 /* Scratch (device, 256-byte aligned) of crystal_sort_pairs: one ping-pong  */
 /* copy of the keys (and of the values when with_values) plus one pass's    */
 /* scratch.                                                                 */

@@ -149,6 +149,8 @@ def _declare(lib):
         "crystal_radix_partition_scratch_bytes": (ctypes.c_size_t, [c_i64]),
         "crystal_radix_partition": (c_i32, [c_vp, c_vp, c_i64, c_i32, c_i32, c_vp, c_vp, c_vp, c_vp,
                                             ctypes.c_size_t, c_vp]),
+        "crystal_radix_partition_unstable": (c_i32, [c_vp, c_vp, c_i64, c_i32, c_i32, c_vp, c_vp, c_vp, c_vp,
+                                                     ctypes.c_size_t, c_vp]),
         "crystal_sort_pairs_scratch_bytes": (ctypes.c_size_t, [c_i64, c_i32]),
         "crystal_sort_pairs": (c_i32, [c_vp, c_vp, c_i64, c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp]),
         "crystal_tune_variants": (c_i32, [c_i32, P(c_i32), P(c_i32), c_i32]),
@@ -671,8 +673,9 @@ def radix_histogram(keys, shift, bits, hist=None, stream=None):
 
 
 def radix_partition(keys, shift, bits, vals=None, out_keys=None, out_vals=None, part_offsets=None,
-                    scratch=None, stream=None):
-    """Section 4.4 partition pass (histogram + stable shuffle) on one digit.
+                    scratch=None, stream=None, stable=True):
+    """Section 4.4 partition pass (histogram + shuffle) on one digit; stable=False
+    takes the unstable shuffle (equal digits in any order within a partition).
 
     Returns (out_keys, out_vals or None, part_offsets[2^bits + 1])."""
     lib = load()
@@ -684,10 +687,11 @@ def radix_partition(keys, shift, bits, vals=None, out_keys=None, out_vals=None, 
     nb = (1 << int(bits)) + 1
     part_offsets = torch.empty(nb, dtype=torch.int32, device=dev) if part_offsets is None else part_offsets
     scratch = _scratch(lib.crystal_radix_partition_scratch_bytes(n), scratch, dev)
-    _check(lib.crystal_radix_partition(_words(keys, n, "keys"), _words(vals, n, "vals"), n, int(shift), int(bits),
-                                       _words(out_keys, n, "out_keys"), _words(out_vals, n, "out_vals"),
-                                       _words(part_offsets, nb, "part_offsets"), _ptr(scratch), scratch.numel(),
-                                       _stream(stream)), "crystal_radix_partition")
+    fn = lib.crystal_radix_partition if stable else lib.crystal_radix_partition_unstable
+    _check(fn(_words(keys, n, "keys"), _words(vals, n, "vals"), n, int(shift), int(bits),
+              _words(out_keys, n, "out_keys"), _words(out_vals, n, "out_vals"),
+              _words(part_offsets, nb, "part_offsets"), _ptr(scratch), scratch.numel(), _stream(stream)),
+           "crystal_radix_partition")
     return out_keys, out_vals, part_offsets
 
 

@@ -533,10 +533,10 @@ size_t crystal_radix_partition_scratch_bytes(int64_t n) {
     return (size_t)radix_pass_scratch_bytes(tune_lookup(CRYSTAL_K_RADIX, n), n);
 }
 
-crystal_status crystal_radix_partition(const uint32_t *keys, const uint32_t *vals, int64_t n, int32_t shift,
-                                       int32_t bits, uint32_t *out_keys, uint32_t *out_vals,
-                                       uint32_t *part_offsets, void *scratch, size_t scratch_bytes,
-                                       void *stream) {
+static crystal_status radix_partition_common(const uint32_t *keys, const uint32_t *vals, int64_t n, int32_t shift,
+                                             int32_t bits, uint32_t *out_keys, uint32_t *out_vals,
+                                             uint32_t *part_offsets, void *scratch, size_t scratch_bytes,
+                                             void *stream, bool stable) {
     if (bits < 1 || bits > 8 || shift < 0 || shift + bits > 32 || !radix_args_ok(keys, vals, n, out_keys, out_vals))
         return CRYSTAL_EINVAL;
     const LaunchCfg cfg = tune_lookup(CRYSTAL_K_RADIX, n);
@@ -546,7 +546,23 @@ crystal_status crystal_radix_partition(const uint32_t *keys, const uint32_t *val
         if (scratch_bytes < (size_t)radix_pass_scratch_bytes(cfg, n)) return CRYSTAL_ESCRATCH;
     }
     return from_hip(launch_radix_partition(cfg, keys, vals, n, shift, bits, out_keys, out_vals, part_offsets,
-                                           scratch, as_stream(stream)));
+                                           scratch, stable, as_stream(stream)));
+}
+
+crystal_status crystal_radix_partition(const uint32_t *keys, const uint32_t *vals, int64_t n, int32_t shift,
+                                       int32_t bits, uint32_t *out_keys, uint32_t *out_vals,
+                                       uint32_t *part_offsets, void *scratch, size_t scratch_bytes,
+                                       void *stream) {
+    return radix_partition_common(keys, vals, n, shift, bits, out_keys, out_vals, part_offsets, scratch,
+                                  scratch_bytes, stream, true);
+}
+
+crystal_status crystal_radix_partition_unstable(const uint32_t *keys, const uint32_t *vals, int64_t n,
+                                                int32_t shift, int32_t bits, uint32_t *out_keys,
+                                                uint32_t *out_vals, uint32_t *part_offsets, void *scratch,
+                                                size_t scratch_bytes, void *stream) {
+    return radix_partition_common(keys, vals, n, shift, bits, out_keys, out_vals, part_offsets, scratch,
+                                  scratch_bytes, stream, false);
 }
 
 static int64_t round256(int64_t b) { return (b + 255) / 256 * 256; }
@@ -576,7 +592,7 @@ crystal_status crystal_sort_pairs(const uint32_t *keys, const uint32_t *vals, in
     uint32_t *ok[4] = {tk, out_keys, tk, out_keys};
     uint32_t *ov[4] = {tv, out_vals, tv, out_vals};
     for (int p = 0; p < 4; ++p) {
-        hipError_t e = launch_radix_partition(cfg, ik[p], iv[p], n, 8 * p, 8, ok[p], ov[p], nullptr, pass,
+        hipError_t e = launch_radix_partition(cfg, ik[p], iv[p], n, 8 * p, 8, ok[p], ov[p], nullptr, pass, true,
                                               as_stream(stream));
         if (e != hipSuccess) return CRYSTAL_EHIP;
     }

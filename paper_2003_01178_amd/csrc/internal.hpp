@@ -174,6 +174,6 @@ hipError_t launch_radix_histogram(const LaunchCfg &cfg, const uint32_t *keys, in
                                   uint32_t *hist, hipStream_t s);
 hipError_t launch_radix_partition(const LaunchCfg &cfg, const uint32_t *keys, const uint32_t *vals, int64_t n,
                                   int shift, int bits, uint32_t *out_keys, uint32_t *out_vals,
-                                  uint32_t *part_offsets, void *scratch, hipStream_t s);
+                                  uint32_t *part_offsets, void *scratch, bool stable, hipStream_t s);
 
 }  // namespace crystal

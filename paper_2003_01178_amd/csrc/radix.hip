@@ -224,8 +224,12 @@ __device__ __forceinline__ void load_tile(const uint32_t *__restrict__ keys, con
 }
 
 // One workgroup per chunk of tiles_per_block tiles (the chunks the count
-// matrix's columns b * sub .. b * sub + sub - 1 counted).
-template <int BLOCK, int IPT, bool VALS>
+// matrix's columns b * sub .. b * sub + sub - 1 counted).  STABLE: ballot
+// ranking in input order; otherwise every item takes its rank from an LDS
+// atomic on its wave's digit counter, which orders equal digits of one load
+// arbitrarily (the unstable shuffle of section 4.4) for far fewer
+// instructions per item.
+template <int BLOCK, int IPT, bool VALS, bool STABLE>
 __global__ __launch_bounds__(BLOCK) void radix_shuffle_kernel(
     const uint32_t *__restrict__ keys, const uint32_t *__restrict__ vals, int64_t n, int shift, uint32_t mask,
     int64_t n_tiles, int64_t tiles_per_block, int sub, const uint32_t *__restrict__ counts, int64_t cols,
@@ -277,6 +281,13 @@ __global__ __launch_bounds__(BLOCK) void radix_shuffle_kernel(
         asm volatile("" : "+v"(tidv));
         // 1. rank every item among the wave's earlier items of its digit
         uint32_t rank[IPT];
+        if constexpr (!STABLE) {
+#pragma unroll
+            for (int k = 0; k < IPT; ++k) {
+                rank[k] = 0;
+                if (off0 + k * kWave < rem) rank[k] = atomicAdd(&my_wc[digit_of(key[k], shift, mask)], 1u);
+            }
+        } else
 #pragma unroll
         for (int k = 0; k < IPT; ++k) {
             const bool valid = off0 + k * kWave < rem;
@@ -364,23 +375,14 @@ struct RadixGeom {
 
 template <int BLOCK, int IPT>
 struct RadixKernels {
-    static hipError_t prepare() {
-        static bool done[2] = {false, false};
-        hipError_t e = hipSuccess;
-        if (!done[0]) {
-            e = hipFuncSetAttribute((const void *)radix_shuffle_kernel<BLOCK, IPT, false>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)ShuffleLds<BLOCK, IPT, false>::BYTES);
-            if (e != hipSuccess) return e;
-            done[0] = true;
-        }
-        if (!done[1]) {
-            e = hipFuncSetAttribute((const void *)radix_shuffle_kernel<BLOCK, IPT, true>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)ShuffleLds<BLOCK, IPT, true>::BYTES);
-            if (e != hipSuccess) return e;
-            done[1] = true;
-        }
+    template <bool VALS, bool STABLE>
+    static hipError_t prepare_one() {
+        static bool done = false;
+        if (done) return hipSuccess;
+        hipError_t e = hipFuncSetAttribute((const void *)radix_shuffle_kernel<BLOCK, IPT, VALS, STABLE>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)ShuffleLds<BLOCK, IPT, VALS>::BYTES);
+        if (e == hipSuccess) done = true;
         return e;
     }
 
@@ -397,22 +399,28 @@ struct RadixKernels {
         return hipGetLastError();
     }
 
+    template <bool VALS, bool STABLE>
+    static hipError_t shuffle_t(const uint32_t *keys, const uint32_t *vals, int64_t n, int shift, uint32_t mask,
+                                const RadixGeom &g, const uint32_t *counts, const uint32_t *totals, uint32_t *ok,
+                                uint32_t *ov, uint32_t *part_offsets, hipStream_t s) {
+        hipError_t e = prepare_one<VALS, STABLE>();
+        if (e != hipSuccess) return e;
+        const size_t lds = ShuffleLds<BLOCK, IPT, VALS>::BYTES;
+        hipLaunchKernelGGL((radix_shuffle_kernel<BLOCK, IPT, VALS, STABLE>), dim3((unsigned)g.grid), dim3(BLOCK),
+                           lds, s, keys, vals, n, shift, mask, g.n_tiles, g.tiles_per_block, g.sub, counts, g.cols,
+                           totals, ok, ov, part_offsets);
+        return hipGetLastError();
+    }
+
     static hipError_t shuffle(const uint32_t *keys, const uint32_t *vals, int64_t n, int shift, uint32_t mask,
                               const RadixGeom &g, const uint32_t *counts, const uint32_t *totals,
-                              uint32_t *ok, uint32_t *ov, uint32_t *part_offsets, hipStream_t s) {
-        hipError_t e = prepare();
-        if (e != hipSuccess) return e;
-        const size_t lds_kv = ShuffleLds<BLOCK, IPT, true>::BYTES;
-        const size_t lds_k = ShuffleLds<BLOCK, IPT, false>::BYTES;
+                              uint32_t *ok, uint32_t *ov, uint32_t *part_offsets, bool stable, hipStream_t s) {
         if (vals)
-            hipLaunchKernelGGL((radix_shuffle_kernel<BLOCK, IPT, true>), dim3((unsigned)g.grid), dim3(BLOCK),
-                               lds_kv, s, keys, vals, n, shift, mask, g.n_tiles, g.tiles_per_block, g.sub,
-                               counts, g.cols, totals, ok, ov, part_offsets);
-        else
-            hipLaunchKernelGGL((radix_shuffle_kernel<BLOCK, IPT, false>), dim3((unsigned)g.grid), dim3(BLOCK),
-                               lds_k, s, keys, vals, n, shift, mask, g.n_tiles, g.tiles_per_block, g.sub,
-                               counts, g.cols, totals, ok, ov, part_offsets);
-        return hipGetLastError();
+            return stable ? shuffle_t<true, true>(keys, vals, n, shift, mask, g, counts, totals, ok, ov, part_offsets, s)
+                          : shuffle_t<true, false>(keys, vals, n, shift, mask, g, counts, totals, ok, ov,
+                                                   part_offsets, s);
+        return stable ? shuffle_t<false, true>(keys, vals, n, shift, mask, g, counts, totals, ok, ov, part_offsets, s)
+                      : shuffle_t<false, false>(keys, vals, n, shift, mask, g, counts, totals, ok, ov, part_offsets, s);
     }
 };
 
@@ -489,7 +497,7 @@ hipError_t launch_radix_histogram(const LaunchCfg &cfg, const uint32_t *keys, in
 
 hipError_t launch_radix_partition(const LaunchCfg &cfg, const uint32_t *keys, const uint32_t *vals, int64_t n,
                                   int shift, int bits, uint32_t *out_keys, uint32_t *out_vals,
-                                  uint32_t *part_offsets, void *scratch, hipStream_t s) {
+                                  uint32_t *part_offsets, void *scratch, bool stable, hipStream_t s) {
     const uint32_t mask = (1u << bits) - 1u;
     if (n == 0) return part_offsets ? fill_u32(part_offsets, (int64_t)mask + 2, 0u, s) : hipSuccess;
     const RadixGeom g = geometry(cfg, n);
@@ -509,7 +517,7 @@ hipError_t launch_radix_partition(const LaunchCfg &cfg, const uint32_t *keys, co
 #define X(B, I)                                                                                              \
     case CRYSTAL_VARIANT_KEY(B, I):                                                                          \
         return RadixKernels<B, I>::shuffle(keys, vals, n, shift, mask, g, counts, totals, out_keys, out_vals, \
-                                           part_offsets, s);
+                                           part_offsets, stable, s);
     RADIX_DISPATCH(cfg, X)
 #undef X
 }

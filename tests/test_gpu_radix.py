@@ -166,3 +166,43 @@ def test_sort_repeated_calls_share_scratch():
         ok, ov = cx.sort_pairs(dev(k.view(np.int32)), dev(v.view(np.int32)), scratch=scratch)
         wk, wv = oracle.sort_pairs(k, v)
         assert np.array_equal(u32(ok, n), wk) and np.array_equal(u32(ov, n), wv)
+
+
+# --------------------------------------------------------- unstable shuffle --
+def check_unstable(k, v, shift, bits):
+    """The unstable pass orders equal digits arbitrarily: partition bounds are
+    exact, and each partition holds exactly the oracle's (key, value) pairs."""
+    n = k.size
+    ok, ov, offs = cx.radix_partition(dev(k.view(np.int32)), shift, bits, vals=dev(v.view(np.int32)), stable=False)
+    wk, wv = oracle.radix_partition(k, v, shift, bits)
+    h = oracle.radix_histogram(k, shift, bits)
+    bounds = np.concatenate([[0], np.cumsum(h)])
+    assert np.array_equal(offs.cpu().numpy().astype(np.int64), bounds)
+    gk, gv = u32(ok, n), u32(ov, n)
+    for d in range(1 << bits):
+        a, b = bounds[d], bounds[d + 1]
+        if a == b:
+            continue
+        got = np.sort(gk[a:b].astype(np.uint64) << np.uint64(32) | gv[a:b].astype(np.uint64))
+        want = np.sort(wk[a:b].astype(np.uint64) << np.uint64(32) | wv[a:b].astype(np.uint64))
+        assert np.array_equal(got, want), d
+
+
+@pytest.mark.parametrize("n", [0, 1, 4097, 100_003, 1_000_003])
+@pytest.mark.parametrize("shift,bits", [(0, 8), (24, 8), (4, 4), (31, 1)])
+def test_unstable_partition_matches_oracle_per_partition(n, shift, bits):
+    announce("radix unstable", n, shift, bits)
+    k, v = pairs(n, 1100 + n)
+    check_unstable(k, v, shift, bits)
+
+
+@pytest.mark.parametrize("block,ipt", [(256, 16), (1024, 8), (1024, 16)])
+def test_unstable_partition_skewed_and_shapes(block, ipt):
+    announce("radix unstable skew", block, ipt)
+    cx.tune_set(cx.K_RADIX, block, ipt, 0)
+    n = 300_007
+    rng = np.random.default_rng(5)
+    for keys in (np.full(n, 0x01020304, dtype=np.uint32),
+                 rng.integers(0, 3, size=n, dtype=np.uint64).astype(np.uint32),
+                 rng.integers(0, 2 ** 32, size=n, dtype=np.uint64).astype(np.uint32)):
+        check_unstable(keys, np.arange(n, dtype=np.uint32), 0, 8)
