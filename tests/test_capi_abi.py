@@ -155,3 +155,44 @@ def test_radix_tuning_variants(cx):
     assert lib.crystal_tune_set(cx.K_RADIX, -1, -1, 128, 16, 0) == cx.EINVAL
     assert lib.crystal_tune_set(cx.K_RADIX, -1, -1, 1024, 8, 2) == cx.OK
     cx.tune_reset()
+
+
+def test_build_batch_and_pack_host_errors(cx):
+    """Argument errors of the batched build and of crystal_pack_column are
+    returned on the host before any device work."""
+    lib = cx.load()
+    st = ctypes.c_void_p(1 << 20)
+    assert lib.crystal_ht_build_batch(None, 1, st, None) == cx.EINVAL
+    items = (cx.BuildItemC * 9)()
+    assert lib.crystal_ht_build_batch(items, 9, st, None) == cx.EINVAL          # more than 8 tables
+    assert lib.crystal_ht_build_batch(items, -1, st, None) == cx.EINVAL
+    assert lib.crystal_ht_build_batch(items, 1, st, None) == cx.EINVAL          # no table descriptor
+    assert lib.crystal_ht_build_batch(items, 0, st, None) == cx.OK
+    ht = cx.HT()
+    assert lib.crystal_ht_init(ctypes.byref(ht), cx.HT_DIRECT, 10, 0, 9, 1) == cx.OK
+    ht.mem = 1 << 20
+    items[0].ht = ctypes.pointer(ht)
+    items[0].keys = 1 << 21
+    items[0].n = 10
+    assert lib.crystal_ht_build_batch(items, 1, st, None) == cx.EINVAL          # payload table, no payload
+    items[1] = items[0]
+    items[0].payload = items[1].payload = 1 << 22
+    assert lib.crystal_ht_build_batch(items, 2, st, None) == cx.EINVAL          # the same table twice
+    fake = ctypes.c_void_p(1 << 20)
+    out = ctypes.c_void_p(1 << 24)
+    for width in (0, 3, 4):
+        assert lib.crystal_pack_column(fake, 100, 0, width, out, st, None) == cx.EINVAL
+    assert lib.crystal_pack_column(ctypes.c_void_p((1 << 20) + 4), 100, 0, 2, out, st, None) == cx.EINVAL
+    assert lib.crystal_pack_column(fake, 100, 0, 2, out, None, None) == cx.EINVAL
+    assert lib.crystal_pack_column(None, 0, 0, 1, None, st, None) == cx.OK
+
+
+def test_star_query_format_validation(cx):
+    """Column formats other than int32, uint16 and uint8 are rejected."""
+    lib = cx.load()
+    q = cx.StarQueryC()
+    q.n_cols, q.n_rows, q.n_groups, q.agg = 1, 0, 1, cx.AGG_COUNT
+    assert lib.crystal_star_query_scratch_bytes(ctypes.byref(q)) >= 0
+    q.formats[0] = cx.ColFormatC(3, 0)
+    st = ctypes.c_void_p(1 << 20)
+    assert lib.crystal_run_star_query(ctypes.byref(q), ctypes.c_void_p(1 << 21), st, None, 0, None) == cx.EINVAL
