@@ -224,15 +224,99 @@ __global__ __launch_bounds__(BLOCK) void select_kernel(const int32_t *__restrict
     }
 }
 
+// Unstable selection with buffered reservations.  Persistent workgroups
+// stride over the tiles; each compacts a tile's matches (BlockScan +
+// BlockShuffle, in input order within the tile) into an LDS buffer of two
+// tiles and reserves output space with one atomic only when the buffer could
+// not take another tile, then writes the whole buffer out.  Fewer
+// reservations than one per tile (they serialise on one address), and the
+// next tile's loads are in flight while the current one is compacted.
+template <int BLOCK, int IPT>
+__global__ __launch_bounds__(BLOCK) void select_buffered_kernel(const int32_t *__restrict__ in, int64_t n,
+                                                                int32_t lo, int32_t hi,
+                                                                int32_t *__restrict__ out,
+                                                                int64_t *__restrict__ count_out,
+                                                                int64_t n_tiles) {
+    using T = TileShape<BLOCK, IPT>;
+    constexpr int C = T::CHUNKS, W = T::WAVES, V = T::VEC;
+    constexpr int VBITS = V == 1 ? 1 : V == 2 ? 2 : 3;
+    constexpr uint32_t CAP = 2 * T::ITEMS;
+    extern __shared__ int32_t buf[];  // CAP entries
+    __shared__ uint32_t chunk_tot[C * W];
+    __shared__ uint64_t flush_off;
+    const int w = threadIdx.x / kWave;
+    const uint32_t lane = lane_id();
+    uint32_t fill = 0;  // entries in buf, equal in every thread
+
+    auto flush = [&]() {
+        if (threadIdx.x == 0) flush_off = atomic_add_u64((uint64_t *)count_out, fill);
+        __syncthreads();
+        const uint64_t ob = flush_off;
+        for (uint32_t i = threadIdx.x; i < fill; i += BLOCK) __builtin_nontemporal_store(buf[i], out + ob + i);
+        __syncthreads();  // buf and flush_off are reused
+        fill = 0;
+    };
+    // compact one tile's values (already loaded) into buf
+    auto compact = [&](int64_t tile, const int32_t(&v)[IPT]) {
+        const int64_t base = tile * T::ITEMS;
+        const uint32_t flags = block_pred_range<IPT>(v, valid_mask<BLOCK, IPT>(base, n), lo, hi);
+        uint32_t pre[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            uint32_t wt;
+            pre[c] = wave_exclusive_scan_small<VBITS>((uint32_t)__popc((flags >> (c * V)) & T::VMASK), wt);
+            if (lane == 0) chunk_tot[c * W + w] = wt;
+        }
+        __syncthreads();
+        uint32_t cbase[C];
+        uint32_t total = 0;
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int ww = 0; ww < W; ++ww) {
+                const uint32_t t = chunk_tot[c * W + ww];
+                if (ww == w) cbase[c] = total;
+                total += t;
+            }
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            uint32_t pos = fill + cbase[c] + pre[c];
+#pragma unroll
+            for (int e = 0; e < V; ++e)
+                if ((flags >> (c * V + e)) & 1u) buf[pos++] = v[c * V + e];
+        }
+        fill += total;
+        __syncthreads();  // chunk_tot is rewritten by the next tile; buf is complete
+        if (fill + T::ITEMS > CAP) flush();
+    };
+
+    int32_t va[IPT], vb[IPT];
+    int64_t tile = blockIdx.x;
+    if (tile < n_tiles) block_load<BLOCK, IPT, true>(in, tile * T::ITEMS, n, va);
+    // unrolled by two so that the buffer receiving the next tile's loads is never copied
+    while (tile < n_tiles) {
+        int64_t nxt = tile + gridDim.x;
+        if (nxt < n_tiles) block_load<BLOCK, IPT, true>(in, nxt * T::ITEMS, n, vb);
+        compact(tile, va);
+        tile = nxt;
+        if (tile >= n_tiles) break;
+        nxt = tile + gridDim.x;
+        if (nxt < n_tiles) block_load<BLOCK, IPT, true>(in, nxt * T::ITEMS, n, va);
+        compact(tile, vb);
+        tile = nxt;
+    }
+    if (fill) flush();
+}
+
 template <int BLOCK, int IPT>
 static hipError_t select_t(const LaunchCfg &cfg, const int32_t *in, int64_t n, int32_t lo, int32_t hi,
                            int32_t *out, int64_t *count, uint64_t *st, bool stable, hipStream_t s) {
     using T = TileShape<BLOCK, IPT>;
     const int64_t n_tiles = (n + T::ITEMS - 1) / T::ITEMS;
-    // one workgroup per tile, always: a stable tile only waits for lower-
-    // numbered tiles, which in-order dispatch has already started; workgroups
-    // striding over tiles could wait for a tile whose workgroup is not resident
-    (void)cfg;
+    // stable: one workgroup per tile, always: a stable tile only waits for
+    // lower-numbered tiles, which in-order dispatch has already started;
+    // workgroups striding over tiles could wait for a tile whose workgroup is
+    // not resident
     hipError_t e;
     if (stable) {
         e = fill_u64(st, n_tiles, 0ull, s);
@@ -242,8 +326,20 @@ static hipError_t select_t(const LaunchCfg &cfg, const int32_t *in, int64_t n, i
     } else {
         e = fill_u64((uint64_t *)count, 1, 0ull, s);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((select_kernel<BLOCK, IPT, false>), dim3((unsigned)n_tiles), dim3(BLOCK), 0, s, in, n,
-                           lo, hi, out, st, count, n_tiles);
+        // persistent: as many workgroups per CU as waves and the two-tile LDS buffer allow (or as tuned)
+        const size_t lds = (size_t)2 * T::ITEMS * sizeof(int32_t);
+        int64_t per_cu = cfg.grid_per_cu > 0 ? cfg.grid_per_cu : (2048 / BLOCK > 0 ? 2048 / BLOCK : 1);
+        const int64_t lds_cap = device_lds_per_cu() / (int64_t)(lds + 1024);
+        if (per_cu > lds_cap) per_cu = lds_cap > 0 ? lds_cap : 1;
+        int64_t grid = per_cu * device_cu_count();
+        if (grid > n_tiles) grid = n_tiles;
+        if (lds > 65536) {
+            e = hipFuncSetAttribute((const void *)select_buffered_kernel<BLOCK, IPT>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL((select_buffered_kernel<BLOCK, IPT>), dim3((unsigned)grid), dim3(BLOCK), lds, s, in, n,
+                           lo, hi, out, count, n_tiles);
     }
     return hipGetLastError();
 }
