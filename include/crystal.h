@@ -72,10 +72,10 @@ size_t crystal_struct_size(int32_t which);
 /* ------------------------------------------------------------------------ */
 /* Selection -- section 4.2, query Q3 (and section 3.2, query Q0):           */
 /*   SELECT y FROM R WHERE pred.lo <= y <= pred.hi                           */
-/* One kernel: BlockLoad, BlockPred, BlockScan of the match counts, thread 0 */
-/* reserves the tile's output range with one 64-bit atomic on *out_count     */
-/* (skipped for a tile without matches), BlockShuffle through LDS,           */
-/* BlockStore (coalesced).                                                   */
+/* One kernel: BlockLoad, BlockPred, BlockScan of the match counts,         */
+/* BlockShuffle of the matches into an LDS buffer of two tiles; when the     */
+/* buffer could not take another tile, thread 0 reserves its output range    */
+/* with one 64-bit atomic on *out_count and the buffer is stored coalesced.  */
 /*   in        device, n int32 values                                        */
 /*   out       device, capacity for every match (n values always suffice)    */
 /*   out_count device int64; cleared, then the number of matches             */

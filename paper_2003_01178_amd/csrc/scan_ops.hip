@@ -159,7 +159,8 @@ __device__ __forceinline__ uint64_t block_lookback(uint64_t *st, int64_t tile, u
     return running;
 }
 
-template <int BLOCK, int IPT, bool STABLE>
+// Stable selection: one workgroup per tile, output offsets by decoupled look-back.
+template <int BLOCK, int IPT>
 __global__ __launch_bounds__(BLOCK) void select_kernel(const int32_t *__restrict__ in, int64_t n,
                                                        int32_t lo, int32_t hi,
                                                        int32_t *__restrict__ out,
@@ -173,7 +174,6 @@ __global__ __launch_bounds__(BLOCK) void select_kernel(const int32_t *__restrict
     __shared__ uint32_t chunk_tot[C * W];
     __shared__ uint32_t wave_flags[W];
     __shared__ uint64_t wave_sum[W];
-    __shared__ uint64_t tile_off;
     const int w = threadIdx.x / kWave;
     const uint32_t lane = lane_id();
     {
@@ -202,12 +202,7 @@ __global__ __launch_bounds__(BLOCK) void select_kernel(const int32_t *__restrict
                 if (ww == w) cbase[c] = total;
                 total += t;
             }
-        uint64_t ob;
-        if constexpr (STABLE) {
-            ob = block_lookback<BLOCK>(st, tile, total, wave_flags, wave_sum);
-        } else {
-            if (threadIdx.x == 0 && total) tile_off = atomic_add_u64((uint64_t *)count_out, total);
-        }
+        const uint64_t ob = block_lookback<BLOCK>(st, tile, total, wave_flags, wave_sum);
         // BlockShuffle: matches to their tile positions in LDS
 #pragma unroll
         for (int c = 0; c < C; ++c) {
@@ -217,10 +212,9 @@ __global__ __launch_bounds__(BLOCK) void select_kernel(const int32_t *__restrict
                 if ((flags >> (c * V + e)) & 1u) buf[pos++] = v[c * V + e];
         }
         __syncthreads();
-        if constexpr (!STABLE) ob = total ? tile_off : 0;
         if (ob < kPoison)
             for (uint32_t i = threadIdx.x; i < total; i += BLOCK) __builtin_nontemporal_store(buf[i], out + ob + i);
-        if (STABLE && tile == n_tiles - 1 && threadIdx.x == 0) *count_out = ob < kPoison ? (int64_t)(ob + total) : -1;
+        if (tile == n_tiles - 1 && threadIdx.x == 0) *count_out = ob < kPoison ? (int64_t)(ob + total) : -1;
     }
 }
 
@@ -321,7 +315,7 @@ static hipError_t select_t(const LaunchCfg &cfg, const int32_t *in, int64_t n, i
     if (stable) {
         e = fill_u64(st, n_tiles, 0ull, s);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((select_kernel<BLOCK, IPT, true>), dim3((unsigned)n_tiles), dim3(BLOCK), 0, s, in, n,
+        hipLaunchKernelGGL((select_kernel<BLOCK, IPT>), dim3((unsigned)n_tiles), dim3(BLOCK), 0, s, in, n,
                            lo, hi, out, st, count, n_tiles);
     } else {
         e = fill_u64((uint64_t *)count, 1, 0ull, s);
