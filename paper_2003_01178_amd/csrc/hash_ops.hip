@@ -237,20 +237,75 @@ __global__ __launch_bounds__(BLOCK) void ht_probe_kernel(DevTable t, const int32
         block_load<BLOCK, IPT, true>(fk, base, n, key);
         if (pp) block_load<BLOCK, IPT, true>(pp, base, n, pv);
         const uint32_t valid = valid_mask<BLOCK, IPT>(base, n);
+        uint32_t hit = 0;
+        int32_t pay[IPT];
+        if constexpr (MODE == 2) {
+            // direct table: every item's presence word at once, then the payloads of the hits
+            uint32_t word[IPT], ok = 0;
 #pragma unroll
-        for (int k = 0; k < IPT; ++k) {
-            if (!((valid >> k) & 1u)) continue;
-            int32_t pay = 0;
-            bool hit;
-            if constexpr (MODE == 2)
-                hit = probe_direct(t, key[k], pay, t.has_payload);
-            else
-                hit = key[k] != kEmptyKey && probe_linear(slots, t.mask, t.shift, key[k], pay);
-            if (hit) {
-                sum += (uint64_t)(int64_t)pay + (pp ? (uint64_t)(int64_t)pv[k] : 0ull);
-                cnt += 1;
+            for (int k = 0; k < IPT; ++k) {
+                const uint32_t off = (uint32_t)key[k] - (uint32_t)t.key_min;
+                const bool in = ((valid >> k) & 1u) && (int64_t)off < t.span;
+                ok |= (uint32_t)in << k;
+                word[k] = t.bitmap[in ? (off >> 5) : 0u];
+            }
+#pragma unroll
+            for (int k = 0; k < IPT; ++k) {
+                const uint32_t off = (uint32_t)key[k] - (uint32_t)t.key_min;
+                hit |= (((word[k] >> (off & 31u)) & 1u) << k) & ok;
+            }
+#pragma unroll
+            for (int k = 0; k < IPT; ++k) {
+                const uint32_t off = (uint32_t)key[k] - (uint32_t)t.key_min;
+                pay[k] = t.has_payload && ((hit >> k) & 1u) ? t.payload[off] : 0;
+            }
+        } else if constexpr (MODE == 0) {
+            // table in global memory: one probe sequence per item (issuing every
+            // item's slot at once measured slower when the table sits in the
+            // last-level cache, and no faster from HBM)
+#pragma unroll
+            for (int k = 0; k < IPT; ++k) {
+                pay[k] = 0;
+                if (((valid >> k) & 1u) && key[k] != kEmptyKey && probe_linear(slots, t.mask, t.shift, key[k], pay[k]))
+                    hit |= 1u << k;
+            }
+        } else {
+            // table staged in LDS: linear probing in rounds, the next slot of every
+            // item still searching read at once, so a tile's probes overlap
+            uint32_t slot[IPT];
+            uint32_t pending = 0;
+#pragma unroll
+            for (int k = 0; k < IPT; ++k) {
+                slot[k] = hash_slot(key[k], t.shift);
+                pay[k] = 0;
+                pending |= (uint32_t)(((valid >> k) & 1u) && key[k] != kEmptyKey) << k;
+            }
+            for (uint32_t step = 0; pending && step <= t.mask; ++step) {
+                v2i e[IPT];
+#pragma unroll
+                for (int k = 0; k < IPT; ++k)
+                    if ((pending >> k) & 1u) e[k] = slots[slot[k]];
+#pragma unroll
+                for (int k = 0; k < IPT; ++k) {
+                    if (!((pending >> k) & 1u)) continue;
+                    if (e[k].x == key[k]) {
+                        hit |= 1u << k;
+                        pay[k] = e[k].y;
+                        pending &= ~(1u << k);
+                    } else if (e[k].x == kEmptyKey) {
+                        pending &= ~(1u << k);
+                    } else {
+                        slot[k] = (slot[k] + 1u) & t.mask;
+                    }
+                }
             }
         }
+#pragma unroll
+        for (int k = 0; k < IPT; ++k)
+            if ((hit >> k) & 1u) {
+                sum += (uint64_t)(int64_t)pay[k] + (pp ? (uint64_t)(int64_t)pv[k] : 0ull);
+                cnt += 1;
+            }
     }
     const uint64_t bs = block_sum_u64<BLOCK>(sum, red);
     __syncthreads();
