@@ -36,7 +36,7 @@ def parse():
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=5)
     p.add_argument("--workload", default="star", choices=["star", "q11", "select", "project", "join", "copy", "serve",
-                                                              "partition", "sort"])
+                                                              "partition", "sort", "groupby"])
     p.add_argument("--rows", type=int, default=0, help="override the fact/column length")
     p.add_argument("--sigma", type=float, default=0.5, help="select selectivity")
     p.add_argument("--dim", type=int, default=1 << 20, help="join build size D")
@@ -315,7 +315,7 @@ def main():
     cx.load()
     kernel_id = {"star": cx.K_STAR, "q11": cx.K_STAR, "select": cx.K_SELECT, "project": cx.K_PROJECT,
                  "join": cx.K_HT_PROBE, "copy": cx.K_SELECT, "serve": cx.K_SHARED_SCAN,
-                 "partition": cx.K_RADIX, "sort": cx.K_RADIX}[args.workload]
+                 "partition": cx.K_RADIX, "sort": cx.K_RADIX, "groupby": cx.K_GROUPBY}[args.workload]
     if args.tune:
         b, i, g = (int(x) for x in args.tune.split(","))
         cx.tune_set(kernel_id, b, i, g)
@@ -566,6 +566,33 @@ def main():
 
     elif args.workload == "serve":
         result.update(serve(args, torch, cx, datagen, queries, roof))
+
+    elif args.workload == "groupby":
+        # dense group-by SUM(v) GROUP BY g: 2^28 rows into 7,000 groups (the star query's group array)
+        n = args.rows or (1 << 28)
+        rng = np.random.default_rng(datagen.BASE_SEED + 13)
+        g = queries.to_dev(rng.integers(0, 7000, size=n, dtype=np.int32))
+        v = queries.to_dev(rng.integers(1, 1_000_001, size=n, dtype=np.int32))
+        o = torch.empty(7000, dtype=torch.int64, device="cuda")
+        st = cx.new_status()
+        for _ in range(W):
+            cx.groupby_agg(g, v, 7000, out=o, status=st)
+        torch.cuda.synchronize()
+        timer = Timer(torch)
+        t0 = time.perf_counter()
+        for _ in range(K):
+            timer.run(lambda: cx.groupby_agg(g, v, 7000, out=o, status=st))
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        cx.check_status(st)
+        kern_ms = timer.mean_ms()
+        b = 8 * n
+        result.update(metric="rows/s (dense group-by, 7000 int64 groups)", value=n * K / elapsed, unit="rows/s",
+                      ms_per_step=elapsed / K * 1e3, dtype="int32",
+                      config={"workload": "SUM(v) GROUP BY g, 2^28 rows, g U{0..6999}", "rows": n,
+                              "tile": list(cx.tune_get(cx.K_GROUPBY, n))})
+        roof.update(kernel="crystal::groupby_kernel", achieved=b / (kern_ms * 1e-3) / 1e9, algorithmic_bytes=b,
+                    kernel_ms=kern_ms)
 
     elif args.workload in ("partition", "sort"):
         # section 4.4: 2^28 pairs of 32-bit keys and 32-bit values
