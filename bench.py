@@ -145,7 +145,7 @@ def shared_pass_bytes(torch, mask_steps, agg_cols, reread_cols, n, line=FETCH_BY
     """Algorithmic bytes of one shared-scan pass over rows [0, n): each join
     step reads its key column at the lines holding a row still alive for some
     query, the survivors' measure and group-key columns are read at their
-    lines.  mask_steps: (key column, mask table as int16, key_min) per step."""
+    lines.  mask_steps: (key column, mask table as one entry per key, key_min) per step."""
     per = line // 4
     def lines(alive):
         pad = (-n) % per
@@ -173,10 +173,8 @@ def shared_scan_roofline(torch, cx, datagen, queries, sv, seg, rng, reps):
     sv.build_q11_masks(q11_c)
     torch.cuda.synchronize()
     d = sv.s.dims
-    def table(qmask):
-        return qmask.mem[: ((qmask.c.span + 1) // 2) * 4].view(torch.int16)[: qmask.c.span]
-    star_steps = [(sv.cols[j], table(sv.masks[j]), d[j]["key_min"]) for j in queries.DEFAULT_JOIN_ORDER]
-    q11_steps = [(sv.cols[dm["fk_col"]], table(dm["mask"]), dm["key_min"]) for dm in sv.q11_domains]
+    star_steps = [(sv.cols[j], sv.masks[j].dense(), d[j]["key_min"]) for j in queries.DEFAULT_JOIN_ORDER]
+    q11_steps = [(sv.cols[dm["fk_col"]], dm["mask"].dense(), dm["key_min"]) for dm in sv.q11_domains]
     b_star, s_star = shared_pass_bytes(torch, star_steps, [4], [0, 2], seg)
     b_q11, s_q11 = shared_pass_bytes(torch, q11_steps, [8, 6], [], seg)
     res = {}

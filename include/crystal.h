@@ -58,7 +58,7 @@ typedef struct crystal_range {
 const char *crystal_status_string(int32_t status);
 
 /* ABI version of this header (incremented on any layout change). */
-#define CRYSTAL_ABI_VERSION 4
+#define CRYSTAL_ABI_VERSION 5
 int32_t crystal_abi_version(void);
 
 /* sizeof of the ABI structs as compiled into the library, so a binding can
@@ -319,18 +319,42 @@ crystal_status crystal_pack_column(const int32_t *in, int64_t n, int32_t base, i
 #define CRYSTAL_MAX_BATCH 16
 
 typedef struct crystal_qmask_table {
-    void *mem;         /* device memory of crystal_qmask_bytes(span) bytes (caller-owned) */
+    void *mem;         /* device, 16-byte aligned, caller-owned: crystal_qmask_bytes(span)
+                          bytes, or crystal_qmask_ranked_bytes(span, ranked) when ranked > 0 */
     int64_t span;      /* keys key_min .. key_min + span - 1                          */
     int32_t key_min;
-    int32_t reserved;
+    int32_t ranked;    /* 0: one 16-bit entry per key of the span.  > 0: rank-compressed
+                          (for a sparse key domain): a directory of the keys present,
+                          built once by crystal_qmask_rank, and one entry per present
+                          key, at most `ranked` of them                                */
 } crystal_qmask_table;
 
 size_t crystal_qmask_bytes(int64_t span);
 
-/* Clear the table, then for every dimension row i < n with key keys[i] set bit
- * q of the key's entry when filter_col[i] lies in ranges[q] (q < n_queries;
- * every row passes when filter_col is NULL).  ranges: HOST array.  A key
- * outside the span sets CRYSTAL_ERANGE in *status. */
+/* Rank-compressed layout, for a dimension whose keys fill a small part of
+ * their span (dates stored as yyyymmdd: 2,556 keys over a span of 61,130):
+ *   dir[w], w = 0 .. ceil(span / 32): two 32-bit words, the presence bits of
+ *     keys key_min + 32 w .. + 31 and the number of present keys before them;
+ *     the last entry has no presence bits (keys past the span read it);
+ *   then ranked + 1 16-bit entries, entry r for the present key of rank r,
+ *     entry `ranked` always 0 (absent keys read it).
+ * A key's entry is found with one directory read and a population count.
+ * 0 when ranked <= 0, span <= 0 or span > 2^26. */
+size_t crystal_qmask_ranked_bytes(int64_t span, int32_t ranked);
+
+/* Build a ranked table's directory from the dimension's key column keys[n]
+ * (device; duplicates count once) and clear its entries.  A key outside the
+ * span sets CRYSTAL_ERANGE in *status, more than t->ranked distinct keys
+ * CRYSTAL_EFULL (the table is then unusable).  Run once per dimension; the
+ * directory stays valid for every later crystal_qmask_build of the table. */
+crystal_status crystal_qmask_rank(const crystal_qmask_table *t, const int32_t *keys, int64_t n,
+                                  int32_t *status, void *stream);
+
+/* Clear the table's entries, then for every dimension row i < n with key
+ * keys[i] set bit q of the key's entry when filter_col[i] lies in ranges[q]
+ * (q < n_queries; every row passes when filter_col is NULL).  ranges: HOST
+ * array.  A key outside the span, or (ranked table) absent from its
+ * directory, sets CRYSTAL_ERANGE in *status. */
 crystal_status crystal_qmask_build(const crystal_qmask_table *t, const int32_t *keys,
                                    const int32_t *filter_col, int64_t n,
                                    const crystal_range *ranges, int32_t n_queries,

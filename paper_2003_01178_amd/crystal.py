@@ -69,7 +69,7 @@ MAX_BATCH = 16
 
 
 class QmaskTableC(ctypes.Structure):
-    _fields_ = [("mem", c_vp), ("span", c_i64), ("key_min", c_i32), ("reserved", c_i32)]
+    _fields_ = [("mem", c_vp), ("span", c_i64), ("key_min", c_i32), ("ranked", c_i32)]
 
 
 class BatchQueryC(ctypes.Structure):
@@ -133,6 +133,8 @@ def _declare(lib):
         "crystal_run_star_query_accumulate": (c_i32, [P(StarQueryC), c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp]),
         "crystal_pack_column": (c_i32, [c_vp, c_i64, c_i32, c_i32, c_vp, c_vp, c_vp]),
         "crystal_qmask_bytes": (ctypes.c_size_t, [c_i64]),
+        "crystal_qmask_ranked_bytes": (ctypes.c_size_t, [c_i64, c_i32]),
+        "crystal_qmask_rank": (c_i32, [P(QmaskTableC), c_vp, c_i64, c_vp, c_vp]),
         "crystal_qmask_build": (c_i32, [P(QmaskTableC), c_vp, c_vp, c_i64, P(Range), c_i32, c_vp, c_vp]),
         "crystal_run_shared_scan": (c_i32, [P(BatchC), c_vp, c_vp]),
         "crystal_server_workspace_bytes": (ctypes.c_size_t, [P(ServerConfigC)]),
@@ -448,16 +450,61 @@ class StarQuery:
 
 # ----------------------------------------------------------- shared scan --
 class QueryMask:
-    """Query-mask table of one dimension for a shared-scan batch."""
+    """Query-mask table of one dimension for a shared-scan batch.
 
-    def __init__(self, key_min, key_max, device="cuda"):
+    With ``keys`` (the dimension's key column, device int32) and a sparse key
+    domain the table is rank-compressed: a directory of the keys present,
+    built here once, and one entry per present key.  ``ranked``: True forces
+    that layout, False the plain one, None picks the ranked one when it takes
+    at most half the plain table's bytes."""
+
+    def __init__(self, key_min, key_max, device="cuda", keys=None, ranked=None, status=None, stream=None):
         lib = load()
         self.c = QmaskTableC()
         self.c.span = int(key_max) - int(key_min) + 1
         self.c.key_min = int(key_min)
-        nbytes = lib.crystal_qmask_bytes(self.c.span)
+        plain = lib.crystal_qmask_bytes(self.c.span)
+        nbytes = plain
+        if keys is not None and ranked is not False:
+            rb = lib.crystal_qmask_ranked_bytes(self.c.span, keys.numel())
+            if ranked or (rb and 2 * rb <= plain):
+                if not rb:
+                    raise ValueError("no ranked layout for this span and key count")
+                self.c.ranked = keys.numel()
+                nbytes = rb
+        elif ranked:
+            raise ValueError("a ranked table needs the dimension's key column")
         self.mem = torch.empty(max(16, nbytes), dtype=torch.uint8, device=device)
         self.c.mem = self.mem.data_ptr()
+        self.status = None
+        if self.c.ranked:
+            self.status = new_status(keys.device) if status is None else status
+            _check(lib.crystal_qmask_rank(ctypes.byref(self.c), _col(keys), keys.numel(), _ptr(self.status),
+                                          _stream(stream)), "crystal_qmask_rank")
+
+    @property
+    def ranked(self):
+        return int(self.c.ranked)
+
+    def dense(self):
+        """The table as one int32 entry per key of the span (device)."""
+        span = int(self.c.span)
+        if not self.c.ranked:
+            return self.mem[: ((span + 1) // 2) * 4].view(torch.int16)[:span].to(torch.int32) & 0xFFFF
+        n_dir = (span + 31) // 32 + 1
+        words = self.mem[: 8 * n_dir].view(torch.int32).view(-1, 2).to(torch.int64) & 0xFFFFFFFF
+        ent = self.mem[8 * n_dir: 8 * n_dir + 2 * (self.c.ranked + 1)].view(torch.int16).to(torch.int32) & 0xFFFF
+        off = torch.arange(span, device=self.mem.device, dtype=torch.int64)
+        bits, before = words[off >> 5, 0], words[off >> 5, 1]
+        bit = off & 31
+        present = ((bits >> bit) & 1) == 1
+        below = bits & ((torch.ones_like(bit) << bit) - 1)
+        # population count of the bits below each key
+        cnt = torch.zeros_like(below)
+        for b in range(32):
+            cnt += (below >> b) & 1
+        idx = torch.where(present, before + cnt, torch.full_like(cnt, int(self.c.ranked)))
+        return ent[idx]
 
     def build(self, keys, filter_col, ranges, status=None, stream=None):
         """Bit q of key k: the dimension row with key k has filter_col in ranges[q]."""

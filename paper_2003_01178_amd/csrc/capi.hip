@@ -414,12 +414,33 @@ size_t crystal_qmask_bytes(int64_t span) {
     return (size_t)((span + 1) / 2) * 4;
 }
 
+static constexpr int64_t kMaxRankedSpan = int64_t(1) << 26;
+
+size_t crystal_qmask_ranked_bytes(int64_t span, int32_t ranked) {
+    if (ranked <= 0 || span <= 0 || span > kMaxRankedSpan) return 0;
+    return (size_t)((qmask_ranked_words(span, ranked) * 4 + 15) / 16 * 16);
+}
+
+// A table descriptor the kernels can use: plain, or ranked with a span the
+// directory scan handles.
+static bool qmask_table_ok(const crystal_qmask_table *t) {
+    if (!t || !t->mem || !aligned16(t->mem) || t->span <= 0 || t->span > (int64_t(1) << 32) || t->ranked < 0)
+        return false;
+    return t->ranked == 0 || t->span <= kMaxRankedSpan;
+}
+
+crystal_status crystal_qmask_rank(const crystal_qmask_table *t, const int32_t *keys, int64_t n, int32_t *status,
+                                  void *stream) {
+    if (!qmask_table_ok(t) || t->ranked == 0 || n < 0 || (n > 0 && !keys) || !status) return CRYSTAL_EINVAL;
+    return from_hip(launch_qmask_rank((uint32_t *)t->mem, t->span, t->key_min, t->ranked, keys, n, status,
+                                      as_stream(stream)));
+}
+
 crystal_status crystal_qmask_build(const crystal_qmask_table *t, const int32_t *keys, const int32_t *filter_col,
                                    int64_t n, const crystal_range *ranges, int32_t n_queries, int32_t *status,
                                    void *stream) {
-    if (!t || !t->mem || !aligned16(t->mem) || t->span <= 0 || t->span > (int64_t(1) << 32) || n < 0 ||
-        (n > 0 && !keys) || n_queries < 0 || n_queries > CRYSTAL_MAX_BATCH || (n_queries > 0 && !ranges) ||
-        !status)
+    if (!qmask_table_ok(t) || n < 0 || (n > 0 && !keys) || n_queries < 0 || n_queries > CRYSTAL_MAX_BATCH ||
+        (n_queries > 0 && !ranges) || !status)
         return CRYSTAL_EINVAL;
     QmaskRanges r = {};
     r.n = n_queries;
@@ -427,8 +448,8 @@ crystal_status crystal_qmask_build(const crystal_qmask_table *t, const int32_t *
         r.lo[q] = ranges[q].lo;
         r.hi[q] = ranges[q].hi;
     }
-    return from_hip(launch_qmask_build((uint16_t *)t->mem, t->span, t->key_min, keys, filter_col, n, r, status,
-                                       as_stream(stream)));
+    return from_hip(launch_qmask_build((uint16_t *)t->mem, t->span, t->key_min, t->ranked, keys, filter_col, n, r,
+                                       status, as_stream(stream)));
 }
 
 crystal_status crystal_run_shared_scan(const crystal_batch *b, int32_t *status, void *stream) {
@@ -442,10 +463,11 @@ crystal_status crystal_run_shared_scan(const crystal_batch *b, int32_t *status, 
     if (b->row_begin < 0 || b->row_end > b->plan.n_rows || (b->row_begin & 3)) return CRYSTAL_EINVAL;
     for (int j = 0; j < b->plan.n_joins; ++j) {
         const crystal_qmask_table &m = b->masks[j];
-        if (!m.mem || !aligned16(m.mem) || m.span <= 0 || m.span > (int64_t(1) << 32)) return CRYSTAL_EINVAL;
-        d.mask[j] = (const uint16_t *)m.mem;
-        d.mask_span[j] = m.span;
-        d.mask_kmin[j] = m.key_min;
+        if (!qmask_table_ok(&m)) return CRYSTAL_EINVAL;
+        d.mask[j].mem = (const uint16_t *)m.mem;
+        d.mask[j].span = m.span;
+        d.mask[j].key_min = m.key_min;
+        d.mask[j].ranked = m.ranked;
     }
     d.n_queries = b->n_queries;
     d.all_queries = b->n_queries >= 32 ? 0xffffffffu : ((1u << b->n_queries) - 1u);

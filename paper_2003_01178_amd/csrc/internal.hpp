@@ -138,11 +138,32 @@ struct QmaskRanges {
     int32_t hi[kMaxBatch];
 };
 
+// Rank-compressed query-mask table: ceil(span / 32) + 1 directory entries of
+// two 32-bit words (presence bits, keys present before them; the last entry
+// all zero), then ranked + 1 16-bit entries (the last one zero).
+__host__ __device__ inline int64_t qmask_dir_entries(int64_t span) { return (span + 31) / 32 + 1; }
+__host__ __device__ inline int64_t qmask_ranked_words(int64_t span, int32_t ranked) {
+    return 2 * qmask_dir_entries(span) + ((int64_t)ranked + 2) / 2;
+}
+
+// One join's query-mask table as the batch kernel reads it.  (One struct per
+// join rather than parallel arrays: a dynamic index into a kernel argument's
+// arrays can make the compiler copy the whole argument into scratch.)
+struct MaskDev {
+    const uint16_t *mem;   // the batch's query-mask table
+    int64_t span;
+    int32_t key_min;
+    int32_t ranked;        // 0: plain table; else rank-compressed with this many entries
+    // set by the launcher: the table is copied into the dynamic LDS at 32-bit
+    // word stage_off (stage_words words, then one zero word) when
+    // stage_words > 0
+    int64_t stage_off;
+    int64_t stage_words;
+};
+
 struct BatchDev {
     StarPlanDev plan;                          // the template
-    const uint16_t *mask[CRYSTAL_MAX_JOINS];   // per join: the batch's query-mask table
-    int64_t mask_span[CRYSTAL_MAX_JOINS];
-    int32_t mask_kmin[CRYSTAL_MAX_JOINS];
+    MaskDev mask[CRYSTAL_MAX_JOINS];           // per join
     int32_t n_queries;
     uint32_t all_queries;                      // (1 << n_queries) - 1
     int32_t pred_lo[kMaxBatch][CRYSTAL_MAX_PREDS];
@@ -150,16 +171,13 @@ struct BatchDev {
     uint64_t *out[kMaxBatch];
     int64_t row_begin;
     int64_t row_end;
-    // set by the launcher: join j's mask table is copied into the dynamic LDS
-    // at 32-bit word stage_off[j] (stage_words[j] words, then one zero word)
-    // when stage_words[j] > 0
-    int64_t stage_off[CRYSTAL_MAX_JOINS];
-    int64_t stage_words[CRYSTAL_MAX_JOINS];
 };
 
-hipError_t launch_qmask_build(uint16_t *table, int64_t span, int32_t key_min, const int32_t *keys,
+hipError_t launch_qmask_build(uint16_t *table, int64_t span, int32_t key_min, int32_t ranked, const int32_t *keys,
                               const int32_t *filter_col, int64_t n, const QmaskRanges &r, int32_t *status,
                               hipStream_t s);
+hipError_t launch_qmask_rank(uint32_t *table, int64_t span, int32_t key_min, int32_t ranked, const int32_t *keys,
+                             int64_t n, int32_t *status, hipStream_t s);
 hipError_t launch_shared_scan(const LaunchCfg &cfg, const BatchDev &b, int32_t *status, hipStream_t s);
 // accumulate: add into out instead of overwriting it
 hipError_t launch_star(const LaunchCfg &cfg, const StarPlanDev &plan, uint64_t *out,

@@ -23,12 +23,25 @@
 namespace crystal {
 
 // ------------------------------------------------------------ mask tables --
-// mask[key - key_min] |= bit q for every query q whose range holds the row's
-// filter attribute.  Two 16-bit entries share a 32-bit word, set with atomicOr.
+// Entry of a key (offset off from key_min) in a rank-compressed table, from
+// its directory entry d = (presence bits, keys present before them): the
+// key's rank among the present keys, or `ranked` (the zero entry) when the
+// key is absent.
+__device__ __forceinline__ uint32_t ranked_entry(uint32_t bits, uint32_t before, uint32_t off, uint32_t ranked) {
+    const uint32_t bit = off & 31u;
+    return ((bits >> bit) & 1u) ? before + (uint32_t)__builtin_popcount(bits & ((1u << bit) - 1u)) : ranked;
+}
+
+// entry[key - key_min] |= bit q for every query q whose range holds the row's
+// filter attribute (entry[rank of the key] for a ranked table).  Two 16-bit
+// entries share a 32-bit word, set with atomicOr.
 __global__ __launch_bounds__(256) void qmask_build_kernel(uint32_t *__restrict__ words, int64_t span,
-                                                          int32_t key_min, const int32_t *__restrict__ keys,
+                                                          int32_t key_min, int32_t ranked,
+                                                          const int32_t *__restrict__ keys,
                                                           const int32_t *__restrict__ filter_col, int64_t n,
                                                           QmaskRanges r, int32_t *status) {
+    const uint32_t *dir = words;
+    uint32_t *entries = ranked ? words + 2 * qmask_dir_entries(span) : words;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         const uint32_t off = (uint32_t)keys[i] - (uint32_t)key_min;
@@ -36,24 +49,88 @@ __global__ __launch_bounds__(256) void qmask_build_kernel(uint32_t *__restrict__
             set_status(status, CRYSTAL_ERANGE);
             continue;
         }
+        uint32_t e = off;
+        if (ranked) {
+            e = ranked_entry(dir[2 * (off >> 5)], dir[2 * (off >> 5) + 1], off, (uint32_t)ranked);
+            if (e >= (uint32_t)ranked) {  // not in the directory
+                set_status(status, CRYSTAL_ERANGE);
+                continue;
+            }
+        }
         const int32_t f = filter_col ? filter_col[i] : 0;
         uint32_t m = 0;
         for (int q = 0; q < r.n; ++q)
             m |= (uint32_t)(filter_col ? in_range(f, r.lo[q], r.hi[q]) : true) << q;
-        if (m) atomicOr(words + (off >> 1), m << ((off & 1u) * 16u));
+        if (m) atomicOr(entries + (e >> 1), m << ((e & 1u) * 16u));
     }
 }
 
-hipError_t launch_qmask_build(uint16_t *table, int64_t span, int32_t key_min, const int32_t *keys,
+hipError_t launch_qmask_build(uint16_t *table, int64_t span, int32_t key_min, int32_t ranked, const int32_t *keys,
                               const int32_t *filter_col, int64_t n, const QmaskRanges &r, int32_t *status,
                               hipStream_t s) {
-    hipError_t e = fill_u32((uint32_t *)table, (span + 1) / 2, 0u, s);
+    uint32_t *words = (uint32_t *)table;
+    hipError_t e = ranked ? fill_u32(words + 2 * qmask_dir_entries(span), ((int64_t)ranked + 2) / 2, 0u, s)
+                          : fill_u32(words, (span + 1) / 2, 0u, s);
     if (e != hipSuccess || n == 0) return e;
     int64_t grid = (n + 255) / 256;
     const int64_t cap = (int64_t)device_cu_count() * 16;
     if (grid > cap) grid = cap;
-    hipLaunchKernelGGL(qmask_build_kernel, dim3((unsigned)grid), dim3(256), 0, s, (uint32_t *)table, span, key_min,
-                       keys, filter_col, n, r, status);
+    hipLaunchKernelGGL(qmask_build_kernel, dim3((unsigned)grid), dim3(256), 0, s, words, span, key_min, ranked, keys,
+                       filter_col, n, r, status);
+    return hipGetLastError();
+}
+
+// Directory of a ranked table: presence bits first, then one workgroup turns
+// them into the number of keys present before each entry.
+__global__ __launch_bounds__(256) void qmask_rank_bits_kernel(uint32_t *__restrict__ dir, int64_t span,
+                                                              int32_t key_min, const int32_t *__restrict__ keys,
+                                                              int64_t n, int32_t *status) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const uint32_t off = (uint32_t)keys[i] - (uint32_t)key_min;
+        if ((int64_t)off >= span) {
+            set_status(status, CRYSTAL_ERANGE);
+            continue;
+        }
+        atomicOr(dir + 2 * (off >> 5), 1u << (off & 31u));
+    }
+}
+
+constexpr int kRankScanBlock = 1024;
+
+__global__ __launch_bounds__(kRankScanBlock) void qmask_rank_scan_kernel(uint32_t *__restrict__ dir, int64_t n_dir,
+                                                                         int32_t ranked, int32_t *status) {
+    __shared__ uint32_t wave_sums[kRankScanBlock / kWave];
+    // thread t owns the entries [t * seg, (t + 1) * seg)
+    const int64_t seg = (n_dir + kRankScanBlock - 1) / kRankScanBlock;
+    const int64_t lo = (int64_t)threadIdx.x * seg;
+    const int64_t hi = lo + seg < n_dir ? lo + seg : n_dir;
+    uint32_t local = 0;
+    for (int64_t i = lo; i < hi; ++i) local += (uint32_t)__builtin_popcount(dir[2 * i]);
+    uint32_t total;
+    uint32_t run = block_exclusive_scan<kRankScanBlock, 27>(local, wave_sums, total);
+    for (int64_t i = lo; i < hi; ++i) {
+        dir[2 * i + 1] = run;
+        run += (uint32_t)__builtin_popcount(dir[2 * i]);
+    }
+    if (threadIdx.x == 0 && total > (uint32_t)ranked) set_status(status, CRYSTAL_EFULL);
+}
+
+hipError_t launch_qmask_rank(uint32_t *table, int64_t span, int32_t key_min, int32_t ranked, const int32_t *keys,
+                             int64_t n, int32_t *status, hipStream_t s) {
+    const int64_t n_dir = qmask_dir_entries(span);
+    hipError_t e = fill_u32(table, qmask_ranked_words(span, ranked), 0u, s);
+    if (e != hipSuccess) return e;
+    if (n > 0) {
+        int64_t grid = (n + 255) / 256;
+        const int64_t cap = (int64_t)device_cu_count() * 16;
+        if (grid > cap) grid = cap;
+        hipLaunchKernelGGL(qmask_rank_bits_kernel, dim3((unsigned)grid), dim3(256), 0, s, table, span, key_min, keys,
+                           n, status);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(qmask_rank_scan_kernel, dim3(1), dim3(kRankScanBlock), 0, s, table, n_dir, ranked, status);
     return hipGetLastError();
 }
 
@@ -73,36 +150,47 @@ __device__ __forceinline__ void load_vec_sel(const int32_t *__restrict__ col, in
     }
 }
 
+// Column of plan step s (predicates first, then joins).  Both candidates are
+// loaded (indices clamped into range) and the value is selected: a select
+// between two addresses inside the kernel argument would make the compiler
+// copy the whole argument into scratch memory.
 __device__ __forceinline__ int shared_step_col(const StarPlanDev &p, int s) {
-    return s < p.n_preds ? p.pred_col[s] : p.joins[s - p.n_preds].fk_col;
+    const int i = s < CRYSTAL_MAX_PREDS ? s : CRYSTAL_MAX_PREDS - 1;
+    const int j = s - p.n_preds;
+    const int pc = p.pred_col[i < 0 ? 0 : i];
+    const int jc = p.joins[j < 0 ? 0 : (j < CRYSTAL_MAX_JOINS ? j : CRYSTAL_MAX_JOINS - 1)].fk_col;
+    return s < p.n_preds ? pc : jc;
 }
 
 template <int BLOCK, int IPT>
 __global__ __launch_bounds__(BLOCK) void shared_scan_kernel(const BatchDev b, int32_t *status, int64_t n_tiles) {
     using T = TileShape<BLOCK, IPT>;
-    // scalar results: one private LDS accumulator per (query, thread), so that
-    // adds never contend; reduced once per workgroup at the end
-    // dynamic LDS: b.n_queries * BLOCK words for a scalar plan, then the
-    // staged mask tables (see BatchDev::stage_off)
+    // scalar results: one LDS accumulator per (query, lane), shared by the
+    // workgroup's waves.  The lanes of a wave add to distinct slots, and the
+    // adds are LDS atomics without return, so no wave waits on another's;
+    // reduced once per workgroup at the end.
+    // dynamic LDS: b.n_queries * 64 64-bit slots for a scalar plan, then the
+    // staged mask tables (see MaskDev::stage_off)
     extern __shared__ uint64_t dyn[];
-    uint64_t(*acc)[BLOCK] = reinterpret_cast<uint64_t(*)[BLOCK]>(dyn);
+    uint64_t(*acc)[kWave] = reinterpret_cast<uint64_t(*)[kWave]>(dyn);
     uint32_t *lds_words = reinterpret_cast<uint32_t *>(dyn);
-    __shared__ uint64_t red[BLOCK / kWave];
+    const uint32_t lane = threadIdx.x & (kWave - 1);
     const StarPlanDev &p = b.plan;
     const int n_steps = p.n_preds + p.n_joins;
     if (p.scalar) {
-        for (int q = 0; q < b.n_queries; ++q) acc[q][threadIdx.x] = 0;
+        for (int i = threadIdx.x; i < b.n_queries * kWave; i += BLOCK) dyn[i] = 0;
     }
     bool any_staged = false;
     for (int j = 0; j < p.n_joins; ++j) {
-        if (b.stage_words[j] == 0) continue;
+        const MaskDev &md = b.mask[j];
+        if (md.stage_words == 0) continue;
         any_staged = true;
-        const uint32_t *src = reinterpret_cast<const uint32_t *>(b.mask[j]);
-        uint32_t *dst = lds_words + b.stage_off[j];
-        for (int64_t i = threadIdx.x; i < b.stage_words[j]; i += BLOCK) dst[i] = src[i];
-        if (threadIdx.x == 0) dst[b.stage_words[j]] = 0u;  // entries past the table read 0
+        const uint32_t *src = reinterpret_cast<const uint32_t *>(md.mem);
+        uint32_t *dst = lds_words + md.stage_off;
+        for (int64_t i = threadIdx.x; i < md.stage_words; i += BLOCK) dst[i] = src[i];
+        if (threadIdx.x == 0) dst[md.stage_words] = 0u;  // entries past the table read 0
     }
-    if (any_staged) __syncthreads();
+    if (any_staged || p.scalar) __syncthreads();
     bool bad_group = false;
     uint32_t qm[IPT];
 
@@ -128,23 +216,50 @@ __global__ __launch_bounds__(BLOCK) void shared_scan_kernel(const BatchDev b, in
 #pragma unroll
             for (int k = 0; k < IPT; ++k) qm[k] &= m[k];
         } else {
-            const int j = s - p.n_preds;
-            const uint32_t last = (uint32_t)(b.mask_span[j] - 1);
-            const int32_t kmin = b.mask_kmin[j];
-            if (b.stage_words[j] > 0) {
+            const MaskDev &md = b.mask[s - p.n_preds];
+            const uint32_t last = (uint32_t)(md.span - 1);
+            const int32_t kmin = md.key_min;
+            const uint32_t rk = (uint32_t)md.ranked;
+            if (md.stage_words > 0 && rk) {
+                // ranked table in LDS: keys past the span read the directory's
+                // last entry, which has no presence bits
+                const uint32_t *sw = lds_words + md.stage_off;
+                const uint32_t dlast = (uint32_t)(qmask_dir_entries(md.span) - 1);
+                const uint16_t *ent = reinterpret_cast<const uint16_t *>(sw + 2 * (dlast + 1u));
+#pragma unroll
+                for (int k = 0; k < IPT; ++k) {
+                    const uint32_t off = (uint32_t)x[k] - (uint32_t)kmin;
+                    const uint32_t wi = (off >> 5) < dlast ? (off >> 5) : dlast;
+                    const uint2 d = *reinterpret_cast<const uint2 *>(sw + 2 * wi);
+                    qm[k] &= (uint32_t)ent[ranked_entry(d.x, d.y, off, rk)];
+                }
+            } else if (md.stage_words > 0) {
                 // LDS-typed path (a pointer that may also address global
                 // memory would compile to flat loads).  Keys outside the
                 // table are clamped to the zero entry after it, so no range
                 // test is needed.
-                const uint16_t *stage = reinterpret_cast<const uint16_t *>(lds_words + b.stage_off[j]);
+                const uint16_t *stage = reinterpret_cast<const uint16_t *>(lds_words + md.stage_off);
                 const uint32_t span = last + 1u;
 #pragma unroll
                 for (int k = 0; k < IPT; ++k) {
                     const uint32_t off = (uint32_t)x[k] - (uint32_t)kmin;
                     qm[k] &= (uint32_t)stage[off < span ? off : span];
                 }
+            } else if (rk) {
+                const uint32_t *gw = reinterpret_cast<const uint32_t *>(md.mem);
+                const uint16_t *ent = reinterpret_cast<const uint16_t *>(gw + 2 * qmask_dir_entries(md.span));
+#pragma unroll
+                for (int k = 0; k < IPT; ++k) {
+                    const uint32_t off = (uint32_t)x[k] - (uint32_t)kmin;
+                    uint32_t m = 0;
+                    if (qm[k] != 0u && off <= last) {
+                        const uint2 d = *reinterpret_cast<const uint2 *>(gw + 2 * (off >> 5));
+                        m = ent[ranked_entry(d.x, d.y, off, rk)];
+                    }
+                    qm[k] &= m;
+                }
             } else {
-                const uint16_t *mt = b.mask[j];
+                const uint16_t *mt = md.mem;
 #pragma unroll
                 for (int k = 0; k < IPT; ++k) {
                     const uint32_t off = (uint32_t)x[k] - (uint32_t)kmin;
@@ -154,6 +269,12 @@ __global__ __launch_bounds__(BLOCK) void shared_scan_kernel(const BatchDev b, in
             }
         }
     };
+
+    // Step 2's column is loaded in full at the start of a tile while the
+    // wave's selective loads of it touched at least 3/4 of their cache lines
+    // (measured on the wave's previous tile): then the full load costs little
+    // more and saves one dependent memory round trip.
+    bool dense2 = true;
 
     // One tile.  `cur` holds the first step's column of this tile (loaded one
     // tile ahead); the same column of the workgroup's next tile is loaded into
@@ -167,8 +288,10 @@ __global__ __launch_bounds__(BLOCK) void shared_scan_kernel(const BatchDev b, in
         // the second step's column is read in full together with the first
         // (with up to 16 queries most of its vectors hold a live row anyway),
         // so the two loads share one memory round trip
-        int32_t w[IPT];
+        int32_t w[IPT], w2[IPT];
         if (n_steps > 1) block_load<BLOCK, IPT, true>(p.col[shared_step_col(p, 1)].p, base, b.row_end, w);
+        const bool pre2 = n_steps > 2 && dense2;
+        if (pre2) block_load<BLOCK, IPT, true>(p.col[shared_step_col(p, 2)].p, base, b.row_end, w2);
         const int64_t tn = tile + gridDim.x;
         if (n_steps > 0 && tn < n_tiles)
             block_load<BLOCK, IPT, true>(p.col[col0].p, b.row_begin + tn * T::ITEMS, b.row_end, nxt);
@@ -179,31 +302,46 @@ __global__ __launch_bounds__(BLOCK) void shared_scan_kernel(const BatchDev b, in
 #pragma unroll
             for (int k = 0; k < IPT; ++k) any |= (uint32_t)(qm[k] != 0u) << k;
             if (ballot(any != 0u) == 0) break;
+            if (s == 2) {
+                // cache lines a selective load would touch: eight lanes'
+                // 16-byte vectors per 128-byte line
+                int touched = 0;
+#pragma unroll
+                for (int ch = 0; ch < T::CHUNKS; ++ch) {
+                    uint64_t m = ballot(((any >> (ch * T::VEC)) & T::VMASK) != 0u);
+                    m |= m >> 4;
+                    m |= m >> 2;
+                    m |= m >> 1;
+                    touched += __builtin_popcountll(m & 0x0101010101010101ull);
+                }
+                dense2 = 4 * touched >= 3 * 8 * T::CHUNKS;
+                if (pre2) {
+                    apply_step(2, w2);
+                    continue;
+                }
+            }
             block_load_sel<BLOCK, IPT, true>(p.col[shared_step_col(p, s)].p, base, b.row_end, any, w);
             apply_step(s, w);
         }
-        // survivors: the measure and group index once per row, then every query
-        // that kept the row.  A vector of VEC rows is handled at a time: its
-        // loads (measures, then group keys, then their payloads) are issued
-        // together whenever one of its rows survives, so a vector pays one
-        // memory round trip per load step instead of one per surviving row,
-        // and only one vector's values are live at a time.
+        // survivors.  Their measures are read for the whole tile at once (one
+        // memory round trip); the group index is formed a vector of VEC rows
+        // at a time, skipping vectors without a survivor.
         uint32_t surv = 0;
 #pragma unroll
         for (int k = 0; k < IPT; ++k) surv |= (uint32_t)(qm[k] != 0u) << k;
         if (ballot(surv != 0u) == 0) return;
+        int32_t a[IPT], c[IPT];
+        if (p.agg != CRYSTAL_AGG_COUNT) block_load_sel<BLOCK, IPT, true>(p.col[p.agg_col0].p, base, b.row_end, surv, a);
+        if (p.agg == CRYSTAL_AGG_SUM_PRODUCT || p.agg == CRYSTAL_AGG_SUM_DIFF)
+            block_load_sel<BLOCK, IPT, true>(p.col[p.agg_col1].p, base, b.row_end, surv, c);
 #pragma unroll
         for (int ch = 0; ch < T::CHUNKS; ++ch) {
             const uint32_t sc = (surv >> (ch * T::VEC)) & T::VMASK;
             if (ballot(sc != 0u) == 0) continue;
             const int64_t row0 = T::index(base, ch, 0);
-            int32_t a[T::VEC], c[T::VEC];
             int64_t g[T::VEC];
 #pragma unroll
             for (int e = 0; e < T::VEC; ++e) g[e] = 0;
-            if (p.agg != CRYSTAL_AGG_COUNT) load_vec_sel<T::VEC>(p.col[p.agg_col0].p, row0, b.row_end, sc, a);
-            if (p.agg == CRYSTAL_AGG_SUM_PRODUCT || p.agg == CRYSTAL_AGG_SUM_DIFF)
-                load_vec_sel<T::VEC>(p.col[p.agg_col1].p, row0, b.row_end, sc, c);
             if (!p.scalar) {
                 for (int jj = 0; jj < p.n_joins; ++jj) {
                     const StarJoinDev &j = p.joins[jj];
@@ -229,15 +367,16 @@ __global__ __launch_bounds__(BLOCK) void shared_scan_kernel(const BatchDev b, in
             }
 #pragma unroll
             for (int e = 0; e < T::VEC; ++e) {
-                uint32_t m = qm[ch * T::VEC + e];
+                const int k = ch * T::VEC + e;
+                uint32_t m = qm[k];
                 if (!m) continue;
                 uint64_t val = 1;
                 if (p.agg == CRYSTAL_AGG_SUM)
-                    val = (uint64_t)(int64_t)a[e];
+                    val = (uint64_t)(int64_t)a[k];
                 else if (p.agg == CRYSTAL_AGG_SUM_PRODUCT)
-                    val = (uint64_t)((int64_t)a[e] * (int64_t)c[e]);
+                    val = (uint64_t)((int64_t)a[k] * (int64_t)c[k]);
                 else if (p.agg == CRYSTAL_AGG_SUM_DIFF)
-                    val = (uint64_t)((int64_t)a[e] - (int64_t)c[e]);
+                    val = (uint64_t)((int64_t)a[k] - (int64_t)c[k]);
                 if (!p.scalar && (uint64_t)g[e] >= (uint64_t)p.n_groups) {
                     bad_group = true;
                     continue;
@@ -245,9 +384,9 @@ __global__ __launch_bounds__(BLOCK) void shared_scan_kernel(const BatchDev b, in
                 while (m) {
                     const int q = __builtin_ctz(m);
                     m &= m - 1u;
-                    if (p.scalar)  // private slot: an LDS add without return, no read-modify-write wait
-                        __hip_atomic_fetch_add((__attribute__((address_space(3))) uint64_t *)&acc[q][threadIdx.x],
-                                               val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    if (p.scalar)  // the lane's slot: an LDS add without return
+                        __hip_atomic_fetch_add((__attribute__((address_space(3))) uint64_t *)&acc[q][lane], val,
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                     else
                         atomic_add_u64(b.out[q] + g[e], val);
                 }
@@ -270,10 +409,12 @@ __global__ __launch_bounds__(BLOCK) void shared_scan_kernel(const BatchDev b, in
     }
     if (bad_group) set_status(status, CRYSTAL_ERANGE);
     if (p.scalar) {
-        for (int q = 0; q < b.n_queries; ++q) {
-            const uint64_t t = block_sum_u64<BLOCK>(acc[q][threadIdx.x], red);
-            if (threadIdx.x == 0 && t) atomic_add_u64(b.out[q], t);
-            __syncthreads();  // red is reused by the next query's sum
+        __syncthreads();  // every wave's adds are done
+        if (threadIdx.x < kWave) {
+            for (int q = 0; q < b.n_queries; ++q) {
+                const uint64_t t = wave_sum_u64(acc[q][lane]);
+                if (lane == 0 && t) atomic_add_u64(b.out[q], t);
+            }
         }
     }
 }
@@ -289,19 +430,25 @@ static hipError_t shared_t(const LaunchCfg &cfg_in, const BatchDev &b_in, int32_
     // LDS: the scalar accumulators, then, in join order, every join's mask
     // table (plus one zero word) that still fits without dropping below 8
     // waves per CU
-    const int64_t acc_words32 = b.plan.scalar ? (int64_t)b.n_queries * BLOCK * 2 : 0;
+    const int64_t acc_words32 = b.plan.scalar ? (int64_t)b.n_queries * kWave * 2 : 0;
     const int64_t min_blocks = (8 * kWave + BLOCK - 1) / BLOCK;
     int64_t words32 = acc_words32;
     for (int j = 0; j < CRYSTAL_MAX_JOINS; ++j) {
-        b.stage_off[j] = 0;
-        b.stage_words[j] = 0;
+        MaskDev &md = b.mask[j];
+        md.stage_off = 0;
+        md.stage_words = 0;
         if (j >= b.plan.n_joins) continue;
-        const int64_t w = (b.mask_span[j] + 1) / 2;
-        const int64_t bytes = (words32 + w + 1) * 4;
+        // a ranked table starts at an even word (its directory is read 64
+        // bits at a time) and carries its own zero entries; a plain one is
+        // followed by one zero word
+        const bool ranked = md.ranked > 0;
+        const int64_t w = ranked ? qmask_ranked_words(md.span, md.ranked) : (md.span + 1) / 2;
+        const int64_t at = ranked ? (words32 + 1) & ~int64_t(1) : words32;
+        const int64_t bytes = (at + w + 1) * 4;
         if (bytes + 1024 > device_lds_per_block() || device_lds_per_cu() / (bytes + 1024) < min_blocks) continue;
-        b.stage_off[j] = words32;
-        b.stage_words[j] = w;
-        words32 += w + 1;
+        md.stage_off = at;
+        md.stage_words = w;
+        words32 = at + w + 1;
     }
     const int64_t lds_bytes = words32 * 4;
     if (words32 > acc_words32) {

@@ -211,7 +211,11 @@ class ServingTemplates:
                               device=dev)
             ht.build(d["key"], payload=payload, status=self.status)
             self.tables.append(ht)
-        self.masks = [cx.QueryMask(d["key_min"], d["key_max"], device=dev) for d in schema.dims]
+        # query-mask tables: rank-compressed where the dimension's keys fill
+        # little of their span (the date keys), so that the date table fits
+        # in LDS beside the first join's
+        self.masks = [cx.QueryMask(d["key_min"], d["key_max"], device=dev, keys=d["key"], status=self.status)
+                      for d in schema.dims]
         joins = []
         for j in DEFAULT_JOIN_ORDER:
             jj = dict(table=self.tables[j], fk_col=j)
@@ -241,6 +245,9 @@ class ServingTemplates:
             ht = cx.HashTable(cx.HT_DIRECT, dm["n"], dm["key_min"], dm["key_max"], has_payload=False, device=dev)
             ht.build(dm["key"], status=self.status)
             dm["table"] = ht
+            # plain tables: with the scalar accumulators the Q1.1 template's
+            # plain date table (122 KB) still fits in LDS, and a plain lookup
+            # is one LDS read where a ranked one is two dependent reads
             dm["mask"] = cx.QueryMask(dm["key_min"], dm["key_max"], device=dev)
             q11_joins.append(dict(table=ht, fk_col=dm["fk_col"]))
         self.q11_template = cx.StarQuery(self.cols, n_groups=1, joins=q11_joins,

@@ -34,7 +34,7 @@ def test_every_declared_symbol_is_exported(cx):
 
 def test_struct_layout_matches_binding(cx):
     lib = cx.load()
-    assert lib.crystal_abi_version() == 4
+    assert lib.crystal_abi_version() == 5
     for which, ty in enumerate((cx.Range, cx.HT, cx.Pred, cx.Join, cx.StarQueryC, cx.QmaskTableC,
                                 cx.BatchQueryC, cx.BatchC, cx.ServerTemplateC, cx.ServerConfigC,
                                 cx.ServerStatsC, cx.BuildItemC, cx.ColFormatC)):
@@ -196,3 +196,27 @@ def test_star_query_format_validation(cx):
     q.formats[0] = cx.ColFormatC(3, 0)
     st = ctypes.c_void_p(1 << 20)
     assert lib.crystal_run_star_query(ctypes.byref(q), ctypes.c_void_p(1 << 21), st, None, 0, None) == cx.EINVAL
+
+
+def test_ranked_qmask_sizes_and_host_errors(cx):
+    """Rank-compressed query-mask tables: ceil(span / 32) + 1 directory entries
+    of 8 bytes, then ranked + 1 two-byte entries, rounded up to 16 bytes."""
+    lib = cx.load()
+    assert lib.crystal_qmask_ranked_bytes(61_130, 2556) == (8 * 1912 + 4 * 1279 + 15) // 16 * 16
+    assert lib.crystal_qmask_ranked_bytes(1, 1) == 32        # two directory entries, one entry word
+    for span, ranked in [(0, 4), (100, 0), (100, -1), ((1 << 26) + 1, 4)]:
+        assert lib.crystal_qmask_ranked_bytes(span, ranked) == 0
+    status = ctypes.c_int32()
+    mem = ctypes.create_string_buffer(4096 + 16)
+    addr = (ctypes.addressof(mem) + 15) // 16 * 16
+    keys = ctypes.c_void_p(addr)
+    bad = []
+    for span, ranked, n in [(100, 0, 4), (100, -2, 4), ((1 << 26) + 1, 4, 4), (100, 4, -1), (0, 4, 4)]:
+        t = cx.QmaskTableC(mem=addr, span=span, key_min=0, ranked=ranked)
+        bad.append(lib.crystal_qmask_rank(ctypes.byref(t), keys, n, ctypes.byref(status), None))
+    assert bad == [cx.EINVAL] * 5
+    t = cx.QmaskTableC(mem=addr + 4, span=100, key_min=0, ranked=4)       # misaligned table
+    assert lib.crystal_qmask_rank(ctypes.byref(t), keys, 4, ctypes.byref(status), None) == cx.EINVAL
+    rs = (cx.Range * 1)(cx.Range(0, 0))
+    t = cx.QmaskTableC(mem=addr, span=(1 << 26) + 1, key_min=0, ranked=4)
+    assert lib.crystal_qmask_build(ctypes.byref(t), keys, None, 4, rs, 1, ctypes.byref(status), None) == cx.EINVAL

@@ -1,6 +1,8 @@
 """GPU parity of shared-scan batches: every query of a batch equals the CPU
 oracle and its own single-query launch, over the whole table and over row
 segments accumulated launch by launch."""
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -93,3 +95,105 @@ def test_qmask_table_bits(serving):
         keep = (d.filter >= lo) & (d.filter <= hi)
         want[d.key[keep] - d.key.min()] |= np.uint16(1 << q)
     assert np.array_equal(raw, want)
+
+
+# ---------------------------------------------------- rank-compressed masks --
+def test_date_mask_is_ranked_and_matches_plain(serving):
+    """The date dimension's keys fill 2,556 of a 61,130-key span: its table is
+    rank-compressed, and reads, key by key, like the plain table."""
+    announce("qmask ranked dense")
+    t, sv = serving
+    d = sv.s.dims[0]
+    assert sv.masks[0].ranked == d["n"]
+    assert sv.masks[1].ranked == 0                       # dense key domain: plain table
+    plain = cx.QueryMask(d["key_min"], d["key_max"], keys=d["key"], ranked=False)
+    ranges = [(c, c) for c in range(16)]
+    cx.check_status(sv.masks[0].build(d["key"], d["filter"], ranges))
+    cx.check_status(plain.build(d["key"], d["filter"], ranges))
+    got = sv.masks[0].dense().cpu().numpy()
+    assert np.array_equal(got, plain.dense().cpu().numpy())
+    dim = t.dims[0]
+    want = np.zeros(plain.c.span, dtype=np.int64)
+    for q, (lo, hi) in enumerate(ranges):
+        keep = (dim.filter >= lo) & (dim.filter <= hi)
+        want[dim.key[keep] - dim.key.min()] |= 1 << q
+    assert np.array_equal(got, want)
+
+
+def plain_scan(sv, template, dims):
+    masks = [cx.QueryMask(d["key_min"], d["key_max"], keys=d["key"], ranked=False) for d in dims]
+    return cx.SharedScan(template, masks), masks
+
+
+@pytest.mark.parametrize("block,ipt", [(64, 4), (256, 8), (1024, 16)])
+def test_ranked_and_plain_batches_agree(serving, block, ipt):
+    """64-thread workgroups leave the ranked date table in global memory
+    (staging it would cut below eight waves per CU); larger ones stage it."""
+    announce("shared ranked vs plain", block, ipt)
+    t, sv = serving
+    cx.tune_set(cx.K_SHARED_SCAN, block, ipt, 0)
+    try:
+        rng = np.random.default_rng(block + ipt)
+        consts = [datagen.random_star_constants(rng) for _ in range(16)]
+        sv.build_star_masks(consts)
+        outs = zeros(STAR_GROUPS, 16)
+        cx.check_status(sv.run_star_batch(outs))
+        dims = [sv.s.dims[j] for j in queries.DEFAULT_JOIN_ORDER]
+        scan, masks = plain_scan(sv, sv.star_template, dims)
+        for m, d, j in zip(masks, dims, queries.DEFAULT_JOIN_ORDER):
+            cx.check_status(m.build(d["key"], d["filter"], [(c[j], c[j]) for c in consts]))
+        ref = zeros(STAR_GROUPS, 16)
+        cx.check_status(scan.run([[] for _ in ref], ref))
+        for q in range(16):
+            assert torch.equal(outs[q], ref[q]), q
+        for q in (0, 15):
+            assert np.array_equal(outs[q].cpu().numpy(), star_oracle(t, consts[q])[0]), q
+        f = q11_fact_of(t)
+        qc = [datagen.random_q11_constants(rng) for _ in range(16)]
+        qo = zeros(1, 16)
+        cx.check_status(sv.run_q11_batch(qc, qo))
+        for q in (0, 7, 15):
+            y, dl, qm = qc[q]
+            assert int(qo[q].item()) == q11_oracle(f, y, (dl, dl + 2), qm), (q, qc[q])
+    finally:
+        cx.tune_reset()
+    cx.check_status(sv.status)
+
+
+def ranked_table(span, ranked, key_min=0):
+    lib = cx.load()
+    c = cx.QmaskTableC()
+    c.span, c.key_min, c.ranked = span, key_min, ranked
+    mem = torch.zeros(max(16, lib.crystal_qmask_ranked_bytes(span, ranked)), dtype=torch.uint8, device="cuda")
+    c.mem = mem.data_ptr()
+    return c, mem
+
+
+def rank(c, keys):
+    lib = cx.load()
+    st = cx.new_status()
+    k = torch.tensor(keys, dtype=torch.int32, device="cuda")
+    assert lib.crystal_qmask_rank(ctypes.byref(c), cx._ptr(k), k.numel(), cx._ptr(st), cx._stream()) == cx.OK
+    torch.cuda.synchronize()
+    return int(st.item())
+
+
+def test_qmask_rank_directory_and_errors():
+    announce("qmask rank errors")
+    lib = cx.load()
+    c, mem = ranked_table(100, 8, key_min=1000)
+    assert rank(c, [1000, 1031, 1032, 1099, 1031]) == cx.OK     # a duplicate counts once
+    words = mem[:8 * 5].view(torch.int32).view(-1, 2).cpu().numpy().astype(np.int64) & 0xFFFFFFFF
+    assert list(words[:, 0]) == [1 | (1 << 31), 1, 0, 1 << 3, 0]     # presence bits per 32 keys
+    assert list(words[:, 1]) == [0, 2, 3, 3, 4]                       # keys present before each entry
+    # build: the entry of a key absent from the directory is an error
+    st = cx.new_status()
+    k = torch.tensor([1000, 1099, 1001], dtype=torch.int32, device="cuda")
+    rs = (cx.Range * 1)(cx.Range(0, 0))
+    assert lib.crystal_qmask_build(ctypes.byref(c), cx._ptr(k), None, 3, rs, 1, cx._ptr(st), cx._stream()) == cx.OK
+    torch.cuda.synchronize()
+    assert int(st.item()) == cx.ERANGE
+    c2, _ = ranked_table(64, 2)
+    assert rank(c2, [0, 5, 9]) == cx.EFULL                        # three keys, room for two
+    c3, _ = ranked_table(64, 8)
+    assert rank(c3, [0, 64]) == cx.ERANGE                          # 64 is past the span
