@@ -8,11 +8,13 @@
 // misses.  A join step loads its foreign-key column once and ANDs the row's
 // mask with the dimension's query-mask table: for every key, the set of
 // batch queries whose dimension filter that row passes (built per batch by
-// qmask_build_kernel).  So a join costs one 2-byte lookup per row however many
-// queries share the pass.  Survivors form their group index from the
+// qmask_build_kernel).  So a join costs one 2-byte lookup per row (a
+// directory read and an entry read for a rank-compressed table) however many
+// queries share the pass.  Tables that fit are copied into LDS once per
+// workgroup and read there.  Survivors form their group index from the
 // template's dimension payloads once, then add the measure to every query
 // whose bit is set: grouped results with 64-bit atomics into the query's own
-// output, scalar results through per-workgroup LDS partials.
+// output, scalar results through per-workgroup LDS accumulators.
 //
 // Outputs are accumulated, never cleared here: a query admitted into a batch
 // can be answered over several launches that cover successive row ranges.
