@@ -228,12 +228,23 @@ __global__ __launch_bounds__(BLOCK) void shared_scan_kernel(const BatchDev b, in
                 const uint32_t *sw = lds_words + md.stage_off;
                 const uint32_t dlast = (uint32_t)(qmask_dir_entries(md.span) - 1);
                 const uint16_t *ent = reinterpret_cast<const uint16_t *>(sw + 2 * (dlast + 1u));
+                // a vector of VEC items at a time: its directory reads issued
+                // together, then its entry reads, so the two dependent LDS
+                // latencies are paid once per vector rather than per item
 #pragma unroll
-                for (int k = 0; k < IPT; ++k) {
-                    const uint32_t off = (uint32_t)x[k] - (uint32_t)kmin;
-                    const uint32_t wi = (off >> 5) < dlast ? (off >> 5) : dlast;
-                    const uint2 d = *reinterpret_cast<const uint2 *>(sw + 2 * wi);
-                    qm[k] &= (uint32_t)ent[ranked_entry(d.x, d.y, off, rk)];
+                for (int c = 0; c < IPT; c += T::VEC) {
+                    uint32_t off[T::VEC], e[T::VEC];
+                    uint2 d[T::VEC];
+#pragma unroll
+                    for (int i = 0; i < T::VEC; ++i) {
+                        off[i] = (uint32_t)x[c + i] - (uint32_t)kmin;
+                        const uint32_t wi = (off[i] >> 5) < dlast ? (off[i] >> 5) : dlast;
+                        d[i] = *reinterpret_cast<const uint2 *>(sw + 2 * wi);
+                    }
+#pragma unroll
+                    for (int i = 0; i < T::VEC; ++i) e[i] = ranked_entry(d[i].x, d[i].y, off[i], rk);
+#pragma unroll
+                    for (int i = 0; i < T::VEC; ++i) qm[c + i] &= (uint32_t)ent[e[i]];
                 }
             } else if (md.stage_words > 0) {
                 // LDS-typed path (a pointer that may also address global
