@@ -503,7 +503,7 @@ crystal_status crystal_graph_end(void *stream, crystal_graph **out) {
     if (hipStreamEndCapture(as_stream(stream), &g) != hipSuccess || !g) return CRYSTAL_EHIP;
     hipGraphExec_t e = nullptr;
     if (hipGraphInstantiate(&e, g, nullptr, nullptr, 0) != hipSuccess) {
-        hipGraphDestroy(g);
+        (void)hipGraphDestroy(g);
         return CRYSTAL_EHIP;
     }
     *out = new crystal_graph{g, e};

@@ -197,9 +197,11 @@ struct Server {
     bool step_done(const Step &s) {
         if (cfg.fake_executor) return now_ns() - s.t_issue >= cfg.fake_step_ns;
         const hipError_t e = hipEventQuery(s.ev);
-        if (e == hipSuccess) return true;
-        if (e != hipErrorNotReady) fail(CRYSTAL_EHIP);
-        return false;
+        if (e == hipErrorNotReady) return false;
+        // a failed query retires the step too (so that shutdown never waits on
+        // it); the server's error is set, and every later call reports it
+        if (e != hipSuccess) fail(CRYSTAL_EHIP);
+        return true;
     }
 
     // Retire completed steps in order: finished queries get their results.
@@ -207,7 +209,7 @@ struct Server {
         while (!inflight.empty() && step_done(inflight.front())) {
             Step s = std::move(inflight.front());
             inflight.pop_front();
-            if (s.ev) hipEventDestroy(s.ev);
+            if (s.ev) (void)hipEventDestroy(s.ev);  // the step is complete; nothing to do on failure
             const int64_t t_done = now_ns();
             std::lock_guard<std::mutex> lk(mu);
             for (auto [t, q] : s.completing) {
@@ -248,7 +250,10 @@ struct Server {
     }
 
     void run() {
-        if (!cfg.fake_executor) hipSetDevice(device_id);
+        if (!cfg.fake_executor && hipSetDevice(device_id) != hipSuccess) {
+            fail(CRYSTAL_EHIP);
+            return;
+        }
         while (!stop.load()) {
             retire();
             admit();
@@ -325,7 +330,10 @@ crystal_status crystal_server_create(const crystal_server_config *cfg, crystal_s
     s.masks_dirty.assign(cfg->n_templates, std::vector<bool>(1, true));
     s.queue.resize(cfg->n_templates);
     if (!cfg->fake_executor) {
-        hipGetDevice(&s.device_id);
+        if (hipGetDevice(&s.device_id) != hipSuccess) {
+            delete h;
+            return CRYSTAL_EHIP;
+        }
         if (cfg->stream) {
             s.stream = (hipStream_t)cfg->stream;
         } else if (hipStreamCreate(&s.stream) != hipSuccess) {
@@ -337,14 +345,14 @@ crystal_status crystal_server_create(const crystal_server_config *cfg, crystal_s
         size_t host_bytes = 0;
         for (int t = 0; t < cfg->n_templates; ++t) host_bytes += (size_t)s.n_groups(t) * 8 * cfg->slots_per_template;
         if (hipHostMalloc((void **)&s.pinned, host_bytes, hipHostMallocDefault) != hipSuccess) {
-            if (s.own_stream) hipStreamDestroy(s.stream);
+            if (s.own_stream) (void)hipStreamDestroy(s.stream);
             delete h;
             return CRYSTAL_EHIP;
         }
         s.status = (int32_t *)cfg->workspace;
         if (fill_u32((uint32_t *)s.status, 4, 0u, s.stream) != hipSuccess) {
-            hipHostFree(s.pinned);
-            if (s.own_stream) hipStreamDestroy(s.stream);
+            (void)hipHostFree(s.pinned);
+            if (s.own_stream) (void)hipStreamDestroy(s.stream);
             delete h;
             return CRYSTAL_EHIP;
         }
@@ -425,9 +433,11 @@ crystal_status crystal_server_destroy(crystal_server *h) {
     if (s.worker.joinable()) s.worker.join();
     crystal_status st = s.error;
     if (!s.cfg.fake_executor) {
-        hipStreamSynchronize(s.stream);
-        if (s.pinned) hipHostFree(s.pinned);
-        if (s.own_stream) hipStreamDestroy(s.stream);
+        // teardown: a failure here leaves nothing to undo; the server's own
+        // error (if any) is what is reported
+        if (hipStreamSynchronize(s.stream) != hipSuccess && st == CRYSTAL_OK) st = CRYSTAL_EHIP;
+        if (s.pinned) (void)hipHostFree(s.pinned);
+        if (s.own_stream) (void)hipStreamDestroy(s.stream);
     }
     delete h;
     return st;
