@@ -52,7 +52,7 @@ def parse():
                    help="star: store the two dense-phase foreign keys as 16-bit offsets (compressed columns)")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
     p.add_argument("--tune", default="", help="kernel block,ipt,grid_per_cu override, e.g. 256,16,0")
-    p.add_argument("--rates", default="200,500,1000,2000", help="serve: Poisson arrival rates (q/s)")
+    p.add_argument("--rates", default="500,1000,2000,4000", help="serve: Poisson arrival rates (q/s)")
     p.add_argument("--seconds", type=float, default=3.0, help="serve: arrival window per rate")
     p.add_argument("--segments", type=int, default=8, help="serve: clock segments of the fact table")
     return p.parse_args()

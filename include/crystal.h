@@ -66,7 +66,7 @@ int32_t crystal_abi_version(void);
  * 3 crystal_join, 4 crystal_star_query, 5 crystal_qmask_table,
  * 6 crystal_batch_query, 7 crystal_batch, 8 crystal_server_template,
  * 9 crystal_server_config, 10 crystal_server_stats, 11 crystal_ht_build_item,
- * 12 crystal_col_format.  0 for any other value. */
+ * 12 crystal_col_format, 13 crystal_qmask_build_item.  0 for any other value. */
 size_t crystal_struct_size(int32_t which);
 
 /* ------------------------------------------------------------------------ */
@@ -360,6 +360,25 @@ crystal_status crystal_qmask_build(const crystal_qmask_table *t, const int32_t *
                                    const crystal_range *ranges, int32_t n_queries,
                                    int32_t *status, void *stream);
 
+/* Build the query-mask tables of several joins in one call: the same
+ * result, per item, as crystal_qmask_build on it, from two launches (one
+ * clears every table, one builds them all) instead of two per table.  Items
+ * must use distinct table memory; n_items <= CRYSTAL_MAX_JOINS.  `t` and
+ * `ranges` point to host memory; the other pointers are device memory as in
+ * crystal_qmask_build.  This is the call the server makes when a template's
+ * set of queries changes. */
+typedef struct {
+    const crystal_qmask_table *t;
+    const int32_t *keys;
+    const int32_t *filter_col;    /* NULL: every row passes */
+    int64_t n;
+    const crystal_range *ranges;  /* n_queries ranges */
+    int32_t n_queries;
+    int32_t reserved;
+} crystal_qmask_build_item;
+crystal_status crystal_qmask_build_batch(const crystal_qmask_build_item *items, int32_t n_items,
+                                         int32_t *status, void *stream);
+
 typedef struct crystal_batch_query {
     crystal_range preds[CRYSTAL_MAX_PREDS]; /* this query's fact-predicate ranges, plan order */
     int64_t *out;                           /* device, n_groups int64, ACCUMULATED (not cleared) */
@@ -402,7 +421,8 @@ typedef struct crystal_server_template {
     const int32_t *dim_keys[CRYSTAL_MAX_JOINS];   /* per join: dimension key column (device)    */
     const int32_t *dim_filter[CRYSTAL_MAX_JOINS]; /* per join: dimension filter column (device) */
     int64_t dim_rows[CRYSTAL_MAX_JOINS];
-    crystal_qmask_table masks[CRYSTAL_MAX_JOINS]; /* per join: mask-table memory (caller-owned) */
+    crystal_qmask_table masks[CRYSTAL_MAX_JOINS]; /* per join: its own mask table (caller-owned; a
+                                                     ranked one's directory built beforehand) */
 } crystal_server_template;
 
 typedef struct crystal_server_config {

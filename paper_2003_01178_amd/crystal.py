@@ -72,6 +72,11 @@ class QmaskTableC(ctypes.Structure):
     _fields_ = [("mem", c_vp), ("span", c_i64), ("key_min", c_i32), ("ranked", c_i32)]
 
 
+class QmaskBuildItemC(ctypes.Structure):
+    _fields_ = [("t", ctypes.POINTER(QmaskTableC)), ("keys", c_vp), ("filter_col", c_vp), ("n", c_i64),
+                ("ranges", ctypes.POINTER(Range)), ("n_queries", c_i32), ("reserved", c_i32)]
+
+
 class BatchQueryC(ctypes.Structure):
     _fields_ = [("preds", Range * MAX_PREDS), ("out", c_vp)]
 
@@ -135,6 +140,7 @@ def _declare(lib):
         "crystal_qmask_bytes": (ctypes.c_size_t, [c_i64]),
         "crystal_qmask_ranked_bytes": (ctypes.c_size_t, [c_i64, c_i32]),
         "crystal_qmask_rank": (c_i32, [P(QmaskTableC), c_vp, c_i64, c_vp, c_vp]),
+        "crystal_qmask_build_batch": (c_i32, [P(QmaskBuildItemC), c_i32, c_vp, c_vp]),
         "crystal_qmask_build": (c_i32, [P(QmaskTableC), c_vp, c_vp, c_i64, P(Range), c_i32, c_vp, c_vp]),
         "crystal_run_shared_scan": (c_i32, [P(BatchC), c_vp, c_vp]),
         "crystal_server_workspace_bytes": (ctypes.c_size_t, [P(ServerConfigC)]),
@@ -184,7 +190,8 @@ def load(path: str = LIB_PATH):
             raise ImportError(f"libcrystal.so is missing and could not be built: {e}") from e
     lib = _declare(ctypes.CDLL(path))
     for which, ty in enumerate((Range, HT, Pred, Join, StarQueryC, QmaskTableC, BatchQueryC, BatchC,
-                                ServerTemplateC, ServerConfigC, ServerStatsC, BuildItemC, ColFormatC)):
+                                ServerTemplateC, ServerConfigC, ServerStatsC, BuildItemC, ColFormatC,
+                                QmaskBuildItemC)):
         if lib.crystal_struct_size(which) != ctypes.sizeof(ty):
             raise ImportError(f"ABI layout mismatch for {ty.__name__}")
     _lib = lib
@@ -517,6 +524,29 @@ class QueryMask:
                                        _col(filter_col) if filter_col is not None else None, keys.numel(),
                                        rs, len(ranges), _ptr(status), _stream(stream)), "crystal_qmask_build")
         return status
+
+
+def build_query_masks(items, status=None, stream=None):
+    """Build several joins' query-mask tables in one call (two launches):
+    the same tables as QueryMask.build on each.  items: (QueryMask, keys,
+    filter_col or None, ranges) per join, at most MAX_JOINS, distinct tables."""
+    lib = load()
+    if len(items) > MAX_JOINS:
+        raise ValueError("at most MAX_JOINS tables per batch")
+    arr = (QmaskBuildItemC * max(1, len(items)))()
+    keep = []
+    dev = items[0][1].device if items else "cuda"
+    for i, (m, keys, filt, ranges) in enumerate(items):
+        if filt is not None and filt.numel() != keys.numel():
+            raise ValueError("filter column and keys differ in length")
+        rs = (Range * max(1, len(ranges)))(*[Range(int(lo), int(hi)) for lo, hi in ranges])
+        keep.append(rs)
+        arr[i] = QmaskBuildItemC(ctypes.pointer(m.c), _col(keys), _col(filt) if filt is not None else None,
+                                 keys.numel(), ctypes.cast(rs, ctypes.POINTER(Range)), len(ranges), 0)
+    status = new_status(dev) if status is None else status
+    _check(lib.crystal_qmask_build_batch(arr, len(items), _ptr(status), _stream(stream)),
+           "crystal_qmask_build_batch")
+    return status
 
 
 class SharedScan:

@@ -248,6 +248,7 @@ size_t crystal_struct_size(int32_t which) {
     case 10: return sizeof(crystal_server_stats);
     case 11: return sizeof(crystal_ht_build_item);
     case 12: return sizeof(crystal_col_format);
+    case 13: return sizeof(crystal_qmask_build_item);
     default: return 0;
     }
 }
@@ -450,6 +451,35 @@ crystal_status crystal_qmask_build(const crystal_qmask_table *t, const int32_t *
     }
     return from_hip(launch_qmask_build((uint16_t *)t->mem, t->span, t->key_min, t->ranked, keys, filter_col, n, r,
                                        status, as_stream(stream)));
+}
+
+crystal_status crystal_qmask_build_batch(const crystal_qmask_build_item *items, int32_t n_items, int32_t *status,
+                                         void *stream) {
+    if (!items || !status || n_items < 0 || n_items > CRYSTAL_MAX_JOINS) return CRYSTAL_EINVAL;
+    QmaskItem it[CRYSTAL_MAX_JOINS];
+    for (int i = 0; i < n_items; ++i) {
+        const crystal_qmask_build_item &x = items[i];
+        if (!qmask_table_ok(x.t) || x.n < 0 || (x.n > 0 && !x.keys) || x.n_queries < 0 ||
+            x.n_queries > CRYSTAL_MAX_BATCH || (x.n_queries > 0 && !x.ranges))
+            return CRYSTAL_EINVAL;
+        for (int j = 0; j < i; ++j)
+            if (items[j].t->mem == x.t->mem) return CRYSTAL_EINVAL;
+        QmaskItem &d = it[i];
+        d.words = (uint32_t *)x.t->mem;
+        d.span = x.t->span;
+        d.key_min = x.t->key_min;
+        d.ranked = x.t->ranked;
+        d.keys = x.keys;
+        d.filter_col = x.filter_col;
+        d.n = x.n;
+        d.r = QmaskRanges{};
+        d.r.n = x.n_queries;
+        for (int q = 0; q < x.n_queries; ++q) {
+            d.r.lo[q] = x.ranges[q].lo;
+            d.r.hi[q] = x.ranges[q].hi;
+        }
+    }
+    return from_hip(launch_qmask_build_batch(it, n_items, status, as_stream(stream)));
 }
 
 crystal_status crystal_run_shared_scan(const crystal_batch *b, int32_t *status, void *stream) {

@@ -176,6 +176,18 @@ struct BatchDev {
 hipError_t launch_qmask_build(uint16_t *table, int64_t span, int32_t key_min, int32_t ranked, const int32_t *keys,
                               const int32_t *filter_col, int64_t n, const QmaskRanges &r, int32_t *status,
                               hipStream_t s);
+// One table of a batched query-mask build.
+struct QmaskItem {
+    uint32_t *words;
+    int64_t span;
+    int32_t key_min;
+    int32_t ranked;
+    const int32_t *keys;
+    const int32_t *filter_col;
+    int64_t n;
+    QmaskRanges r;
+};
+hipError_t launch_qmask_build_batch(const QmaskItem *items, int n_items, int32_t *status, hipStream_t s);
 hipError_t launch_qmask_rank(uint32_t *table, int64_t span, int32_t key_min, int32_t ranked, const int32_t *keys,
                              int64_t n, int32_t *status, hipStream_t s);
 hipError_t launch_shared_scan(const LaunchCfg &cfg, const BatchDev &b, int32_t *status, hipStream_t s);

@@ -124,17 +124,20 @@ struct Server {
             if (!cfg.fake_executor) {
                 // rebuild the query masks of joins whose slot set changed
                 if (masks_dirty[t][0]) {
+                    // every join's table in one batched build (two launches)
+                    crystal_range r[CRYSTAL_MAX_JOINS][CRYSTAL_MAX_BATCH];
+                    crystal_qmask_build_item items[CRYSTAL_MAX_JOINS];
                     for (int j = 0; j < tp.plan.n_joins; ++j) {
-                        crystal_range r[CRYSTAL_MAX_BATCH];
                         for (int q = 0; q < cfg.slots_per_template; ++q) {
                             const bool on = ss[q].busy && ss[q].steps_left > 0;
-                            r[q] = on ? ss[q].filters[j] : crystal_range{1, 0};
+                            r[j][q] = on ? ss[q].filters[j] : crystal_range{1, 0};
                         }
-                        if (crystal_qmask_build(&tp.masks[j], tp.dim_keys[j], tp.dim_filter[j], tp.dim_rows[j], r,
-                                                cfg.slots_per_template, status, stream) != CRYSTAL_OK) {
-                            fail(CRYSTAL_EHIP);
-                            return false;
-                        }
+                        items[j] = crystal_qmask_build_item{&tp.masks[j], tp.dim_keys[j], tp.dim_filter[j],
+                                                            tp.dim_rows[j], r[j], cfg.slots_per_template, 0};
+                    }
+                    if (crystal_qmask_build_batch(items, tp.plan.n_joins, status, stream) != CRYSTAL_OK) {
+                        fail(CRYSTAL_EHIP);
+                        return false;
                     }
                     masks_dirty[t][0] = false;
                 }
@@ -293,8 +296,11 @@ static crystal_status validate(const crystal_server_config &c) {
         if (n_rows >= 0 && tp.plan.n_rows != n_rows) return CRYSTAL_EINVAL;  // one fact table
         n_rows = tp.plan.n_rows;
         if (!c.fake_executor)
-            for (int j = 0; j < tp.plan.n_joins; ++j)
+            for (int j = 0; j < tp.plan.n_joins; ++j) {
                 if (!tp.masks[j].mem || !tp.dim_keys[j] || tp.dim_rows[j] < 0) return CRYSTAL_EINVAL;
+                for (int i = 0; i < j; ++i)  // each join has its own table (built together)
+                    if (tp.masks[i].mem == tp.masks[j].mem) return CRYSTAL_EINVAL;
+            }
     }
     if (n_rows <= 0) return CRYSTAL_EINVAL;
     if (!c.fake_executor && (!c.workspace || c.workspace_bytes < workspace_bytes(c))) return CRYSTAL_ESCRATCH;

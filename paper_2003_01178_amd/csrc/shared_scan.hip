@@ -37,48 +37,115 @@ __device__ __forceinline__ uint32_t ranked_entry(uint32_t bits, uint32_t before,
 // entry[key - key_min] |= bit q for every query q whose range holds the row's
 // filter attribute (entry[rank of the key] for a ranked table).  Two 16-bit
 // entries share a 32-bit word, set with atomicOr.
+__device__ __forceinline__ void qmask_row(uint32_t *__restrict__ words, int64_t span, int32_t key_min,
+                                          int32_t ranked, const int32_t *__restrict__ keys,
+                                          const int32_t *__restrict__ filter_col, int64_t i, const QmaskRanges &r,
+                                          int32_t *status) {
+    const uint32_t *dir = words;
+    uint32_t *entries = ranked ? words + 2 * qmask_dir_entries(span) : words;
+    const uint32_t off = (uint32_t)keys[i] - (uint32_t)key_min;
+    if ((int64_t)off >= span) {
+        set_status(status, CRYSTAL_ERANGE);
+        return;
+    }
+    uint32_t e = off;
+    if (ranked) {
+        e = ranked_entry(dir[2 * (off >> 5)], dir[2 * (off >> 5) + 1], off, (uint32_t)ranked);
+        if (e >= (uint32_t)ranked) {  // not in the directory
+            set_status(status, CRYSTAL_ERANGE);
+            return;
+        }
+    }
+    const int32_t f = filter_col ? filter_col[i] : 0;
+    uint32_t m = 0;
+    for (int q = 0; q < r.n; ++q) m |= (uint32_t)(filter_col ? in_range(f, r.lo[q], r.hi[q]) : true) << q;
+    if (m) atomicOr(entries + (e >> 1), m << ((e & 1u) * 16u));
+}
+
+// words of a table's entries, cleared before every build
+__host__ __device__ inline int64_t qmask_entry_words(int64_t span, int32_t ranked) {
+    return ranked ? ((int64_t)ranked + 2) / 2 : (span + 1) / 2;
+}
+__host__ __device__ inline int64_t qmask_entry_offset(int64_t span, int32_t ranked) {
+    return ranked ? 2 * qmask_dir_entries(span) : 0;
+}
+
 __global__ __launch_bounds__(256) void qmask_build_kernel(uint32_t *__restrict__ words, int64_t span,
                                                           int32_t key_min, int32_t ranked,
                                                           const int32_t *__restrict__ keys,
                                                           const int32_t *__restrict__ filter_col, int64_t n,
                                                           QmaskRanges r, int32_t *status) {
-    const uint32_t *dir = words;
-    uint32_t *entries = ranked ? words + 2 * qmask_dir_entries(span) : words;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const uint32_t off = (uint32_t)keys[i] - (uint32_t)key_min;
-        if ((int64_t)off >= span) {
-            set_status(status, CRYSTAL_ERANGE);
-            continue;
-        }
-        uint32_t e = off;
-        if (ranked) {
-            e = ranked_entry(dir[2 * (off >> 5)], dir[2 * (off >> 5) + 1], off, (uint32_t)ranked);
-            if (e >= (uint32_t)ranked) {  // not in the directory
-                set_status(status, CRYSTAL_ERANGE);
-                continue;
-            }
-        }
-        const int32_t f = filter_col ? filter_col[i] : 0;
-        uint32_t m = 0;
-        for (int q = 0; q < r.n; ++q)
-            m |= (uint32_t)(filter_col ? in_range(f, r.lo[q], r.hi[q]) : true) << q;
-        if (m) atomicOr(entries + (e >> 1), m << ((e & 1u) * 16u));
-    }
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        qmask_row(words, span, key_min, ranked, keys, filter_col, i, r, status);
 }
 
 hipError_t launch_qmask_build(uint16_t *table, int64_t span, int32_t key_min, int32_t ranked, const int32_t *keys,
                               const int32_t *filter_col, int64_t n, const QmaskRanges &r, int32_t *status,
                               hipStream_t s) {
     uint32_t *words = (uint32_t *)table;
-    hipError_t e = ranked ? fill_u32(words + 2 * qmask_dir_entries(span), ((int64_t)ranked + 2) / 2, 0u, s)
-                          : fill_u32(words, (span + 1) / 2, 0u, s);
+    hipError_t e = fill_u32(words + qmask_entry_offset(span, ranked), qmask_entry_words(span, ranked), 0u, s);
     if (e != hipSuccess || n == 0) return e;
     int64_t grid = (n + 255) / 256;
     const int64_t cap = (int64_t)device_cu_count() * 16;
     if (grid > cap) grid = cap;
     hipLaunchKernelGGL(qmask_build_kernel, dim3((unsigned)grid), dim3(256), 0, s, words, span, key_min, ranked, keys,
                        filter_col, n, r, status);
+    return hipGetLastError();
+}
+
+// Batched build: one kernel clears every table's entries, a second builds
+// them all, its workgroups split among the tables in proportion to their rows.
+struct QmaskBatchDev {
+    int32_t count;
+    QmaskItem it[CRYSTAL_MAX_JOINS];
+    int64_t block0[CRYSTAL_MAX_JOINS + 1];  // first workgroup of each table; block0[count] = grid
+};
+
+__global__ __launch_bounds__(256) void qmask_clear_batch_kernel(QmaskBatchDev b) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int t = 0; t < b.count; ++t) {
+        const QmaskItem &it = b.it[t];
+        uint32_t *w = it.words + qmask_entry_offset(it.span, it.ranked);
+        const int64_t n = qmask_entry_words(it.span, it.ranked);
+        for (int64_t i = g0; i < n; i += stride) w[i] = 0u;
+    }
+}
+
+__global__ __launch_bounds__(256) void qmask_build_batch_kernel(QmaskBatchDev b, int32_t *status) {
+    int t = 0;
+    while (t + 1 < b.count && (int64_t)blockIdx.x >= b.block0[t + 1]) ++t;
+    const QmaskItem &it = b.it[t];
+    const int64_t stride = (b.block0[t + 1] - b.block0[t]) * blockDim.x;
+    for (int64_t i = ((int64_t)blockIdx.x - b.block0[t]) * blockDim.x + threadIdx.x; i < it.n; i += stride)
+        qmask_row(it.words, it.span, it.key_min, it.ranked, it.keys, it.filter_col, i, it.r, status);
+}
+
+hipError_t launch_qmask_build_batch(const QmaskItem *items, int n_items, int32_t *status, hipStream_t s) {
+    if (n_items <= 0) return hipSuccess;
+    QmaskBatchDev b = {};
+    b.count = n_items;
+    int64_t clear_words = 0, blocks = 0;
+    const int64_t cap = (int64_t)device_cu_count() * 16;
+    for (int t = 0; t < n_items; ++t) {
+        b.it[t] = items[t];
+        const int64_t w = qmask_entry_words(items[t].span, items[t].ranked);
+        clear_words = w > clear_words ? w : clear_words;
+        b.block0[t] = blocks;
+        int64_t nb = (items[t].n + 255) / 256;
+        if (nb > cap) nb = cap;
+        if (nb < 1) nb = 1;  // a table with no rows still owns one (idle) workgroup
+        blocks += nb;
+    }
+    b.block0[n_items] = blocks;
+    int64_t cgrid = (clear_words + 255) / 256;
+    if (cgrid > cap) cgrid = cap;
+    if (cgrid < 1) cgrid = 1;
+    hipLaunchKernelGGL(qmask_clear_batch_kernel, dim3((unsigned)cgrid), dim3(256), 0, s, b);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(qmask_build_batch_kernel, dim3((unsigned)blocks), dim3(256), 0, s, b, status);
     return hipGetLastError();
 }
 

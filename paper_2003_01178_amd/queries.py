@@ -284,9 +284,8 @@ class ServingTemplates:
 
     def build_star_masks(self, consts_per_query, stream=None):
         """Dimension j of query q keeps rows with filter == consts_per_query[q][j]."""
-        for j, d in enumerate(self.s.dims):
-            self.masks[j].build(d["key"], d["filter"], [(c[j], c[j]) for c in consts_per_query],
-                                status=self.status, stream=stream)
+        cx.build_query_masks([(self.masks[j], d["key"], d["filter"], [(c[j], c[j]) for c in consts_per_query])
+                              for j, d in enumerate(self.s.dims)], status=self.status, stream=stream)
 
     @staticmethod
     def q11_preds(year, disc_lo, qty_max):
@@ -298,8 +297,8 @@ class ServingTemplates:
 
     def build_q11_masks(self, consts_per_query, stream=None):
         ranges = [self.q11_preds(*c) for c in consts_per_query]
-        for i, dm in enumerate(self.q11_domains):
-            dm["mask"].build(dm["key"], dm["filter"], [r[i] for r in ranges], status=self.status, stream=stream)
+        cx.build_query_masks([(dm["mask"], dm["key"], dm["filter"], [r[i] for r in ranges])
+                              for i, dm in enumerate(self.q11_domains)], status=self.status, stream=stream)
 
     def run_q11_batch(self, consts, outs, row_begin=0, row_end=None, status=None, stream=None):
         self.build_q11_masks(consts, stream=stream)

@@ -37,7 +37,7 @@ def test_struct_layout_matches_binding(cx):
     assert lib.crystal_abi_version() == 5
     for which, ty in enumerate((cx.Range, cx.HT, cx.Pred, cx.Join, cx.StarQueryC, cx.QmaskTableC,
                                 cx.BatchQueryC, cx.BatchC, cx.ServerTemplateC, cx.ServerConfigC,
-                                cx.ServerStatsC, cx.BuildItemC, cx.ColFormatC)):
+                                cx.ServerStatsC, cx.BuildItemC, cx.ColFormatC, cx.QmaskBuildItemC)):
         assert lib.crystal_struct_size(which) == ctypes.sizeof(ty), ty.__name__
     assert lib.crystal_struct_size(99) == 0
 
@@ -220,3 +220,32 @@ def test_ranked_qmask_sizes_and_host_errors(cx):
     rs = (cx.Range * 1)(cx.Range(0, 0))
     t = cx.QmaskTableC(mem=addr, span=(1 << 26) + 1, key_min=0, ranked=4)
     assert lib.crystal_qmask_build(ctypes.byref(t), keys, None, 4, rs, 1, ctypes.byref(status), None) == cx.EINVAL
+
+
+def test_qmask_build_batch_host_errors(cx):
+    lib = cx.load()
+    status = ctypes.c_int32()
+    mem = ctypes.create_string_buffer(4096 + 16)
+    addr = (ctypes.addressof(mem) + 15) // 16 * 16
+    t1 = cx.QmaskTableC(mem=addr, span=100, key_min=0, ranked=0)
+    t2 = cx.QmaskTableC(mem=addr + 1024, span=100, key_min=0, ranked=0)
+    rs = (cx.Range * 2)(cx.Range(0, 1), cx.Range(2, 3))
+    keys = ctypes.c_void_p(addr + 2048)
+
+    def item(t, n=4, nq=2, k=keys, r=rs):
+        return cx.QmaskBuildItemC(ctypes.pointer(t), k, None, n, ctypes.cast(r, ctypes.POINTER(cx.Range)), nq, 0)
+
+    def call(items, n=None):
+        arr = (cx.QmaskBuildItemC * max(1, len(items)))(*items)
+        return lib.crystal_qmask_build_batch(arr, len(items) if n is None else n, ctypes.byref(status), None)
+
+    assert call([item(t1), item(t1)]) == cx.EINVAL                  # one table twice
+    assert call([item(t1)] * 1, n=5) == cx.EINVAL                   # more than CRYSTAL_MAX_JOINS
+    assert call([item(t1), item(t2, n=-1)]) == cx.EINVAL
+    assert call([item(t1, nq=17)]) == cx.EINVAL
+    assert call([item(t1, k=None)]) == cx.EINVAL                    # rows without keys
+    assert call([item(t1, r=None)]) == cx.EINVAL                    # queries without ranges
+    bad = cx.QmaskTableC(mem=addr + 4, span=100, key_min=0, ranked=0)  # misaligned
+    assert call([item(bad)]) == cx.EINVAL
+    assert lib.crystal_qmask_build_batch(None, 1, ctypes.byref(status), None) == cx.EINVAL
+    assert call([], n=0) == cx.OK

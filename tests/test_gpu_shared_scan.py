@@ -197,3 +197,32 @@ def test_qmask_rank_directory_and_errors():
     assert rank(c2, [0, 5, 9]) == cx.EFULL                        # three keys, room for two
     c3, _ = ranked_table(64, 8)
     assert rank(c3, [0, 64]) == cx.ERANGE                          # 64 is past the span
+
+
+def test_qmask_build_batch_matches_single_builds(serving):
+    """One batched build of every join's table (a ranked date table among
+    plain ones) leaves the same tables as one build per table."""
+    announce("qmask build batch")
+    t, sv = serving
+    dims = sv.s.dims
+    rng = np.random.default_rng(7)
+    ranges = [[(int(a), int(a) + int(w)) for a, w in zip(rng.integers(0, 25, 16), rng.integers(0, 3, 16))]
+              for _ in dims]
+    single = [cx.QueryMask(d["key_min"], d["key_max"], keys=d["key"]) for d in dims]
+    for m, d, r in zip(single, dims, ranges):
+        cx.check_status(m.build(d["key"], d["filter"], r))
+    batched = [cx.QueryMask(d["key_min"], d["key_max"], keys=d["key"]) for d in dims]
+    # dirty the batched tables first: the batch clears before it builds
+    for m, d in zip(batched, dims):
+        cx.check_status(m.build(d["key"], None, [(0, 0)] * 16))
+    cx.check_status(cx.build_query_masks([(m, d["key"], d["filter"], r) for m, d, r in zip(batched, dims, ranges)]))
+    assert batched[0].ranked > 0 and batched[1].ranked == 0
+    for j, (a, b) in enumerate(zip(single, batched)):
+        assert torch.equal(a.dense(), b.dense()), j
+    # a key outside a table's span is reported, as by the single build
+    d = dims[1]
+    bad_keys = d["key"].clone()
+    bad_keys[5] = d["key_max"] + 1
+    st = cx.build_query_masks([(batched[1], bad_keys, d["filter"], ranges[1])])
+    torch.cuda.synchronize()
+    assert int(st.item()) == cx.ERANGE
