@@ -34,8 +34,8 @@ LLC_BYTES = 256 * 2 ** 20   # MI355X last-level (Infinity) cache
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=20)
-    p.add_argument("--warmup", type=int, default=5)
+    p.add_argument("--steps", type=int, default=200)
+    p.add_argument("--warmup", type=int, default=20)
     p.add_argument("--workload", default="star", choices=["star", "q11", "select", "project", "join", "copy", "serve",
                                                               "partition", "sort", "groupby"])
     p.add_argument("--rows", type=int, default=0, help="override the fact/column length")
