@@ -226,3 +226,27 @@ def test_qmask_build_batch_matches_single_builds(serving):
     st = cx.build_query_masks([(batched[1], bad_keys, d["filter"], ranges[1])])
     torch.cuda.synchronize()
     assert int(st.item()) == cx.ERANGE
+
+
+def test_ranked_table_wide_span():
+    """A ranked table over a 2^24-key span (65,536 directory entries, ranked
+    by one workgroup) reads like the plain table, key by key."""
+    announce("qmask ranked wide span")
+    rng = np.random.default_rng(11)
+    span = 1 << 24
+    keys = np.unique(rng.integers(0, span, 5000)).astype(np.int32) + 1000
+    rng.shuffle(keys)
+    filt = rng.integers(0, 10, keys.size).astype(np.int32)
+    kd, fd = torch.from_numpy(keys).cuda(), torch.from_numpy(filt).cuda()
+    ranges = [(q % 10, q % 10 + q // 10) for q in range(16)]
+    ranked = cx.QueryMask(1000, 1000 + span - 1, keys=kd, ranked=True)
+    plain = cx.QueryMask(1000, 1000 + span - 1, keys=kd, ranked=False)
+    cx.check_status(ranked.status)
+    assert ranked.ranked == keys.size
+    cx.check_status(ranked.build(kd, fd, ranges))
+    cx.check_status(plain.build(kd, fd, ranges))
+    assert torch.equal(ranked.dense(), plain.dense())
+    want = np.zeros(keys.size, dtype=np.int64)
+    for q, (lo, hi) in enumerate(ranges):
+        want |= ((filt >= lo) & (filt <= hi)).astype(np.int64) << q
+    assert np.array_equal(ranked.dense()[kd.long() - 1000].cpu().numpy(), want)
