@@ -171,6 +171,9 @@ struct BatchDev {
     uint64_t *out[kMaxBatch];
     int64_t row_begin;
     int64_t row_end;
+    // set by the launcher: 32-bit word of the dynamic LDS where the per-wave
+    // queues of sparse rows start (kQueueCap rows and masks per wave), or -1
+    int64_t queue_off;
 };
 
 hipError_t launch_qmask_build(uint16_t *table, int64_t span, int32_t key_min, int32_t ranked, const int32_t *keys,

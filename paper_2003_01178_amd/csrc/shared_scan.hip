@@ -231,9 +231,63 @@ __device__ __forceinline__ int shared_step_col(const StarPlanDev &p, int s) {
     return s < p.n_preds ? pc : jc;
 }
 
+// Queue of sparse rows per wave: once a tile's rows still alive after the
+// dense steps are few, they are appended (row, query mask, next step) to the
+// wave's queue and finished 64 at a time, one row per lane, instead of
+// running every later step over the whole tile.
+constexpr int kQueueCap = 128;  // entries per wave (a power of two, at least 2 x 64)
+
+// One plan step for one queued row: its value x and query mask m.
+__device__ __forceinline__ uint32_t step_one(const BatchDev &b, const uint32_t *lds_words, int s, int32_t x,
+                                             uint32_t m) {
+    const StarPlanDev &p = b.plan;
+    if (s < p.n_preds) {
+        uint32_t r = 0;
+        for (int q = 0; q < b.n_queries; ++q) {
+            const uint32_t bit = 1u << q;
+            if (ballot((m & bit) != 0u) == 0) continue;
+            r |= in_range(x, b.pred_lo[q][s], b.pred_hi[q][s]) ? bit : 0u;
+        }
+        return m & r;
+    }
+    const MaskDev &md = b.mask[s - p.n_preds];
+    const uint32_t off = (uint32_t)x - (uint32_t)md.key_min;
+    const uint32_t rk = (uint32_t)md.ranked;
+    if (md.stage_words > 0) {
+        const uint32_t *sw = lds_words + md.stage_off;
+        if (rk) {
+            const uint32_t dlast = (uint32_t)(qmask_dir_entries(md.span) - 1);
+            const uint32_t wi = (off >> 5) < dlast ? (off >> 5) : dlast;
+            const uint2 d = *reinterpret_cast<const uint2 *>(sw + 2 * wi);
+            const uint16_t *ent = reinterpret_cast<const uint16_t *>(sw + 2 * (dlast + 1u));
+            return m & (uint32_t)ent[ranked_entry(d.x, d.y, off, rk)];
+        }
+        const uint16_t *stage = reinterpret_cast<const uint16_t *>(sw);
+        const uint32_t span = (uint32_t)md.span;
+        return m & (uint32_t)stage[off < span ? off : span];
+    }
+    if (m == 0u || (int64_t)off >= md.span) return 0u;
+    if (rk) {
+        const uint32_t *gw = reinterpret_cast<const uint32_t *>(md.mem);
+        const uint2 d = *reinterpret_cast<const uint2 *>(gw + 2 * (off >> 5));
+        const uint16_t *ent = reinterpret_cast<const uint16_t *>(gw + 2 * qmask_dir_entries(md.span));
+        return m & (uint32_t)ent[ranked_entry(d.x, d.y, off, rk)];
+    }
+    return m & (uint32_t)md.mem[off];
+}
+
 template <int BLOCK, int IPT>
-__global__ __launch_bounds__(BLOCK) void shared_scan_kernel(const BatchDev b, int32_t *status, int64_t n_tiles) {
+__global__ __launch_bounds__(BLOCK) void shared_scan_kernel(const BatchDev batch, int32_t *status, int64_t n_tiles) {
     using T = TileShape<BLOCK, IPT>;
+    // The batch is read in place from the kernel-argument segment, where it
+    // is the first argument (offset 0).  Used as a by-value parameter, its
+    // many dynamically indexed fields made the compiler copy all 1.6 KB of it
+    // into scratch memory.
+#if __HIP_DEVICE_COMPILE__
+    const BatchDev &b = *reinterpret_cast<const BatchDev *>(__builtin_amdgcn_kernarg_segment_ptr());
+#else  // the host pass only parses the body
+    const BatchDev &b = batch;
+#endif
     // scalar results: one LDS accumulator per (query, lane), shared by the
     // workgroup's waves.  The lanes of a wave add to distinct slots, and the
     // adds are LDS atomics without return, so no wave waits on another's;
@@ -350,6 +404,64 @@ __global__ __launch_bounds__(BLOCK) void shared_scan_kernel(const BatchDev b, in
         }
     };
 
+    // queue of sparse rows (see kQueueCap): absolute row, then query mask |
+    // (next step << 16); head and tail are the same in every lane of the wave
+    uint32_t *q_row = lds_words + (b.queue_off >= 0 ? b.queue_off : 0) + (threadIdx.x / kWave) * (2 * kQueueCap);
+    uint32_t *q_msk = q_row + kQueueCap;
+    uint32_t head = 0, tail = 0;
+
+    // The remaining plan steps of one queued row from step s0, then its
+    // aggregate for every query still set in m.
+    auto finish_row = [&](int64_t row, uint32_t m, int s0) {
+        for (int s = 2; s < n_steps; ++s) {
+            if (ballot(m != 0u) == 0) return;
+            if (s < s0) continue;
+            const int32_t x = m ? p.col[shared_step_col(p, s)].p[row] : 0;
+            m = step_one(b, lds_words, s, x, m);
+        }
+        if (m == 0u) return;
+        uint64_t val = 1;
+        if (p.agg != CRYSTAL_AGG_COUNT) {
+            const int64_t a = p.col[p.agg_col0].p[row];
+            const int64_t c = (p.agg == CRYSTAL_AGG_SUM_PRODUCT || p.agg == CRYSTAL_AGG_SUM_DIFF)
+                                  ? (int64_t)p.col[p.agg_col1].p[row] : 0;
+            val = (uint64_t)(p.agg == CRYSTAL_AGG_SUM ? a : p.agg == CRYSTAL_AGG_SUM_PRODUCT ? a * c : a - c);
+        }
+        int64_t g = 0;
+        if (!p.scalar) {
+            for (int jj = 0; jj < p.n_joins; ++jj) {
+                const StarJoinDev &j = p.joins[jj];
+                if (j.g_bits == 0) continue;
+                const int32_t fk = p.col[j.fk_col].p[row];
+                int32_t pay = 0;
+                if (j.kind == CRYSTAL_HT_DIRECT) {
+                    const uint32_t off = (uint32_t)fk - (uint32_t)j.key_min;
+                    if ((int64_t)off < j.span && j.payload) pay = j.payload[off];
+                } else if (fk != kEmptyKey) {
+                    probe_linear((const v2i *)j.slots, j.mask, j.shift, fk, pay);
+                }
+                g += ((int64_t)payload_field(pay, j.g_shift, j.g_mask, j.g_bits) - (int64_t)j.g_base) * j.g_stride;
+            }
+            if ((uint64_t)g >= (uint64_t)p.n_groups) {
+                bad_group = true;
+                return;
+            }
+        }
+        while (m) {
+            const int q = __builtin_ctz(m);
+            m &= m - 1u;
+            if (p.scalar)
+                __hip_atomic_fetch_add((__attribute__((address_space(3))) uint64_t *)&acc[q][lane], val,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            else
+                atomic_add_u64(b.out[q] + g, val);
+        }
+    };
+    auto finish_entry = [&](uint32_t slot) {
+        const uint32_t mw = q_msk[slot];
+        finish_row((int64_t)q_row[slot], mw & 0xffffu, (int)(mw >> 16));
+    };
+
     // Step 2's column is loaded in full at the start of a tile while the
     // wave's selective loads of it touched at least 3/4 of their cache lines
     // (measured on the wave's previous tile): then the full load costs little
@@ -381,7 +493,7 @@ __global__ __launch_bounds__(BLOCK) void shared_scan_kernel(const BatchDev b, in
             uint32_t any = 0;
 #pragma unroll
             for (int k = 0; k < IPT; ++k) any |= (uint32_t)(qm[k] != 0u) << k;
-            if (ballot(any != 0u) == 0) break;
+            if (ballot(any != 0u) == 0) return;
             if (s == 2) {
                 // cache lines a selective load would touch: eight lanes'
                 // 16-byte vectors per 128-byte line
@@ -398,6 +510,33 @@ __global__ __launch_bounds__(BLOCK) void shared_scan_kernel(const BatchDev b, in
                 if (pre2) {
                     apply_step(2, w2);
                     continue;
+                }
+            }
+            if (b.queue_off >= 0) {
+                // few live rows left in the wave: queue them (the queue holds
+                // fewer than 64 before, so at most 127 after) and finish the
+                // queue 64 rows at a time
+                uint32_t total;
+                const uint32_t before = wave_exclusive_scan_small<T::CBITS>((uint32_t)__builtin_popcount(any), total);
+                if (total <= (uint32_t)kWave) {
+                    uint32_t pos = tail + before;
+#pragma unroll
+                    for (int k = 0; k < IPT; ++k) {
+                        if ((any >> k) & 1u) {
+                            const uint32_t slot = pos & (uint32_t)(kQueueCap - 1);
+                            q_row[slot] = (uint32_t)T::index(base, k / T::VEC, k % T::VEC);
+                            q_msk[slot] = qm[k] | ((uint32_t)s << 16);
+                            ++pos;
+                        }
+                    }
+                    tail += total;
+                    __builtin_amdgcn_wave_barrier();
+                    while (tail - head >= (uint32_t)kWave) {
+                        finish_entry((head + lane) & (uint32_t)(kQueueCap - 1));
+                        head += kWave;
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                    return;
                 }
             }
             block_load_sel<BLOCK, IPT, true>(p.col[shared_step_col(p, s)].p, base, b.row_end, any, w);
@@ -487,6 +626,7 @@ __global__ __launch_bounds__(BLOCK) void shared_scan_kernel(const BatchDev b, in
         run_tile(tile, vb, va);
         tile += gridDim.x;
     }
+    if (lane < tail - head) finish_entry((head + lane) & (uint32_t)(kQueueCap - 1));
     if (bad_group) set_status(status, CRYSTAL_ERANGE);
     if (p.scalar) {
         __syncthreads();  // every wave's adds are done
@@ -529,6 +669,15 @@ static hipError_t shared_t(const LaunchCfg &cfg_in, const BatchDev &b_in, int32_
         md.stage_off = at;
         md.stage_words = w;
         words32 = at + w + 1;
+    }
+    // the per-wave queues of sparse rows, when the plan has steps after the
+    // two dense ones, rows fit in 32 bits and the LDS has room
+    b.queue_off = -1;
+    const int64_t qwords = (int64_t)T::WAVES * 2 * kQueueCap;
+    if (b.plan.n_preds + b.plan.n_joins > 2 && b.plan.n_rows <= (int64_t)UINT32_MAX &&
+        (words32 + qwords) * 4 + 1024 <= device_lds_per_block()) {
+        b.queue_off = words32;
+        words32 += qwords;
     }
     const int64_t lds_bytes = words32 * 4;
     if (words32 > acc_words32) {
