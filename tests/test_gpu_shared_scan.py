@@ -8,7 +8,7 @@ import pytest
 import torch
 
 import oracle
-from helpers import STAR_GROUPS, announce, q11_oracle, star_oracle
+from helpers import STAR_GROUPS, announce, q11_oracle, star_oracle, star_oracle_joins
 from paper_2003_01178_amd import crystal as cx
 from paper_2003_01178_amd import datagen, queries
 
@@ -250,3 +250,41 @@ def test_ranked_table_wide_span():
     for q, (lo, hi) in enumerate(ranges):
         want |= ((filt >= lo) & (filt <= hi)).astype(np.int64) << q
     assert np.array_equal(ranked.dense()[kd.long() - 1000].cpu().numpy(), want)
+
+
+@pytest.mark.parametrize("nq", [3, 16])
+def test_batch_with_fact_predicates(serving, nq):
+    """A template with three fact predicates ahead of the four joins: the
+    predicate steps run over whole tiles, and, with few queries, the third
+    predicate and the joins also from the queue of sparse rows."""
+    announce("shared preds", nq)
+    t, sv = serving
+    joins = []
+    for j in queries.DEFAULT_JOIN_ORDER:
+        jj = dict(table=sv.tables[j], fk_col=j)
+        if j == 0:
+            jj["group"] = (32, 0, datagen.FIRST_YEAR, queries.GROUPS_PER_YEAR)
+        if j == 2:
+            jj["group"] = (32, 0, 0, 1)
+        joins.append(jj)
+    # fact columns: 0-3 keys, 4-5 measures, 6 discount, 7 quantity, 8 price
+    template = cx.StarQuery(sv.cols, n_groups=STAR_GROUPS, preds=[(6, 0, 0), (7, 0, 0), (5, 0, 0)],
+                            joins=joins, agg=cx.AGG_SUM, agg_cols=(4, 0))
+    scan = cx.SharedScan(template, [sv.masks[j] for j in queries.DEFAULT_JOIN_ORDER])
+    rng = np.random.default_rng(300 + nq)
+    consts = [datagen.random_star_constants(rng) for _ in range(nq)]
+    # narrow discount and quantity ranges keep few rows alive for few queries
+    preds = []
+    for _ in range(nq):
+        d = int(rng.integers(0, 11))
+        qlo = int(rng.integers(1, 46))
+        m2lo = int(rng.integers(1, 500_000))
+        preds.append([(d, d), (qlo, qlo + 4), (m2lo, m2lo + 500_000)])
+    sv.build_star_masks(consts)
+    outs = zeros(STAR_GROUPS, nq)
+    cx.check_status(scan.run(preds, outs))
+    cols = [*t.fk, t.m1, t.m2, t.extra["discount"], t.extra["quantity"], t.extra["price"]]
+    for q in range(nq):
+        want = oracle.star(cols, STAR_GROUPS, preds=[(6, *preds[q][0]), (7, *preds[q][1]), (5, *preds[q][2])],
+                           joins=star_oracle_joins(t, consts[q]), agg=oracle.AGG_SUM, agg_cols=(4, 0))
+        assert np.array_equal(outs[q].cpu().numpy(), want), q
