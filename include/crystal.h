@@ -58,7 +58,7 @@ typedef struct crystal_range {
 const char *crystal_status_string(int32_t status);
 
 /* ABI version of this header (incremented on any layout change). */
-#define CRYSTAL_ABI_VERSION 5
+#define CRYSTAL_ABI_VERSION 6
 int32_t crystal_abi_version(void);
 
 /* sizeof of the ABI structs as compiled into the library, so a binding can
@@ -540,9 +540,10 @@ enum {
     CRYSTAL_K_HT_PROBE = 2,
     CRYSTAL_K_GROUPBY = 3,
     CRYSTAL_K_STAR = 4,
-    CRYSTAL_K_SHARED_SCAN = 5,
+    CRYSTAL_K_SHARED_SCAN = 5,        /* shared-scan batches of grouped templates */
     CRYSTAL_K_RADIX = 6,
-    CRYSTAL_K_COUNT = 7
+    CRYSTAL_K_SHARED_SCAN_SCALAR = 7, /* shared-scan batches of scalar templates  */
+    CRYSTAL_K_COUNT = 8
 };
 
 /* Number of compiled (block, ipt) variants of `kernel`; fills up to `max`. */

@@ -192,16 +192,26 @@ def main(argv=None):
         outs_s = [torch.zeros(queries.STAR_GROUPS, dtype=torch.int64, device="cuda") for _ in range(16)]
         outs_q = [torch.zeros(1, dtype=torch.int64, device="cuda") for _ in range(16)]
 
-        def passes():
-            for o in outs_s + outs_q:
+        # grouped templates (the star template) and scalar ones (Q1.1) are
+        # tuned separately: their passes differ in registers and LDS
+        def star_pass():
+            for o in outs_s:
                 o.zero_()
             sv.star_scan.run([[] for _ in outs_s], outs_s, 0, n)
+
+        def q11_pass():
+            for o in outs_q:
+                o.zero_()
             sv.q11_scan.run([[] for _ in outs_q], outs_q, 0, n)
 
-        rows = sweep(cx.K_SHARED_SCAN, n, passes, lambda: np.concatenate([o.cpu().numpy() for o in outs_s + outs_q]),
+        rows = sweep(cx.K_SHARED_SCAN, n, star_pass, lambda: np.concatenate([o.cpu().numpy() for o in outs_s]),
                      candidates=quick_vec if args.quick else None, gpcs=(0, 1, 2, 4), reps=args.reps, log=log)
         assign(cx.K_SHARED_SCAN, [(n, rows[0][1:])])
-        report["shared_75M_2x16"] = rows[:8]
+        report["shared_star_75M_16"] = rows[:8]
+        rows = sweep(cx.K_SHARED_SCAN_SCALAR, n, q11_pass, lambda: np.concatenate([o.cpu().numpy() for o in outs_q]),
+                     candidates=quick_vec if args.quick else None, gpcs=(0, 1, 2, 4), reps=args.reps, log=log)
+        assign(cx.K_SHARED_SCAN_SCALAR, [(n, rows[0][1:])])
+        report["shared_q11_75M_16"] = rows[:8]
         del sv
         torch.cuda.empty_cache()
     if "radix" in kernels:

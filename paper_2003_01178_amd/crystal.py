@@ -20,7 +20,7 @@ LIB_PATH = os.environ.get("CRYSTAL_LIB", DEFAULT_LIB)
 OK, EINVAL, ESCRATCH, EFULL, EDUPKEY, EHIP, EBUSY, ERANGE = range(8)
 HT_LINEAR, HT_DIRECT = 0, 1
 AGG_SUM, AGG_SUM_PRODUCT, AGG_SUM_DIFF, AGG_COUNT = 0, 1, 2, 3
-K_SELECT, K_PROJECT, K_HT_PROBE, K_GROUPBY, K_STAR, K_SHARED_SCAN, K_RADIX = range(7)
+K_SELECT, K_PROJECT, K_HT_PROBE, K_GROUPBY, K_STAR, K_SHARED_SCAN, K_RADIX, K_SHARED_SCAN_SCALAR = range(8)
 MAX_COLS, MAX_PREDS, MAX_JOINS = 16, 4, 4
 I32_MIN, I32_MAX = -(2 ** 31), 2 ** 31 - 1
 

@@ -75,7 +75,8 @@ static LaunchCfg default_cfg(int kernel) {
     case CRYSTAL_K_HT_PROBE: return {256, 16, 8};
     case CRYSTAL_K_GROUPBY: return {256, 16, 0};
     case CRYSTAL_K_STAR: return {256, 16, 0};
-    case CRYSTAL_K_SHARED_SCAN: return {512, 16, 0};
+    case CRYSTAL_K_SHARED_SCAN: return {1024, 16, 0};
+    case CRYSTAL_K_SHARED_SCAN_SCALAR: return {1024, 8, 0};
     case CRYSTAL_K_RADIX: return {1024, 16, 0};
     default: return {256, 16, 0};
     }
@@ -511,7 +512,8 @@ crystal_status crystal_run_shared_scan(const crystal_batch *b, int32_t *status, 
     }
     d.row_begin = b->row_begin;
     d.row_end = b->row_end;
-    return from_hip(launch_shared_scan(tune_lookup(CRYSTAL_K_SHARED_SCAN, b->row_end - b->row_begin), d, status,
+    const int kernel = d.plan.scalar ? CRYSTAL_K_SHARED_SCAN_SCALAR : CRYSTAL_K_SHARED_SCAN;
+    return from_hip(launch_shared_scan(tune_lookup(kernel, b->row_end - b->row_begin), d, status,
                                        as_stream(stream)));
 }
 

@@ -481,7 +481,8 @@ __global__ __launch_bounds__(BLOCK) void shared_scan_kernel(const BatchDev batch
         // (with up to 16 queries most of its vectors hold a live row anyway),
         // so the two loads share one memory round trip
         int32_t w[IPT], w2[IPT];
-        if (n_steps > 1) block_load<BLOCK, IPT, true>(p.col[shared_step_col(p, 1)].p, base, b.row_end, w);
+        int w_col = n_steps > 1 ? shared_step_col(p, 1) : -1;  // the column w holds for the live rows
+        if (n_steps > 1) block_load<BLOCK, IPT, true>(p.col[w_col].p, base, b.row_end, w);
         const bool pre2 = n_steps > 2 && dense2;
         if (pre2) block_load<BLOCK, IPT, true>(p.col[shared_step_col(p, 2)].p, base, b.row_end, w2);
         const int64_t tn = tile + gridDim.x;
@@ -539,7 +540,8 @@ __global__ __launch_bounds__(BLOCK) void shared_scan_kernel(const BatchDev batch
                     return;
                 }
             }
-            block_load_sel<BLOCK, IPT, true>(p.col[shared_step_col(p, s)].p, base, b.row_end, any, w);
+            w_col = shared_step_col(p, s);
+            block_load_sel<BLOCK, IPT, true>(p.col[w_col].p, base, b.row_end, any, w);
             apply_step(s, w);
         }
         // survivors.  Their measures are read for the whole tile at once (one
@@ -549,10 +551,28 @@ __global__ __launch_bounds__(BLOCK) void shared_scan_kernel(const BatchDev batch
 #pragma unroll
         for (int k = 0; k < IPT; ++k) surv |= (uint32_t)(qm[k] != 0u) << k;
         if (ballot(surv != 0u) == 0) return;
+        // A measure that is also the column still held in w (the last step
+        // column read for these rows; the Q1.1 template's discount) is taken
+        // from the registers.  Only up to 8 items per thread: at 16 keeping w
+        // live this long spills.
         int32_t a[IPT], c[IPT];
-        if (p.agg != CRYSTAL_AGG_COUNT) block_load_sel<BLOCK, IPT, true>(p.col[p.agg_col0].p, base, b.row_end, surv, a);
-        if (p.agg == CRYSTAL_AGG_SUM_PRODUCT || p.agg == CRYSTAL_AGG_SUM_DIFF)
-            block_load_sel<BLOCK, IPT, true>(p.col[p.agg_col1].p, base, b.row_end, surv, c);
+        const bool a_in_w = IPT <= 8 && p.agg_col0 == w_col, c_in_w = IPT <= 8 && p.agg_col1 == w_col;
+        if (p.agg != CRYSTAL_AGG_COUNT) {
+            if (a_in_w) {
+#pragma unroll
+                for (int k = 0; k < IPT; ++k) a[k] = w[k];
+            } else {
+                block_load_sel<BLOCK, IPT, true>(p.col[p.agg_col0].p, base, b.row_end, surv, a);
+            }
+        }
+        if (p.agg == CRYSTAL_AGG_SUM_PRODUCT || p.agg == CRYSTAL_AGG_SUM_DIFF) {
+            if (c_in_w) {
+#pragma unroll
+                for (int k = 0; k < IPT; ++k) c[k] = w[k];
+            } else {
+                block_load_sel<BLOCK, IPT, true>(p.col[p.agg_col1].p, base, b.row_end, surv, c);
+            }
+        }
 #pragma unroll
         for (int ch = 0; ch < T::CHUNKS; ++ch) {
             const uint32_t sc = (surv >> (ch * T::VEC)) & T::VMASK;
