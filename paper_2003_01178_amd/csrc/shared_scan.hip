@@ -11,7 +11,9 @@
 // qmask_build_kernel).  So a join costs one 2-byte lookup per row (a
 // directory read and an entry read for a rank-compressed table) however many
 // queries share the pass.  Tables that fit are copied into LDS once per
-// workgroup and read there.  Survivors form their group index from the
+// workgroup and read there.  The first steps run over whole tiles; once few
+// rows of a wave's tile are still alive, they go to a per-wave queue and are
+// finished 64 at a time, one row per lane.  Survivors form their group index from the
 // template's dimension payloads once, then add the measure to every query
 // whose bit is set: grouped results with 64-bit atomics into the query's own
 // output, scalar results through per-workgroup LDS accumulators.
