@@ -41,6 +41,9 @@ inline bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 // Every launcher returns hipSuccess or the launch error; argument checking has
 // been done by the C ABI layer.
 hipError_t fill_u64(uint64_t *p, int64_t n, uint64_t value, hipStream_t s);
+// zero the slots slots[0..count) (each len words) of base in one launch; count <= kMaxSlots
+constexpr int kMaxSlots = 64;
+hipError_t zero_slots(uint64_t *base, int64_t len, const int32_t *slots, int count, hipStream_t s);
 hipError_t fill_u32(uint32_t *p, int64_t n, uint32_t value, hipStream_t s);
 // Zero two separate 64-bit words with one launch.
 hipError_t zero_pair(uint64_t *a, uint64_t *b, hipStream_t s);

@@ -49,6 +49,33 @@ hipError_t fill_u32(uint32_t *p, int64_t n, uint32_t value, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Zero several equal-sized slots of one array in one launch: slot slots[i]
+// covers base[slots[i] * len, (slots[i] + 1) * len).
+struct SlotList {
+    int32_t count;
+    int32_t slot[kMaxSlots];
+};
+
+__global__ __launch_bounds__(256) void zero_slots_kernel(uint64_t *__restrict__ base, int64_t len, SlotList l) {
+    const int64_t n = (int64_t)l.count * len;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const int64_t k = i / len;
+        base[(int64_t)l.slot[k] * len + (i - k * len)] = 0ull;
+    }
+}
+
+hipError_t zero_slots(uint64_t *base, int64_t len, const int32_t *slots, int count, hipStream_t s) {
+    if (count <= 0 || len <= 0) return hipSuccess;
+    if (count > kMaxSlots) return hipErrorInvalidValue;
+    SlotList l = {};
+    l.count = count;
+    for (int i = 0; i < count; ++i) l.slot[i] = slots[i];
+    hipLaunchKernelGGL(zero_slots_kernel, dim3((unsigned)fill_grid((int64_t)count * len)), dim3(256), 0, s, base, len,
+                       l);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------- selection --
 // Tile = BlockLoad -> BlockPred -> BlockScan of the match counts -> the tile's
 // output offset -> BlockShuffle into LDS (matches in input order within the

@@ -146,18 +146,22 @@ struct Server {
                 b.plan = tp.plan;
                 for (int j = 0; j < tp.plan.n_joins; ++j) b.masks[j] = tp.masks[j];
                 b.n_queries = cfg.slots_per_template;
+                int32_t zero[CRYSTAL_MAX_BATCH];
+                int n_zero = 0;
                 for (int q = 0; q < cfg.slots_per_template; ++q) {
                     Slot &sl = ss[q];
                     const bool on = sl.busy && sl.steps_left > 0;
                     if (sl.zero_pending) {
-                        if (fill_u64((uint64_t *)slot_out(t, q), n_groups(t), 0ull, stream) != hipSuccess) {
-                            fail(CRYSTAL_EHIP);
-                            return false;
-                        }
+                        zero[n_zero++] = q;
                         sl.zero_pending = false;
                     }
                     for (int i = 0; i < tp.plan.n_preds; ++i) b.queries[q].preds[i] = on ? sl.preds[i] : crystal_range{1, 0};
                     b.queries[q].out = slot_out(t, q);
+                }
+                // the outputs of newly admitted queries, cleared in one launch
+                if (zero_slots((uint64_t *)slot_out(t, 0), n_groups(t), zero, n_zero, stream) != hipSuccess) {
+                    fail(CRYSTAL_EHIP);
+                    return false;
                 }
                 b.row_begin = seg_lo;
                 b.row_end = seg_hi;
