@@ -288,3 +288,35 @@ def test_batch_with_fact_predicates(serving, nq):
         want = oracle.star(cols, STAR_GROUPS, preds=[(6, *preds[q][0]), (7, *preds[q][1]), (5, *preds[q][2])],
                            joins=star_oracle_joins(t, consts[q]), agg=oracle.AGG_SUM, agg_cols=(4, 0))
         assert np.array_equal(outs[q].cpu().numpy(), want), q
+
+
+@pytest.mark.parametrize("block,ipt", [(64, 4), (1024, 16)])
+def test_ranked_table_in_a_late_join(serving, block, ipt):
+    """Join order (1, 2, 0, 3) puts the ranked date table third, where rows
+    are sparse: it is read from the queue of sparse rows, in LDS (1024-thread
+    workgroups stage it) or in global memory (64-thread ones do not)."""
+    announce("shared late ranked join", block, ipt)
+    t, sv = serving
+    order = (1, 2, 0, 3)
+    joins = []
+    for j in order:
+        jj = dict(table=sv.tables[j], fk_col=j)
+        if j == 0:
+            jj["group"] = (32, 0, datagen.FIRST_YEAR, queries.GROUPS_PER_YEAR)
+        if j == 2:
+            jj["group"] = (32, 0, 0, 1)
+        joins.append(jj)
+    template = cx.StarQuery(sv.cols, n_groups=STAR_GROUPS, joins=joins, agg=cx.AGG_SUM, agg_cols=(4, 0))
+    assert sv.masks[0].ranked > 0
+    scan = cx.SharedScan(template, [sv.masks[j] for j in order])
+    cx.tune_set(cx.K_SHARED_SCAN, block, ipt, 0)
+    try:
+        rng = np.random.default_rng(block)
+        consts = [datagen.random_star_constants(rng) for _ in range(8)]
+        sv.build_star_masks(consts)
+        outs = zeros(STAR_GROUPS, 8)
+        cx.check_status(scan.run([[] for _ in outs], outs))
+        for q in range(8):
+            assert np.array_equal(outs[q].cpu().numpy(), star_oracle(t, consts[q])[0]), q
+    finally:
+        cx.tune_reset()
