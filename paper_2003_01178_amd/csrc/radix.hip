@@ -124,22 +124,38 @@ __global__ __launch_bounds__(kHistBlock) void radix_hist_kernel(const uint32_t *
     const int64_t i0 = ch.t0 * tile_items;
     int64_t i1 = ch.t1 * tile_items;
     if (i1 > n) i1 = n;
-    for (int64_t b = i0; b < i1; b += STEP) {
-        const uint32_t *kb = keys + b;
+    // full batches of STEP keys, the next batch's loads in flight while the
+    // current one is counted (two register buffers, so that the one receiving
+    // loads is never copied); then the partial batch
+    const int64_t nfull = i1 > i0 ? (i1 - i0) / STEP : 0;
+    auto load = [&](int64_t bi, uint32_t(&v)[kHistIpt]) {
+        const uint32_t *kb = keys + i0 + bi * STEP;
         asm volatile("" : "+s"(kb));
+#pragma unroll
+        for (int k = 0; k < kHistIpt; ++k) v[k] = __builtin_nontemporal_load(kb + k * kHistBlock + threadIdx.x);
+    };
+    auto count = [&](const uint32_t(&v)[kHistIpt]) {
+#pragma unroll
+        for (int k = 0; k < kHistIpt; ++k) atomicAdd(&h[w][digit_of(v[k], shift, mask)], 1u);
+    };
+    uint32_t va[kHistIpt], vb[kHistIpt];
+    if (nfull > 0) load(0, va);
+    for (int64_t bi = 0; bi < nfull;) {
+        if (bi + 1 < nfull) load(bi + 1, vb);
+        count(va);
+        if (++bi >= nfull) break;
+        if (bi + 1 < nfull) load(bi + 1, va);
+        count(vb);
+        ++bi;
+    }
+    const int64_t b = i0 + nfull * STEP;
+    if (b < i1) {
+        const uint32_t *kb = keys + b;
         const int64_t left = i1 - b;
-        if (left >= STEP) {
-            uint32_t v[kHistIpt];
 #pragma unroll
-            for (int k = 0; k < kHistIpt; ++k) v[k] = __builtin_nontemporal_load(kb + k * kHistBlock + threadIdx.x);
-#pragma unroll
-            for (int k = 0; k < kHistIpt; ++k) atomicAdd(&h[w][digit_of(v[k], shift, mask)], 1u);
-        } else {
-#pragma unroll
-            for (int k = 0; k < kHistIpt; ++k) {
-                const int i = k * kHistBlock + (int)threadIdx.x;
-                if (i < left) atomicAdd(&h[w][digit_of(kb[i], shift, mask)], 1u);
-            }
+        for (int k = 0; k < kHistIpt; ++k) {
+            const int i = k * kHistBlock + (int)threadIdx.x;
+            if (i < left) atomicAdd(&h[w][digit_of(kb[i], shift, mask)], 1u);
         }
     }
     __syncthreads();
