@@ -249,3 +249,20 @@ def test_qmask_build_batch_host_errors(cx):
     assert call([item(bad)]) == cx.EINVAL
     assert lib.crystal_qmask_build_batch(None, 1, ctypes.byref(status), None) == cx.EINVAL
     assert call([], n=0) == cx.OK
+
+
+def test_shared_scan_tuning_classes(cx):
+    """Grouped and scalar shared-scan templates are tuned separately; both
+    classes take the 16-byte-vector tile shapes."""
+    lib = cx.load()
+    assert cx.K_SHARED_SCAN_SCALAR == 7 and lib.crystal_tune_variants(8, None, None, 0) == 0
+    assert lib.crystal_tune_variants(cx.K_SHARED_SCAN_SCALAR, None, None, 0) == \
+        lib.crystal_tune_variants(cx.K_SHARED_SCAN, None, None, 0) > 0
+    try:
+        assert lib.crystal_tune_set(cx.K_SHARED_SCAN_SCALAR, -1, -1, 1024, 8, 0) == cx.OK
+        assert lib.crystal_tune_set(cx.K_SHARED_SCAN, -1, -1, 1024, 16, 0) == cx.OK
+        assert cx.tune_get(cx.K_SHARED_SCAN_SCALAR, 1 << 26) == (1024, 8, 0)
+        assert cx.tune_get(cx.K_SHARED_SCAN, 1 << 26) == (1024, 16, 0)
+        assert lib.crystal_tune_set(cx.K_SHARED_SCAN_SCALAR, -1, -1, 1024, 3, 0) == cx.EINVAL
+    finally:
+        cx.tune_reset()
