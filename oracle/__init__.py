@@ -14,7 +14,11 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 Parity pins: every function here is checked in ``tests/test_oracle_pins.py``
 against closed forms, the paper's worked compaction example, exact special
 cases and brute force on tiny inputs.  Only the sigmoid projection relies on
-an error bound against ``math.exp`` rather than an exact value.
+an error bound (against exponentials computed with ``decimal``) rather than
+an exact value.
+
+The C functions keep no global state, so several threads may call them at
+once (ctypes releases the GIL during each call).
 """
 from __future__ import annotations
 

@@ -18,6 +18,7 @@
  * Return codes: 0 ok, 1 bad argument, 4 duplicate dimension key,
  * 7 group index outside the dense group array.
  */
+#define _GNU_SOURCE /* qsort_r: the comparison gets the key column as an argument */
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -30,9 +31,10 @@
 
 /* ------------------------------------------------------------------------ */
 /* Selection (section 4.2, query Q3; section 3.2, query Q0).                 */
-/* SELECT y FROM R WHERE lo <= y <= hi.  The predicated loop of the paper's   */
-/* selection-scan figure: every value is copied, the cursor advances only    */
-/* when the predicate holds.  Output is in input order.  Returns the count.   */
+/* SELECT y FROM R WHERE lo <= y <= hi.  The branching loop of the paper's   */
+/* selection-scan figure: a value is copied to the cursor and the cursor     */
+/* advances only when the predicate holds.  Output is in input order.        */
+/* Returns the count.                                                        */
 /* ------------------------------------------------------------------------ */
 int64_t oracle_select(const int32_t *y, int64_t n, int32_t lo, int32_t hi,
                       int32_t *out)
@@ -88,12 +90,11 @@ typedef struct {
     const int32_t *key;
 } key_index;
 
-static const int32_t *g_sort_keys; /* qsort has no context argument */
-
-static int cmp_rows_by_key(const void *pa, const void *pb)
+static int cmp_rows_by_key(const void *pa, const void *pb, void *keys)
 {
-    int32_t ka = g_sort_keys[*(const int64_t *)pa];
-    int32_t kb = g_sort_keys[*(const int64_t *)pb];
+    const int32_t *key = (const int32_t *)keys;
+    int32_t ka = key[*(const int64_t *)pa];
+    int32_t kb = key[*(const int64_t *)pb];
     return (ka > kb) - (ka < kb);
 }
 
@@ -133,8 +134,7 @@ static int key_index_build(key_index *ix, const int32_t *key, int64_t n)
     ix->order = (int64_t *)malloc((size_t)n * sizeof(int64_t));
     if (!ix->order) return ORACLE_EINVAL;
     for (int64_t r = 0; r < n; ++r) ix->order[r] = r;
-    g_sort_keys = key;
-    qsort(ix->order, (size_t)n, sizeof(int64_t), cmp_rows_by_key);
+    qsort_r(ix->order, (size_t)n, sizeof(int64_t), cmp_rows_by_key, (void *)key);
     for (int64_t r = 1; r < n; ++r)
         if (key[ix->order[r]] == key[ix->order[r - 1]]) {
             key_index_free(ix);
@@ -360,12 +360,11 @@ int oracle_radix_partition(const uint32_t *keys, const uint32_t *vals, int64_t n
 
 /* Sort of 32-bit (key, value) pairs by unsigned key, stable (section 4.4,
  * the sort the radix passes build up to). */
-static const uint32_t *g_sort_ukeys;
-
-static int cmp_pairs(const void *pa, const void *pb)
+static int cmp_pairs(const void *pa, const void *pb, void *keys)
 {
+    const uint32_t *ukey = (const uint32_t *)keys;
     int64_t a = *(const int64_t *)pa, b = *(const int64_t *)pb;
-    uint32_t ka = g_sort_ukeys[a], kb = g_sort_ukeys[b];
+    uint32_t ka = ukey[a], kb = ukey[b];
     if (ka != kb) return ka < kb ? -1 : 1;
     return (a > b) - (a < b); /* equal keys keep input order */
 }
@@ -377,8 +376,7 @@ int oracle_sort_pairs(const uint32_t *keys, const uint32_t *vals, int64_t n, uin
     int64_t *idx = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
     if (!idx) return ORACLE_EINVAL;
     for (int64_t i = 0; i < n; ++i) idx[i] = i;
-    g_sort_ukeys = keys;
-    qsort(idx, (size_t)n, sizeof(int64_t), cmp_pairs);
+    qsort_r(idx, (size_t)n, sizeof(int64_t), cmp_pairs, (void *)keys);
     for (int64_t i = 0; i < n; ++i) {
         out_keys[i] = keys[idx[i]];
         if (vals) out_vals[i] = vals[idx[i]];
