@@ -11,7 +11,14 @@ Prints one JSON line.  ``roofline`` refers to the fused star kernel: its
 algorithmic bytes (fact-column cache lines the selective loads must touch, at
 the HBM fetch granularity) over its average duration measured with HIP events
 on the launch stream.  ``cpu_baseline`` is the plain CPU oracle timed on the
-host (single thread) over repeated passes of the same workload.
+host over full passes of the same workload, with the rows split over the
+host threads (and on one thread beside it), next to the host's streaming
+read bandwidth.  ``serving`` is the served mixed workload measured in the
+same run: a 600M-row fact table, Poisson arrivals at 50..2,000 queries/s of
+star-join and Q1.1-shaped queries answered by the continuous-batching
+server, p50/p99 latency per rate, a burst, one launch per query beside it,
+sampled answers checked against their single launches and the oracle, and
+the roofline of one 16-query shared-scan pass per template.
 """
 from __future__ import annotations
 
@@ -37,9 +44,10 @@ def parse():
     p.add_argument("--steps", type=int, default=200)
     p.add_argument("--warmup", type=int, default=20)
     p.add_argument("--workload", default="star", choices=["star", "q11", "select", "project", "join", "copy", "serve",
-                                                              "partition", "sort", "groupby"])
+                                                              "pass", "partition", "sort", "groupby"])
     p.add_argument("--rows", type=int, default=0, help="override the fact/column length")
     p.add_argument("--sigma", type=float, default=0.5, help="select selectivity")
+    p.add_argument("--sigma-sweep", action="store_true", help="select: also time sigma = 0, 0.1, ..., 1")
     p.add_argument("--dim", type=int, default=1 << 20, help="join build size D")
     p.add_argument("--kind", default="linear", choices=["linear", "direct"])
     p.add_argument("--bits", type=int, default=8, help="partition: radix bits")
@@ -52,9 +60,13 @@ def parse():
                    help="star: store the two dense-phase foreign keys as 16-bit offsets (compressed columns)")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
     p.add_argument("--tune", default="", help="kernel block,ipt,grid_per_cu override, e.g. 256,16,0")
-    p.add_argument("--rates", default="500,1000,2000,4000", help="serve: Poisson arrival rates (q/s)")
-    p.add_argument("--seconds", type=float, default=3.0, help="serve: arrival window per rate")
+    p.add_argument("--rates", default="50,200,500,1000,2000", help="serve: Poisson arrival rates (q/s)")
+    p.add_argument("--seconds", type=float, default=0.0,
+                   help="serve: arrival window per rate (0: 5,000 arrivals, between 5 and 10 s)")
     p.add_argument("--segments", type=int, default=8, help="serve: clock segments of the fact table")
+    p.add_argument("--serve-rows", type=int, default=0, help="serve: fact rows (default 600M)")
+    p.add_argument("--serve-pass-reps", type=int, default=20, help="serve: timed shared-scan passes per template")
+    p.add_argument("--no-serve", action="store_true", help="star: skip the served-mix measurement")
     return p.parse_args()
 
 
@@ -174,8 +186,24 @@ def shared_scan_roofline(torch, cx, datagen, queries, sv, seg, rng, reps):
     sv.build_q11_masks(q11_c)
     torch.cuda.synchronize()
     d = sv.s.dims
-    star_steps = [(sv.cols[j], sv.masks[j].dense(), d[j]["key_min"]) for j in queries.DEFAULT_JOIN_ORDER]
-    q11_steps = [(sv.cols[dm["fk_col"]], dm["mask"].dense(), dm["key_min"]) for dm in sv.q11_domains]
+
+    def mask_table(keys, filt, kmin, kmax, ranges):
+        # per key of the span: bit q set when the row with that key passes query q (the
+        # definition of a query-mask entry, computed here for the byte count only)
+        table = torch.zeros(kmax - kmin + 1, dtype=torch.int32, device="cuda")
+        m = torch.zeros_like(keys)
+        for q, (lo, hi) in enumerate(ranges):
+            m |= ((filt >= lo) & (filt <= hi)).to(torch.int32) << q
+        table[(keys - kmin).long()] = m
+        return table
+
+    star_steps = [(sv.cols[j], mask_table(d[j]["key"], d[j]["filter"], d[j]["key_min"], d[j]["key_max"],
+                                          [(c[j], c[j]) for c in star_c]), d[j]["key_min"])
+                  for j in queries.DEFAULT_JOIN_ORDER]
+    q11_ranges = [sv.q11_preds(*c) for c in q11_c]
+    q11_steps = [(sv.cols[dm["fk_col"]], mask_table(dm["key"], dm["filter"], dm["key_min"], dm["key_max"],
+                                                    [r[i] for r in q11_ranges]), dm["key_min"])
+                 for i, dm in enumerate(sv.q11_domains)]
     b_star, s_star = shared_pass_bytes(torch, star_steps, [4], [0, 2], seg)
     # the Q1.1 measures: price, and discount, which its second step has read already
     b_q11, s_q11 = shared_pass_bytes(torch, q11_steps, [8], [], seg)
@@ -198,16 +226,76 @@ def shared_scan_roofline(torch, cx, datagen, queries, sv, seg, rng, reps):
                                       "q11": {"ms": res["q11"], "bytes": b_q11, "survivors": s_q11}})
 
 
-def serve(args, torch, cx, datagen, queries, roof):
-    """Served mixed workload: Poisson arrivals of star-template and Q1.1-template
-    queries with seeded constants, answered by the continuous-batching server
-    over shared-scan passes; compared with one launch per query."""
-    n = args.rows or 600_000_000
+def cpu_threads():
+    """Host threads to use: the CPUs this process may run on, at most 16
+    (one GPU's share of the host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def host_read_gbs(threads, nbytes=1 << 31, reps=3):
+    """Streaming read bandwidth of the host: a max-reduction of a 2 GiB
+    int32 array split over `threads` threads (numpy releases the GIL)."""
+    from concurrent.futures import ThreadPoolExecutor
+    x = np.ones(nbytes // 4, dtype=np.int32)
+    bounds = [(x.size * i // threads, x.size * (i + 1) // threads) for i in range(threads)]
+    best = 0.0
+    with ThreadPoolExecutor(threads) as ex:
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            list(ex.map(lambda ab: x[ab[0]:ab[1]].max(), bounds))
+            best = max(best, x.nbytes / (time.perf_counter() - t0) / 1e9)
+    return best
+
+
+def oracle_star_rows(oracle, cols, n_groups, threads, **kw):
+    """The oracle's star query over contiguous row ranges on several threads
+    (its C call releases the GIL), the partial group arrays added modulo
+    2^64: the answer over all rows."""
+    from concurrent.futures import ThreadPoolExecutor
+    n = len(cols[0])
+    bounds = [n * i // threads for i in range(threads + 1)]
+    with ThreadPoolExecutor(threads) as ex:
+        parts = list(ex.map(lambda ab: oracle.star([c[ab[0]:ab[1]] for c in cols], n_groups, **kw),
+                            zip(bounds[:-1], bounds[1:])))
+    total = np.zeros(int(n_groups), dtype=np.uint64)
+    for q in parts:
+        total += q.view(np.uint64)
+    return total.view(np.int64)
+
+
+def star_oracle_joins(t, consts, datagen, queries, order=(1, 2, 3, 0)):
+    """Oracle join list of the star query (dimension j keeps filter ==
+    consts[j]; group = (year - 1992) * 1000 + dim3.group), in `order`: the
+    result does not depend on it, and the dense dimensions first make the
+    oracle faster."""
+    joins = []
+    for j in order:
+        d = t.dims[j]
+        jj = dict(fk_col=j, key=d.key, filter=d.filter, flo=consts[j], fhi=consts[j])
+        if j == 0:
+            jj.update(group=d.year, base=datagen.FIRST_YEAR, stride=queries.GROUPS_PER_YEAR)
+        if j == 2:
+            jj.update(group=d.group, base=0, stride=1)
+        joins.append(jj)
+    return joins
+
+
+def serve(args, torch, cx, datagen, queries):
+    """Served mixed workload (600M fact rows, the star schema plus the Q1.1
+    columns): Poisson arrivals of star-template and Q1.1-template queries
+    with seeded constants, answered by the continuous-batching server over
+    shared-scan passes, beside one launch per query.  Returns the `serving`
+    object and the shared-scan pass roofline."""
+    import oracle
+    n = args.serve_rows or 600_000_000
     t0 = time.time()
     t = datagen.star_tables(n=n, workload=4, with_q11_columns=True)
-    print(f"# generated {n} fact rows x 9 columns in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    print(f"# serve: generated {n} fact rows x 9 columns in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
     sv = queries.ServingTemplates(queries.StarSchema(t))
-    del t
     torch.cuda.synchronize()
     rng = np.random.default_rng(2003)
 
@@ -216,25 +304,33 @@ def serve(args, torch, cx, datagen, queries, roof):
             return 0, datagen.random_star_constants(rng)
         return 1, datagen.random_q11_constants(rng)
 
-    # one launch per query (filtered builds + fused kernel, or the Q1.1 kernel)
-    single = []
-    t0 = time.perf_counter()
+    def single(tp, c):
+        return sv.single_star(c) if tp == 0 else sv.single_q11(*c)
+
+    # one launch per query, back to back: each query's own latency (filtered
+    # builds + fused kernel, or the Q1.1 kernel, to a synchronised result)
+    for k in range(4):
+        single(*draw(k))
+    torch.cuda.synchronize()
+    single_lat = []
     for k in range(64):
         tp, c = draw(k)
-        r = sv.single_star(c) if tp == 0 else sv.single_q11(*c)
-        single.append((tp, c, r))
-    torch.cuda.synchronize()
-    single_qps = 64 / (time.perf_counter() - t0)
+        q0 = time.perf_counter()
+        single(tp, c)
+        torch.cuda.synchronize()
+        single_lat.append(time.perf_counter() - q0)
+    single_lat = np.array(single_lat) * 1e3
+    single_qps = len(single_lat) / (single_lat.sum() / 1e3)
     seg = (n // args.segments + 3) // 4 * 4
-    order = queries.DEFAULT_JOIN_ORDER
     srv = cx.Server(sv.server_templates(), slots=16, segment_rows=seg, max_queue=1 << 16, inflight=2)
     per_rate = []
-    checks = mismatches = 0
+    answers = []            # (template, constants, served answer), sampled for the checks
     try:
         for rate in [float(x) for x in args.rates.split(",")]:
-            arrivals = np.cumsum(rng.exponential(1.0 / rate, size=int(rate * args.seconds * 1.2) + 8))
-            arrivals = arrivals[arrivals < args.seconds]
-            pending, lat, submitted = {}, [], 0
+            window = args.seconds if args.seconds > 0 else min(10.0, max(5.0, 5000.0 / rate))
+            arrivals = np.cumsum(rng.exponential(1.0 / rate, size=int(rate * window * 1.3) + 16))
+            arrivals = arrivals[arrivals < window]
+            pending, lat, sampled = {}, [], 0
             st0 = srv.stats()
             start = time.perf_counter()
             i = 0
@@ -242,61 +338,89 @@ def serve(args, torch, cx, datagen, queries, roof):
                 now = time.perf_counter() - start
                 while i < len(arrivals) and arrivals[i] <= now:
                     tp, c = draw(i)
-                    if tp == 0:
-                        tk = srv.submit(0, filters=[(c[j], c[j]) for j in order])
-                    else:
-                        tk = srv.submit(1, **sv.q11_request(*c))
+                    tk = srv.submit(0, **sv.star_request(c)) if tp == 0 else srv.submit(1, **sv.q11_request(*c))
                     if tk is not None:
                         pending[tk] = (tp, c)
-                        submitted += 1
                     i += 1
                 for tk in list(pending):
-                    tp, c = pending[tk]
-                    done, out, ns = srv.poll(tk, tp)
+                    done, out, ns = srv.poll(tk)
                     if done:
                         lat.append(ns / 1e6)
-                        del pending[tk]
-                        if checks < 200 and len(lat) % 5 == 1:
-                            want = sv.single_star(c).cpu().numpy() if tp == 0 else np.array(
-                                [int(sv.single_q11(*c).item())])
-                            checks += 1
-                            mismatches += int(not np.array_equal(out, want))
+                        tp, c = pending.pop(tk)
+                        if sampled < 40 and len(lat) % 5 == 1:      # 40 answers per rate
+                            answers.append((tp, c, out))
+                            sampled += 1
                 time.sleep(0.0002)
             wall = time.perf_counter() - start
             st1 = srv.stats()
             steps = st1["steps"] - st0["steps"]
             lat = np.array(lat)
-            per_rate.append({"offered_qps": rate, "served_qps": len(lat) / wall, "queries": int(len(lat)),
+            per_rate.append({"offered_qps": rate, "window_s": window, "queries": int(lat.size),
+                             "served_qps": lat.size / wall,
                              "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
                              "clock_steps": int(steps),
                              "mean_batch": (st1["busy_slot_steps"] - st0["busy_slot_steps"]) / max(1, steps)})
-            print(f"# rate {rate}: {per_rate[-1]}", file=sys.stderr, flush=True)
-        # saturation: a burst of 256 queries at once
-        tks = []
+            print(f"# serve: rate {rate}: {per_rate[-1]}", file=sys.stderr, flush=True)
+        # saturation: a burst of 256 queries submitted at once
+        tks = {}
         start = time.perf_counter()
         for k in range(256):
             tp, c = draw(k)
-            tk = srv.submit(0, filters=[(c[j], c[j]) for j in order]) if tp == 0 else srv.submit(
-                1, **sv.q11_request(*c))
-            tks.append((tk, tp))
-        left = dict(tks)
-        while left:
-            for tk in list(left):
-                if srv.poll(tk, left[tk])[0]:
-                    del left[tk]
+            tk = srv.submit(0, **sv.star_request(c)) if tp == 0 else srv.submit(1, **sv.q11_request(*c))
+            tks[tk] = (tp, c)
+        burst_lat = []
+        while tks:
+            for tk in list(tks):
+                done, out, ns = srv.poll(tk)
+                if done:
+                    burst_lat.append(ns / 1e6)
+                    tks.pop(tk)
             time.sleep(0.0002)
         burst_qps = 256 / (time.perf_counter() - start)
     finally:
         srv.close()
-    best = max(per_rate, key=lambda r: r["served_qps"])
-    roof.update(shared_scan_roofline(torch, cx, datagen, queries, sv, seg, rng, args.steps))
-    return dict(metric="served queries/s + p99 latency (shared-scan continuous batching)",
-                value=burst_qps, unit="queries/s", ms_per_step=1e3 / burst_qps, dtype="int32",
-                config={"workload": f"served mix: fact {n} rows x 9 int32 columns, 50/50 star-join / Q1.1 "
-                                    "templates with seeded constants, Poisson arrivals",
-                        "segments": args.segments, "slots_per_template": 16},
-                serving={"rates": per_rate, "burst_256_qps": burst_qps, "single_launch_qps": single_qps,
-                         "checked_vs_single_launch": checks, "mismatches": mismatches})
+    print(f"# serve: burst {burst_qps:.0f} q/s; checking answers", file=sys.stderr, flush=True)
+    # every sampled served answer against its own single launch
+    mism_single = 0
+    for tp, c, out in answers:
+        want = single(tp, c)
+        mism_single += int(not np.array_equal(out, want.cpu().numpy().reshape(-1)))
+    # twenty against the oracle (ten per template), over all 600M rows
+    threads = cpu_threads()
+    cols = [*t.fk, t.m1, t.m2]
+    q11_cols = [t.fk[0], t.extra["discount"], t.extra["quantity"], t.extra["price"]]
+    mism_oracle = n_oracle = 0
+    o0 = time.perf_counter()
+    for want_tp in (0, 1):
+        for tp, c, out in [a for a in answers if a[0] == want_tp][:10]:
+            if tp == 0:
+                want = oracle_star_rows(oracle, cols, queries.STAR_GROUPS, threads, agg=oracle.AGG_SUM,
+                                        agg_cols=(4, 0), joins=star_oracle_joins(t, c, datagen, queries))
+            else:
+                year, d, qm = c
+                lo, hi = datagen.q11_year_range(year)
+                want = oracle_star_rows(oracle, q11_cols, 1, threads, agg=oracle.AGG_SUM_PRODUCT, agg_cols=(3, 1),
+                                        preds=[(0, lo, hi), (1, d, d + 2), (2, datagen.INT32_MIN, qm)])
+            n_oracle += 1
+            mism_oracle += int(not np.array_equal(out, want))
+    print(f"# serve: {n_oracle} oracle checks in {time.perf_counter() - o0:.1f}s", file=sys.stderr, flush=True)
+    pass_roof = shared_scan_roofline(torch, cx, datagen, queries, sv, seg, rng, args.serve_pass_reps)
+    pass_roof["frac"] = pass_roof["achieved"] / HBM_PEAK_GBS
+    del sv
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return {"workload": f"served mix: fact {n} rows x 9 int32 columns resident in HBM, 50/50 star-join / "
+                        "Q1.1 templates with seeded constants, Poisson arrivals",
+            "fact_rows": n, "segments": args.segments, "slots_per_template": 16,
+            "rates": per_rate, "burst_256": {"qps": burst_qps, "p50_ms": float(np.percentile(burst_lat, 50)),
+                                             "p99_ms": float(np.percentile(burst_lat, 99))},
+            "single_launch": {"qps": single_qps, "p50_ms": float(np.percentile(single_lat, 50)),
+                              "p99_ms": float(np.percentile(single_lat, 99)), "queries": int(single_lat.size),
+                              "note": "one query at a time, back to back: its own latency, no queueing; "
+                                      "offered rates above this q/s would queue without bound"},
+            "checked_vs_single_launch": len(answers), "mismatches_vs_single_launch": mism_single,
+            "checked_vs_oracle": n_oracle, "mismatches_vs_oracle": mism_oracle,
+            "pass_roofline": pass_roof}
 
 
 def main():
@@ -410,28 +534,41 @@ def main():
         if not args.no_cpu_baseline:
             import oracle
             from_cols = [*t.fk, t.m1, t.m2]
-            joins = []
-            for j, d in enumerate(t.dims):
-                jj = dict(fk_col=j, key=d.key, filter=d.filter, flo=t.consts[j], fhi=t.consts[j])
-                if j == 0:
-                    jj.update(group=d.year, base=datagen.FIRST_YEAR, stride=queries.GROUPS_PER_YEAR)
-                if j == 2:
-                    jj.update(group=d.group, base=0, stride=1)
-                joins.append(jj)
+            # the oracle runs the GPU plan's join order (any order gives the same result)
+            joins = star_oracle_joins(t, t.consts, datagen, queries, order=order)
+            budget = args.cpu_seconds / 2
             passes, c0 = 0, time.perf_counter()
             while True:
-                want = oracle.star(from_cols, queries.STAR_GROUPS, joins=joins, agg=oracle.AGG_SUM,
-                                   agg_cols=(4, 0))
+                want = oracle.star(from_cols, queries.STAR_GROUPS, joins=joins, agg=oracle.AGG_SUM, agg_cols=(4, 0))
                 passes += 1
-                if time.perf_counter() - c0 >= args.cpu_seconds or passes >= 20:
+                if time.perf_counter() - c0 >= budget or passes >= 20:
                     break
-            cdt = time.perf_counter() - c0
-            cpu = {"value": n * passes / cdt, "unit": "rows/s", "cores": 1, "kind": "oracle",
-                   "sample": f"{passes} full pass(es) over the {n}-row fact table, single thread",
-                   "host": model}
-            result["exact_vs_oracle"] = bool(np.array_equal(gpu_out, want))
+            one = n * passes / (time.perf_counter() - c0)
+            threads = cpu_threads()
+            apasses, c0 = 0, time.perf_counter()
+            while True:
+                want_all = oracle_star_rows(oracle, from_cols, queries.STAR_GROUPS, threads, joins=joins,
+                                            agg=oracle.AGG_SUM, agg_cols=(4, 0))
+                apasses += 1
+                if time.perf_counter() - c0 >= budget or apasses >= 50:
+                    break
+            allc = n * apasses / (time.perf_counter() - c0)
+            read_gbs = host_read_gbs(threads)
+            cpu = {"value": allc, "unit": "rows/s", "cores": threads, "kind": "oracle",
+                   "sample": f"{apasses} full pass(es) over the {n}-row fact table, rows split over {threads} "
+                             f"threads; single thread: {passes} pass(es)",
+                   "single_thread_value": one, "host": model, "host_logical_cpus": ncpu,
+                   "host_read_GBps": read_gbs,
+                   "gpu_over_cpu_bandwidth": HBM_PEAK_GBS / read_gbs,
+                   "paper_bandwidth_ratio": "16.2x (880 GB/s V100 over 54 GB/s i7-6900)"}
+            result["exact_vs_oracle"] = bool(np.array_equal(gpu_out, want) and np.array_equal(gpu_out, want_all))
         result["paper_context"] = ("SSB q2.1 (3 joins, 120M rows) on V100: 3.86 ms = 3.1e10 rows/s; "
                                    "GPU/CPU 25x on SSB (different hardware and workload)")
+        if not args.no_serve:
+            del s, plan, t
+            torch.cuda.synchronize()
+            torch.cuda.empty_cache()
+            result["serving"] = serve(args, torch, cx, datagen, queries)
 
     elif args.workload == "q11":
         n = args.rows or 6_000_000
@@ -483,10 +620,28 @@ def main():
         c = int(cnt.item())
         kern_ms = timer.mean_ms()
         b = 4 * n + 4 * c
+        sweep = []
+        if args.sigma_sweep:
+            for k in range(11):
+                slo, shi = datagen.select_threshold_range(k / 10)
+                for _ in range(3):
+                    cx.select(x, slo, shi, out=outb, count=cnt)
+                st = Timer(torch)
+                for _ in range(K):
+                    st.run(lambda: cx.select(x, slo, shi, out=outb, count=cnt))
+                torch.cuda.synchronize()
+                sc = int(cnt.item())
+                sms = st.mean_ms()
+                sweep.append({"sigma": k / 10, "matches": sc, "kernel_ms": sms,
+                              "GBps": (4 * n + 4 * sc) / (sms * 1e-3) / 1e9,
+                              "frac": (4 * n + 4 * sc) / (sms * 1e-3) / 1e9 / HBM_PEAK_GBS})
+                print(f"# sigma {k / 10}: {sweep[-1]}", file=sys.stderr, flush=True)
         result.update(metric="rows/s (selection, compacted output)", value=n * K / elapsed, unit="rows/s",
                       ms_per_step=elapsed / K * 1e3, dtype="int32",
                       config={"workload": f"select y < v on 2^29 int32, sigma={args.sigma}", "rows": n,
                               "matches": c, "tile": list(cx.tune_get(cx.K_SELECT, n))})
+        if sweep:
+            result["sigma_sweep"] = sweep
         roof.update(kernel="crystal::select_kernel", achieved=b / (kern_ms * 1e-3) / 1e9, algorithmic_bytes=b,
                     kernel_ms=kern_ms)
 
@@ -571,8 +726,31 @@ def main():
                               "rows": n})
         roof.update(kernel="copy", achieved=b / (kern_ms * 1e-3) / 1e9, algorithmic_bytes=b, kernel_ms=kern_ms)
 
+    elif args.workload == "pass":
+        # one 16-query shared-scan pass per template over one clock segment of
+        # the served table, timed alone (for kernel traces and counters)
+        n = args.serve_rows or 600_000_000
+        t = datagen.star_tables(n=n, workload=4, with_q11_columns=True)
+        sv = queries.ServingTemplates(queries.StarSchema(t))
+        del t
+        seg = (n // args.segments + 3) // 4 * 4
+        pr = shared_scan_roofline(torch, cx, datagen, queries, sv, seg, np.random.default_rng(2003), K)
+        roof.update({k: pr[k] for k in ("kernel", "achieved", "algorithmic_bytes", "kernel_ms", "passes")})
+        result.update(metric="rows/s per shared-scan pass pair (16 queries per template)",
+                      value=seg / (pr["kernel_ms"] * 1e-3), unit="rows/s", ms_per_step=pr["kernel_ms"],
+                      dtype="int32", config={"workload": f"one 16-query pass per template over {seg} of {n} "
+                                                         "served fact rows", "rows": seg})
+
     elif args.workload == "serve":
-        result.update(serve(args, torch, cx, datagen, queries, roof))
+        serving = serve(args, torch, cx, datagen, queries)
+        pr = serving["pass_roofline"]
+        roof.update({k: pr[k] for k in ("kernel", "achieved", "algorithmic_bytes", "kernel_ms", "passes")})
+        b = serving["burst_256"]["qps"]
+        result.update(metric="served queries/s + p99 latency (shared-scan continuous batching)", value=b,
+                      unit="queries/s", ms_per_step=1e3 / b, dtype="int32",
+                      config={"workload": serving["workload"], "segments": args.segments,
+                              "slots_per_template": 16},
+                      serving=serving)
 
     elif args.workload == "groupby":
         # dense group-by SUM(v) GROUP BY g: 2^28 rows into 7,000 groups (the star query's group array)

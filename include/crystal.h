@@ -44,8 +44,9 @@ typedef enum crystal_status {
     CRYSTAL_EDUPKEY = 4,  /* duplicate build key (device status)                        */
     CRYSTAL_EHIP = 5,     /* HIP runtime or launch error                                */
     CRYSTAL_EBUSY = 6,    /* shared-scan batch or server has no free slot               */
-    CRYSTAL_ERANGE = 7    /* key outside a direct table, or group index outside the
+    CRYSTAL_ERANGE = 7,   /* key outside a direct table, or group index outside the
                              dense group array (device status); the row is skipped     */
+    CRYSTAL_ETIMEDOUT = 8 /* served query dropped at its deadline                       */
 } crystal_status;
 
 /* Inclusive int32 range lo <= x <= hi.  lo > hi is the empty range. */
@@ -58,7 +59,7 @@ typedef struct crystal_range {
 const char *crystal_status_string(int32_t status);
 
 /* ABI version of this header (incremented on any layout change). */
-#define CRYSTAL_ABI_VERSION 6
+#define CRYSTAL_ABI_VERSION 7
 int32_t crystal_abi_version(void);
 
 /* sizeof of the ABI structs as compiled into the library, so a binding can
@@ -441,7 +442,7 @@ typedef struct crystal_server_config {
 } crystal_server_config;
 
 typedef struct crystal_server_stats {
-    int64_t admitted, completed, rejected, queued, steps, busy_slot_steps, n_segments;
+    int64_t admitted, completed, rejected, queued, steps, busy_slot_steps, n_segments, cancelled, timed_out;
 } crystal_server_stats;
 
 typedef struct crystal_server crystal_server;
@@ -451,14 +452,33 @@ size_t crystal_server_workspace_bytes(const crystal_server_config *cfg);
 crystal_status crystal_server_create(const crystal_server_config *cfg, crystal_server **out);
 /* Queue one query of template_id with its constants: preds[i] for the
  * template's fact predicates, dim_filters[j] for its joins' dimension filter
- * columns (host arrays).  Returns a ticket. */
+ * columns (host arrays).  Returns a ticket.  deadline_ns > 0: a query not
+ * complete that many nanoseconds after submission is dropped (from the
+ * queue, or from its slot if its last segment has not been issued yet) and
+ * polls as CRYSTAL_ETIMEDOUT; 0: no deadline. */
 crystal_status crystal_server_submit(crystal_server *s, int32_t template_id, const crystal_range *preds,
-                                     const crystal_range *dim_filters, int64_t *ticket);
+                                     const crystal_range *dim_filters, int64_t deadline_ns, int64_t *ticket);
+/* Withdraw a query: a queued one leaves its queue, a running one frees its
+ * slot at the next clock step (unless its last segment is already on the
+ * GPU; the slot is then freed when that step completes), a finished one's
+ * result is discarded.  The ticket is released: polling it returns
+ * CRYSTAL_EINVAL.  Unknown ticket: CRYSTAL_EINVAL. */
+crystal_status crystal_server_cancel(crystal_server *s, int64_t ticket);
 /* *done = 1 once the query has finished; then its n_groups int64 result is
  * copied into `result` (host, may be NULL), *latency_ns is the time from
- * submit to completion, and the ticket is released. */
-crystal_status crystal_server_poll(crystal_server *s, int64_t ticket, int64_t *result, int32_t *done,
-                                   int64_t *latency_ns);
+ * submit to completion, and the ticket is released.  A query dropped at its
+ * deadline returns CRYSTAL_ETIMEDOUT with *done = 1 (no result; the ticket
+ * is released).  result_capacity: the
+ * number of int64 values `result` holds; less than the n_groups of the
+ * ticket's template returns CRYSTAL_EINVAL and copies nothing.
+ * Device errors: the kernels' status word is copied back with every step
+ * that completes a query and checked before that step's results are
+ * released; a nonzero code (CRYSTAL_ERANGE for a dimension key outside its
+ * mask table or a group index outside the group array, CRYSTAL_EFULL for a
+ * full ranked table) stops the server, and this call, crystal_server_submit
+ * and crystal_server_get_stats return that code from then on. */
+crystal_status crystal_server_poll(crystal_server *s, int64_t ticket, int64_t *result, int64_t result_capacity,
+                                   int32_t *done, int64_t *latency_ns);
 crystal_status crystal_server_get_stats(crystal_server *s, crystal_server_stats *out);
 /* Stops the thread after the work on the GPU has drained; frees the server. */
 crystal_status crystal_server_destroy(crystal_server *s);

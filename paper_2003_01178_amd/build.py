@@ -3,6 +3,12 @@
 Each ``csrc/*.hip`` translation unit is compiled to an object in ``_build/``
 (in parallel), then the objects are linked into ``libcrystal.so`` next to this
 file.  Usage: ``python -m paper_2003_01178_amd.build``.
+
+``build_sanitized(out_dir)`` builds a checking variant for host-side tests:
+the host code with AddressSanitizer and UndefinedBehaviorSanitizer (device
+code uninstrumented and mostly unoptimised, so it compiles quickly; it is
+never run by those tests).  Load it with the clang sanitizer runtime preloaded
+(``sanitizer_runtime()``).
 """
 from __future__ import annotations
 
@@ -41,6 +47,51 @@ def _compile(src: str) -> str:
         if lines:
             sys.stderr.write("\n".join(lines[-40:]) + "\n")
     return obj
+
+
+SAN_FLAGS = [
+    f"--offload-arch={ARCH}", "-O1", "-g", "-std=c++17", "-fPIC",
+    "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+    "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer",
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+]
+
+
+def sanitizer_runtime() -> str:
+    """Path of the clang AddressSanitizer runtime the sanitized library needs."""
+    llvm = os.path.join(os.path.dirname(os.path.dirname(os.path.realpath(HIPCC))), "llvm")
+    hits = sorted(glob.glob(os.path.join(llvm, "lib", "clang", "*", "lib", "linux", "libclang_rt.asan-x86_64.so")))
+    if not hits:
+        hits = sorted(glob.glob("/opt/rocm/llvm/lib/clang/*/lib/linux/libclang_rt.asan-x86_64.so"))
+    if not hits:
+        raise FileNotFoundError("clang AddressSanitizer runtime not found")
+    return hits[-1]
+
+
+def build_sanitized(out_dir: str, jobs: int | None = None) -> str:
+    os.makedirs(out_dir, exist_ok=True)
+    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+
+    def one(src):
+        obj = os.path.join(out_dir, os.path.basename(src).replace(".hip", ".o"))
+        # device code unoptimised where it compiles that way (the radix kernels pin
+        # values to scalar registers, which needs the optimiser to prove them uniform)
+        dev_opt = [] if os.path.basename(src) == "radix.hip" else ["-Xarch_device", "-O0"]
+        r = subprocess.run([HIPCC, *SAN_FLAGS, *dev_opt, "-c", src, "-o", obj], capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"hipcc failed on {src}:\n{r.stderr[-6000:]}")
+        return obj
+
+    with ThreadPoolExecutor(jobs or min(len(srcs), max(1, os.cpu_count() or 4))) as ex:
+        objs = list(ex.map(one, srcs))
+    lib = os.path.join(out_dir, "libcrystal_san.so")
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-Xarch_host", "-fsanitize=address",
+           "-Xarch_host", "-fsanitize=undefined", "-shared-libsan", "-o", lib, *objs]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed:\n{r.stderr[-4000:]}")
+    return lib
 
 
 def build(jobs: int | None = None) -> str:

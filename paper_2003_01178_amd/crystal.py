@@ -17,7 +17,7 @@ DEFAULT_LIB = os.path.join(_HERE, "libcrystal.so")
 # CRYSTAL_LIB selects another build of the same library (e.g. a tuning experiment)
 LIB_PATH = os.environ.get("CRYSTAL_LIB", DEFAULT_LIB)
 
-OK, EINVAL, ESCRATCH, EFULL, EDUPKEY, EHIP, EBUSY, ERANGE = range(8)
+OK, EINVAL, ESCRATCH, EFULL, EDUPKEY, EHIP, EBUSY, ERANGE, ETIMEDOUT = range(9)
 HT_LINEAR, HT_DIRECT = 0, 1
 AGG_SUM, AGG_SUM_PRODUCT, AGG_SUM_DIFF, AGG_COUNT = 0, 1, 2, 3
 K_SELECT, K_PROJECT, K_HT_PROBE, K_GROUPBY, K_STAR, K_SHARED_SCAN, K_RADIX, K_SHARED_SCAN_SCALAR = range(8)
@@ -104,7 +104,7 @@ class ServerConfigC(ctypes.Structure):
 
 class ServerStatsC(ctypes.Structure):
     _fields_ = [(k, c_i64) for k in ("admitted", "completed", "rejected", "queued", "steps", "busy_slot_steps",
-                                      "n_segments")]
+                                      "n_segments", "cancelled", "timed_out")]
 
 
 class CrystalError(RuntimeError):
@@ -145,8 +145,9 @@ def _declare(lib):
         "crystal_run_shared_scan": (c_i32, [P(BatchC), c_vp, c_vp]),
         "crystal_server_workspace_bytes": (ctypes.c_size_t, [P(ServerConfigC)]),
         "crystal_server_create": (c_i32, [P(ServerConfigC), P(c_vp)]),
-        "crystal_server_submit": (c_i32, [c_vp, c_i32, P(Range), P(Range), P(c_i64)]),
-        "crystal_server_poll": (c_i32, [c_vp, c_i64, c_vp, P(c_i32), P(c_i64)]),
+        "crystal_server_submit": (c_i32, [c_vp, c_i32, P(Range), P(Range), c_i64, P(c_i64)]),
+        "crystal_server_cancel": (c_i32, [c_vp, c_i64]),
+        "crystal_server_poll": (c_i32, [c_vp, c_i64, c_vp, c_i64, P(c_i32), P(c_i64)]),
         "crystal_server_get_stats": (c_i32, [c_vp, P(ServerStatsC)]),
         "crystal_server_destroy": (c_i32, [c_vp]),
         "crystal_graph_begin": (c_i32, [c_vp]),
@@ -493,26 +494,6 @@ class QueryMask:
     def ranked(self):
         return int(self.c.ranked)
 
-    def dense(self):
-        """The table as one int32 entry per key of the span (device)."""
-        span = int(self.c.span)
-        if not self.c.ranked:
-            return self.mem[: ((span + 1) // 2) * 4].view(torch.int16)[:span].to(torch.int32) & 0xFFFF
-        n_dir = (span + 31) // 32 + 1
-        words = self.mem[: 8 * n_dir].view(torch.int32).view(-1, 2).to(torch.int64) & 0xFFFFFFFF
-        ent = self.mem[8 * n_dir: 8 * n_dir + 2 * (self.c.ranked + 1)].view(torch.int16).to(torch.int32) & 0xFFFF
-        off = torch.arange(span, device=self.mem.device, dtype=torch.int64)
-        bits, before = words[off >> 5, 0], words[off >> 5, 1]
-        bit = off & 31
-        present = ((bits >> bit) & 1) == 1
-        below = bits & ((torch.ones_like(bit) << bit) - 1)
-        # population count of the bits below each key
-        cnt = torch.zeros_like(below)
-        for b in range(32):
-            cnt += (below >> b) & 1
-        idx = torch.where(present, before + cnt, torch.full_like(cnt, int(self.c.ranked)))
-        return ent[idx]
-
     def build(self, keys, filter_col, ranges, status=None, stream=None):
         """Bit q of key k: the dimension row with key k has filter_col in ranges[q]."""
         lib = load()
@@ -650,6 +631,7 @@ class Server:
         cfg.fake_executor = 1 if fake_step_ns else 0
         cfg.fake_step_ns = int(fake_step_ns)
         self.keep = []
+        self.ticket_template = {}
         self.n_groups, self.n_preds, self.n_joins = [], [], []
         for t, tp in enumerate(templates):
             plan = tp["plan"]
@@ -680,27 +662,44 @@ class Server:
         _check(lib.crystal_server_create(ctypes.byref(cfg), ctypes.byref(h)), "crystal_server_create")
         self.h = h
 
-    def submit(self, template_id, preds=(), filters=()):
-        """Returns a ticket, or None when the template's queue is full."""
+    def submit(self, template_id, preds=(), filters=(), deadline_ns=0):
+        """Returns a ticket, or None when the template's queue is full.
+        deadline_ns > 0: the query is dropped if not complete by then."""
         lib = load()
         pr = (Range * MAX_PREDS)(*[Range(int(a), int(b)) for a, b in preds])
         fr = (Range * MAX_JOINS)(*[Range(int(a), int(b)) for a, b in filters])
         tk = c_i64()
-        rc = lib.crystal_server_submit(self.h, int(template_id), pr, fr, ctypes.byref(tk))
+        rc = lib.crystal_server_submit(self.h, int(template_id), pr, fr, int(deadline_ns), ctypes.byref(tk))
         if rc == EBUSY:
             return None
         _check(rc, "crystal_server_submit")
+        self.ticket_template[tk.value] = int(template_id)
         return tk.value
 
-    def poll(self, ticket, template_id):
-        """(done, result int64 array or None, latency_ns)."""
+    def poll(self, ticket, template_id=None):
+        """(done, result int64 array or None, latency_ns).  The result buffer
+        is sized from the template the ticket was submitted to; a template_id
+        given here only selects a size to pass (the library rejects one that
+        is too small)."""
         import numpy as np
         lib = load()
-        out = np.zeros(self.n_groups[template_id], dtype=np.int64)
+        t = self.ticket_template.get(int(ticket), 0) if template_id is None else int(template_id)
+        out = np.zeros(self.n_groups[t], dtype=np.int64)
         done, lat = c_i32(), c_i64()
-        _check(lib.crystal_server_poll(self.h, int(ticket), out.ctypes.data_as(c_vp), ctypes.byref(done),
-                                       ctypes.byref(lat)), "crystal_server_poll")
-        return (True, out, lat.value) if done.value else (False, None, 0)
+        rc = lib.crystal_server_poll(self.h, int(ticket), out.ctypes.data_as(c_vp), out.size, ctypes.byref(done),
+                                     ctypes.byref(lat))
+        if rc == ETIMEDOUT:                       # dropped at its deadline: the ticket is released
+            self.ticket_template.pop(int(ticket), None)
+        _check(rc, "crystal_server_poll")
+        if not done.value:
+            return False, None, 0
+        self.ticket_template.pop(int(ticket), None)
+        return True, out, lat.value
+
+    def cancel(self, ticket):
+        """Withdraw a queued, running or finished query; its ticket is released."""
+        _check(load().crystal_server_cancel(self.h, int(ticket)), "crystal_server_cancel")
+        self.ticket_template.pop(int(ticket), None)
 
     def stats(self):
         st = ServerStatsC()

@@ -228,6 +228,7 @@ const char *crystal_status_string(int32_t s) {
     case CRYSTAL_EHIP: return "HIP runtime error";
     case CRYSTAL_EBUSY: return "no free slot";
     case CRYSTAL_ERANGE: return "key or group index out of range";
+    case CRYSTAL_ETIMEDOUT: return "query dropped at its deadline";
     default: return "unknown status";
     }
 }

@@ -11,6 +11,11 @@
 // phases share every pass.  Slot i of a template is bit i of the batch's
 // query masks; the masks are rebuilt when a slot's occupant changes.
 //
+// A query may carry a deadline: one that has not completed by then is
+// dropped (from its queue, or from its slot before its last segment is
+// issued) and reported as timed out.  A client may also cancel a ticket.
+// Both are applied by the server thread between clock steps.
+//
 // With fake_executor set, no HIP call is made: a step completes
 // fake_step_ns after it is issued and results are zero.  This drives the
 // scheduling logic (admission, slot reuse, queue limits, latency accounting)
@@ -43,11 +48,14 @@ struct Request {
     crystal_range preds[CRYSTAL_MAX_PREDS];
     crystal_range filters[CRYSTAL_MAX_JOINS];
     int64_t t_submit;
+    int64_t deadline;         // absolute steady-clock ns; 0: none
 };
 
 struct Result {
+    int32_t tmpl = 0;
     std::vector<int64_t> value;
     int32_t done = 0;
+    crystal_status status = CRYSTAL_OK;  // CRYSTAL_ETIMEDOUT: dropped at its deadline
     int64_t t_submit = 0;
     int64_t t_done = 0;
 };
@@ -55,16 +63,22 @@ struct Result {
 struct Slot {
     bool busy = false;        // occupied (issuing or draining)
     int64_t ticket = -1;
+    int64_t deadline = 0;
     int32_t steps_left = 0;   // segments still to issue
     crystal_range preds[CRYSTAL_MAX_PREDS];
     crystal_range filters[CRYSTAL_MAX_JOINS];
     bool zero_pending = false;
 };
 
+struct Completion {
+    int t, q;                 // template, slot
+    int64_t ticket;           // the slot's occupant when its last segment was issued
+};
+
 struct Step {
     hipEvent_t ev = nullptr;
     int64_t t_issue = 0;
-    std::vector<std::pair<int, int>> completing;  // (template, slot) whose last segment is in this step
+    std::vector<Completion> completing;  // slots whose last segment is in this step
 };
 
 struct Server {
@@ -74,8 +88,9 @@ struct Server {
     int64_t clock = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
-    int64_t *pinned = nullptr;        // host copies of slot outputs
+    int64_t *pinned = nullptr;        // host copies of slot outputs, then of the status word
     int32_t *status = nullptr;        // device status word (inside the workspace)
+    int32_t *pinned_status = nullptr; // its host copy, taken in every step that completes a query
     std::vector<std::vector<Slot>> slots;
     std::vector<std::vector<bool>> masks_dirty;  // [template][0]: slot set changed since the last build
     std::vector<std::deque<Request>> queue;
@@ -86,9 +101,11 @@ struct Server {
     std::thread worker;
     std::atomic<bool> stop{false};
     int64_t next_ticket = 1;
+    std::vector<int64_t> cancel_req;  // tickets cancelled by clients, applied by the server thread
     crystal_status error = CRYSTAL_OK;
     // statistics (written by the server thread, read by crystal_server_stats)
-    std::atomic<int64_t> admitted{0}, completed{0}, rejected{0}, steps{0}, busy_slot_steps{0};
+    std::atomic<int64_t> admitted{0}, completed{0}, rejected{0}, steps{0}, busy_slot_steps{0}, cancelled{0},
+        timed_out{0};
 
     int64_t n_groups(int t) const { return cfg.templates[t].plan.n_groups; }
     int64_t *slot_out(int t, int s) const {
@@ -175,7 +192,7 @@ struct Server {
                 if (!(sl.busy && sl.steps_left > 0)) continue;
                 ++busy_slot_steps;
                 if (--sl.steps_left == 0) {
-                    step.completing.push_back({t, q});
+                    step.completing.push_back({t, q, sl.ticket});
                     masks_dirty[t][0] = true;  // its bit must stop matching
                     if (!cfg.fake_executor &&
                         hipMemcpyAsync(pinned_out(t, q), slot_out(t, q), n_groups(t) * 8, hipMemcpyDeviceToHost,
@@ -187,6 +204,14 @@ struct Server {
             }
         }
         if (!any) return false;
+        // The status word is sticky (the first device error stays), so its
+        // copy after a step's kernels covers every step up to this one; it is
+        // taken only where results are released.
+        if (!cfg.fake_executor && !step.completing.empty() &&
+            hipMemcpyAsync(pinned_status, status, 4, hipMemcpyDeviceToHost, stream) != hipSuccess) {
+            fail(CRYSTAL_EHIP);
+            return false;
+        }
         clock = (clock + 1) % n_segments;
         ++steps;
         step.t_issue = now_ns();
@@ -218,19 +243,29 @@ struct Server {
             inflight.pop_front();
             if (s.ev) (void)hipEventDestroy(s.ev);  // the step is complete; nothing to do on failure
             const int64_t t_done = now_ns();
+            // a device error (key outside a mask table, full ranked table,
+            // group index out of range) means rows were skipped: the results
+            // released by this step, and every later one, would be wrong
+            if (!cfg.fake_executor && !s.completing.empty()) {
+                const int32_t dev_st = __atomic_load_n(pinned_status, __ATOMIC_ACQUIRE);
+                if (dev_st != CRYSTAL_OK) fail((crystal_status)dev_st);
+            }
             std::lock_guard<std::mutex> lk(mu);
-            for (auto [t, q] : s.completing) {
-                Slot &sl = slots[t][q];
-                auto it = results.find(sl.ticket);
+            for (const Completion &c : s.completing) {
+                Slot &sl = slots[c.t][c.q];
+                // a cancelled query's result entry is gone; its slot is
+                // still reserved for it (nothing is admitted into a slot
+                // whose last segment is in flight) and is freed here
+                auto it = results.find(c.ticket);
                 if (it != results.end()) {
-                    it->second.value.assign(n_groups(t), 0);
+                    it->second.value.assign(n_groups(c.t), 0);
                     if (!cfg.fake_executor)
-                        memcpy(it->second.value.data(), pinned_out(t, q), n_groups(t) * 8);
+                        memcpy(it->second.value.data(), pinned_out(c.t, c.q), n_groups(c.t) * 8);
                     it->second.done = 1;
                     it->second.t_done = t_done;
+                    ++completed;
                 }
-                sl = Slot();
-                ++completed;
+                if (sl.ticket == c.ticket) sl = Slot();
             }
         }
     }
@@ -246,6 +281,7 @@ struct Server {
                 queue[t].pop_front();
                 sl.busy = true;
                 sl.ticket = r.ticket;
+                sl.deadline = r.deadline;
                 sl.steps_left = (int32_t)n_segments;
                 memcpy(sl.preds, r.preds, sizeof(sl.preds));
                 memcpy(sl.filters, r.filters, sizeof(sl.filters));
@@ -256,6 +292,65 @@ struct Server {
         }
     }
 
+    // Drop a query that still has segments to issue: its slot is free for
+    // the next admission (in-flight passes may still add into its output,
+    // which the next occupant's clear, later on the same stream, resets).
+    // Called with mu held.
+    bool drop_running(int64_t ticket) {
+        for (int t = 0; t < cfg.n_templates; ++t)
+            for (auto &sl : slots[t])
+                if (sl.busy && sl.ticket == ticket) {
+                    if (sl.steps_left == 0) return false;  // its last segment is in flight
+                    sl = Slot();
+                    masks_dirty[t][0] = true;
+                    return true;
+                }
+        return false;
+    }
+
+    bool drop_queued(int64_t ticket) {
+        for (auto &dq : queue)
+            for (auto it = dq.begin(); it != dq.end(); ++it)
+                if (it->ticket == ticket) {
+                    dq.erase(it);
+                    return true;
+                }
+        return false;
+    }
+
+    // Apply client cancellations and expired deadlines.
+    void expire() {
+        std::lock_guard<std::mutex> lk(mu);
+        for (int64_t tk : cancel_req)
+            if (!drop_queued(tk)) drop_running(tk);
+        cancel_req.clear();
+        const int64_t now = now_ns();
+        auto time_out = [&](int64_t ticket) {
+            auto it = results.find(ticket);
+            if (it == results.end()) return;
+            it->second.done = 1;
+            it->second.status = CRYSTAL_ETIMEDOUT;
+            it->second.t_done = now;
+            ++timed_out;
+        };
+        for (auto &dq : queue)
+            for (auto it = dq.begin(); it != dq.end();) {
+                if (it->deadline && now >= it->deadline) {
+                    time_out(it->ticket);
+                    it = dq.erase(it);
+                } else {
+                    ++it;
+                }
+            }
+        for (int t = 0; t < cfg.n_templates; ++t)
+            for (auto &sl : slots[t])
+                if (sl.busy && sl.steps_left > 0 && sl.deadline && now >= sl.deadline) {
+                    time_out(sl.ticket);
+                    sl = Slot();
+                    masks_dirty[t][0] = true;
+                }
+    }
+
     void run() {
         if (!cfg.fake_executor && hipSetDevice(device_id) != hipSuccess) {
             fail(CRYSTAL_EHIP);
@@ -263,6 +358,7 @@ struct Server {
         }
         while (!stop.load()) {
             retire();
+            expire();
             admit();
             bool issued = false;
             if ((int32_t)inflight.size() < cfg.inflight_steps) issued = issue_step();
@@ -354,11 +450,13 @@ crystal_status crystal_server_create(const crystal_server_config *cfg, crystal_s
         }
         size_t host_bytes = 0;
         for (int t = 0; t < cfg->n_templates; ++t) host_bytes += (size_t)s.n_groups(t) * 8 * cfg->slots_per_template;
-        if (hipHostMalloc((void **)&s.pinned, host_bytes, hipHostMallocDefault) != hipSuccess) {
+        if (hipHostMalloc((void **)&s.pinned, host_bytes + 8, hipHostMallocDefault) != hipSuccess) {
             if (s.own_stream) (void)hipStreamDestroy(s.stream);
             delete h;
             return CRYSTAL_EHIP;
         }
+        s.pinned_status = (int32_t *)((char *)s.pinned + host_bytes);
+        *s.pinned_status = CRYSTAL_OK;
         s.status = (int32_t *)cfg->workspace;
         if (fill_u32((uint32_t *)s.status, 4, 0u, s.stream) != hipSuccess) {
             (void)hipHostFree(s.pinned);
@@ -373,8 +471,8 @@ crystal_status crystal_server_create(const crystal_server_config *cfg, crystal_s
 }
 
 crystal_status crystal_server_submit(crystal_server *h, int32_t template_id, const crystal_range *preds,
-                                     const crystal_range *dim_filters, int64_t *ticket) {
-    if (!h || !ticket) return CRYSTAL_EINVAL;
+                                     const crystal_range *dim_filters, int64_t deadline_ns, int64_t *ticket) {
+    if (!h || !ticket || deadline_ns < 0) return CRYSTAL_EINVAL;
     Server &s = h->s;
     if (template_id < 0 || template_id >= s.cfg.n_templates) return CRYSTAL_EINVAL;
     const crystal_star_query &p = s.cfg.templates[template_id].plan;
@@ -385,6 +483,7 @@ crystal_status crystal_server_submit(crystal_server *h, int32_t template_id, con
     for (int i = 0; i < p.n_preds; ++i) r.preds[i] = preds[i];
     for (int j = 0; j < p.n_joins; ++j) r.filters[j] = dim_filters[j];
     r.t_submit = now_ns();
+    r.deadline = deadline_ns > 0 ? r.t_submit + deadline_ns : 0;
     {
         std::lock_guard<std::mutex> lk(s.mu);
         if (s.error != CRYSTAL_OK) return s.error;
@@ -394,6 +493,7 @@ crystal_status crystal_server_submit(crystal_server *h, int32_t template_id, con
         }
         r.ticket = s.next_ticket++;
         Result res;
+        res.tmpl = template_id;
         res.t_submit = r.t_submit;
         s.results.emplace(r.ticket, std::move(res));
         s.queue[template_id].push_back(r);
@@ -403,19 +503,44 @@ crystal_status crystal_server_submit(crystal_server *h, int32_t template_id, con
     return CRYSTAL_OK;
 }
 
-crystal_status crystal_server_poll(crystal_server *h, int64_t ticket, int64_t *result, int32_t *done,
-                                   int64_t *latency_ns) {
+crystal_status crystal_server_poll(crystal_server *h, int64_t ticket, int64_t *result, int64_t result_capacity,
+                                   int32_t *done, int64_t *latency_ns) {
     if (!h || !done) return CRYSTAL_EINVAL;
     Server &s = h->s;
     std::lock_guard<std::mutex> lk(s.mu);
     if (s.error != CRYSTAL_OK) return s.error;
     auto it = s.results.find(ticket);
     if (it == s.results.end()) return CRYSTAL_EINVAL;
+    // the ticket's own template fixes the result size, whatever is done
+    if (result && result_capacity < s.n_groups(it->second.tmpl)) return CRYSTAL_EINVAL;
     *done = it->second.done;
     if (!it->second.done) return CRYSTAL_OK;
+    if (it->second.status != CRYSTAL_OK) {  // timed out: no result
+        const crystal_status st = it->second.status;
+        if (latency_ns) *latency_ns = it->second.t_done - it->second.t_submit;
+        s.results.erase(it);
+        return st;
+    }
     if (latency_ns) *latency_ns = it->second.t_done - it->second.t_submit;
     if (result) memcpy(result, it->second.value.data(), it->second.value.size() * 8);
     s.results.erase(it);
+    return CRYSTAL_OK;
+}
+
+crystal_status crystal_server_cancel(crystal_server *h, int64_t ticket) {
+    if (!h) return CRYSTAL_EINVAL;
+    Server &s = h->s;
+    {
+        std::lock_guard<std::mutex> lk(s.mu);
+        if (s.error != CRYSTAL_OK) return s.error;
+        auto it = s.results.find(ticket);
+        if (it == s.results.end()) return CRYSTAL_EINVAL;
+        const bool was_done = it->second.done;
+        s.results.erase(it);
+        ++s.cancelled;
+        if (!was_done) s.cancel_req.push_back(ticket);
+    }
+    s.cv.notify_one();
     return CRYSTAL_OK;
 }
 
@@ -428,6 +553,8 @@ crystal_status crystal_server_get_stats(crystal_server *h, crystal_server_stats 
     out->rejected = s.rejected;
     out->steps = s.steps;
     out->busy_slot_steps = s.busy_slot_steps;
+    out->cancelled = s.cancelled;
+    out->timed_out = s.timed_out;
     int64_t q = 0;
     for (auto &d : s.queue) q += (int64_t)d.size();
     out->queued = q;

@@ -50,6 +50,26 @@ def day_keys(n_days: int = N_DAYS):
     return key.astype(np.int32), year.astype(np.int32)
 
 
+def date_key(year: int, month: int, day: int, plus_days: int = 0) -> int:
+    """yyyymmdd key of the calendar date `plus_days` days after year-month-day."""
+    d = np.datetime64(f"{int(year):04d}-{int(month):02d}-{int(day):02d}") + int(plus_days)
+    y = int(d.astype("datetime64[Y]").astype(np.int64)) + 1970
+    m = int(d.astype("datetime64[M]").astype(np.int64)) % 12 + 1
+    dd = int((d - d.astype("datetime64[M]")).astype(np.int64)) + 1
+    return y * 10000 + m * 100 + dd
+
+
+# Packed dimension payload of the flight templates: bits 0..9 the group
+# attribute (the date dimension: year - 1992), bits 16..20 the filter attribute.
+PACK_FILTER_SHIFT = 16
+
+
+def packed_payload(dim, j: int) -> np.ndarray:
+    """Dimension j's packed payload column: (filter << 16) | group field."""
+    grp = (dim.year - FIRST_YEAR) if j == 0 else dim.group
+    return ((dim.filter.astype(np.int32) << PACK_FILTER_SHIFT) | grp.astype(np.int32)).astype(np.int32)
+
+
 def _uniform(g, lo, hi, n):
     """Uniform int32 on the closed interval [lo, hi]."""
     return g.integers(lo, hi, size=int(n), dtype=np.int32, endpoint=True)
@@ -205,3 +225,67 @@ def random_q11_constants(rng: np.random.Generator):
     d = int(rng.integers(0, 9))
     q = int(rng.integers(2, 51))
     return year, d, q
+
+
+# ------------------------------------------------ banded served fact table --
+BAND_DENSE, BAND_SPARSE, BAND_PLAIN = 0, 1, 2
+
+
+@dataclass
+class BandedSpec:
+    """Constants a banded table is drawn around: dense bands hold rows whose
+    dimension-1 key has filter == c1, whose date key has filter == c0 and
+    lies in `year`, and whose discount lies in [disc_lo, disc_lo + 2]."""
+    c0: int
+    c1: int
+    year: int
+    disc_lo: int
+
+
+def banded_star_tables(n: int, band_rows: int = 1 << 19, workload: int = 51,
+                       p_dense: float = 0.3, p_sparse: float = 0.5):
+    """Served fact table (star schema plus the Q1.1 columns) in bands of
+    ``band_rows`` rows of three kinds, drawn at random per band:
+
+    * dense: every row passes the first two steps of the star template
+      (dimension-1 and date joins, for queries with those two constants) and
+      of the Q1.1 template (year and discount window);
+    * sparse: about 1 row in 600 passes the two star joins and 1 in 400 the
+      two Q1.1 tests (date keys outside ``year`` except for 5% of rows);
+    * plain: drawn as ``star_tables``, except that 2% of discounts are
+      U{11..15} and 2% of quantities are 0 or U{51..60} (values outside the
+      generator's usual domains).
+
+    Returns (StarTables, BandedSpec, band kinds)."""
+    t = star_tables(n, workload=workload, with_q11_columns=True)
+    g = streams(workload + 200, 8)
+    d0, d1 = t.dims[0], t.dims[1]
+    c1 = int(t.consts[1])
+    keys1 = d1.key[d1.filter == c1]
+    year = FIRST_YEAR + 2
+    # a date filter constant that keeps some dates of `year`
+    c0 = next(c for c in range(25) if np.any((d0.filter == c) & (d0.year == year)))
+    dates_dense = d0.key[(d0.filter == c0) & (d0.year == year)]
+    dates_other = d0.key[d0.year != year]
+    disc_lo = 4
+    n_bands = (n + band_rows - 1) // band_rows
+    kinds = g[0].choice([BAND_DENSE, BAND_SPARSE, BAND_PLAIN], size=n_bands,
+                        p=[p_dense, p_sparse, 1.0 - p_dense - p_sparse]).astype(np.int32)
+    fk0, fk1, disc, qty = t.fk[0], t.fk[1], t.extra["discount"], t.extra["quantity"]
+    for b, kind in enumerate(kinds):
+        lo, hi = b * band_rows, min(n, (b + 1) * band_rows)
+        m = hi - lo
+        if kind == BAND_DENSE:
+            fk1[lo:hi] = keys1[g[1].integers(0, keys1.size, m)]
+            fk0[lo:hi] = dates_dense[g[2].integers(0, dates_dense.size, m)]
+            disc[lo:hi] = _uniform(g[3], disc_lo, disc_lo + 2, m)
+        elif kind == BAND_SPARSE:
+            keep_year = g[4].random(m) < 0.05
+            fk0[lo:hi] = np.where(keep_year, fk0[lo:hi], dates_other[g[2].integers(0, dates_other.size, m)])
+        else:
+            odd_d = g[5].random(m) < 0.02
+            disc[lo:hi] = np.where(odd_d, _uniform(g[6], 11, 15, m), disc[lo:hi])
+            odd_q = g[5].random(m) < 0.02
+            wide = _uniform(g[7], 50, 60, m)
+            qty[lo:hi] = np.where(odd_q, np.where(wide == 50, 0, wide), qty[lo:hi])
+    return t, BandedSpec(c0=c0, c1=c1, year=year, disc_lo=disc_lo), kinds

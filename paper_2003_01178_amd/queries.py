@@ -18,6 +18,7 @@ Only plan construction lives here; every step runs in the library's kernels.
 """
 from __future__ import annotations
 
+import numpy as np
 import torch
 
 from . import crystal as cx
@@ -47,6 +48,11 @@ class Q11Plan:
         return self.query.run(out=out, status=status, stream=stream, accumulate=accumulate)
 
 
+def _value_range(col):
+    col = np.asarray(col)
+    return (int(col.min()), int(col.max())) if col.size else (0, -1)
+
+
 class StarSchema:
     """Star-schema tables resident in device memory, with their dimension tables."""
 
@@ -56,11 +62,17 @@ class StarSchema:
         self.m1 = to_dev(t.m1, device)
         self.m2 = to_dev(t.m2, device)
         self.extra = {k: to_dev(v, device) for k, v in t.extra.items()}
+        # value range (min, max) of each fact column, recorded when the table
+        # is loaded, as a catalog keeps column statistics: the served Q1.1
+        # template sizes its value -> query-mask tables from them
+        self.col_range = {"datekey": _value_range(t.fk[0]),
+                          **{k: _value_range(v) for k, v in t.extra.items()}}
         self.dims = []
-        for d in t.dims:
+        for j, d in enumerate(t.dims):
             self.dims.append(dict(key=to_dev(d.key, device), filter=to_dev(d.filter, device),
                                   group=to_dev(d.group, device),
                                   year=to_dev(d.year, device) if d.year is not None else None,
+                                  packed=to_dev(datagen.packed_payload(d, j), device),
                                   key_min=int(d.key.min()), key_max=int(d.key.max()), n=d.n))
         self.consts = list(t.consts)
         self.device = device
@@ -115,8 +127,8 @@ def q1x_consts(flight, year=1994, month=1, day=6):
     if flight == 2:
         return (year * 10000 + month * 100 + 1, year * 10000 + month * 100 + 31), (4, 6), (26, 35)
     if flight == 3:
-        d0 = year * 10000 + month * 100 + day
-        return (d0, d0 + 6), (5, 7), (26, 35)
+        return ((datagen.date_key(year, month, day), datagen.date_key(year, month, day, plus_days=6)),
+                (5, 7), (26, 35))
     raise ValueError("flight 1 has queries 1, 2 and 3")
 
 
@@ -128,9 +140,7 @@ def q1x_plan(cols, flight, **kw):
                         agg=cx.AGG_SUM_PRODUCT, agg_cols=(3, 1))
 
 
-# Packed dimension payload of the flight templates: bits 0..9 the group
-# attribute (dim0: year - 1992), bits 16..20 the filter attribute.
-PACK_FILTER_SHIFT = 16
+PACK_FILTER_SHIFT = datagen.PACK_FILTER_SHIFT
 
 
 class FlightTemplates:
@@ -144,12 +154,11 @@ class FlightTemplates:
         self.s = schema
         self.status = cx.new_status(schema.device)
         self.tables = []
-        for j, d in enumerate(schema.dims):
-            grp = d["year"] - datagen.FIRST_YEAR if j == 0 else d["group"]
-            packed = (d["filter"] << PACK_FILTER_SHIFT) | grp
+        for d in schema.dims:
+            # payload: the packed (filter, group) column drawn on the host
             ht = cx.HashTable(cx.HT_DIRECT, d["n"], d["key_min"], d["key_max"], has_payload=True,
                               device=schema.device)
-            ht.build(d["key"], payload=packed.contiguous(), status=self.status)
+            ht.build(d["key"], payload=d["packed"], status=self.status)
             self.tables.append(ht)
 
     def _join(self, j, filt=None, year=None, group=None):
@@ -233,13 +242,11 @@ class ServingTemplates:
         # and a query mask per value, built like a dimension's.  A row passes
         # query q's range on a column iff its value's mask has bit q, which
         # is the range test itself for every value of the domain.
-        date = schema.dims[0]
-        self.q11_domains = [
-            dict(key=date["key"], filter=date["key"], n=date["n"], key_min=date["key_min"],
-                 key_max=date["key_max"], fk_col=0),
-            self._domain(0, 10, 6, dev),                     # discount U{0..10}
-            self._domain(1, 50, 7, dev),                     # quantity U{1..50}
-        ]
+        # Each table covers every value between the column's minimum and
+        # maximum (the table's statistics), so no row's value falls outside
+        # it, whatever the data.
+        self.q11_domains = [self._domain(*schema.col_range[name], fk_col, dev)
+                            for name, fk_col in (("datekey", 0), ("discount", 6), ("quantity", 7))]
         q11_joins = []
         for dm in self.q11_domains:
             ht = cx.HashTable(cx.HT_DIRECT, dm["n"], dm["key_min"], dm["key_max"], has_payload=False, device=dev)
@@ -254,8 +261,15 @@ class ServingTemplates:
                                          agg=cx.AGG_SUM_PRODUCT, agg_cols=(8, 6))
         self.q11_scan = cx.SharedScan(self.q11_template, [dm["mask"] for dm in self.q11_domains])
 
-    @staticmethod
-    def _domain(lo, hi, fk_col, dev):
+    MAX_DOMAIN = 1 << 22
+
+    @classmethod
+    def _domain(cls, lo, hi, fk_col, dev):
+        if hi < lo:
+            lo = hi = 0                                      # empty column: any one-value domain
+        if hi - lo + 1 > cls.MAX_DOMAIN:
+            raise ValueError(f"fact column {fk_col} spans {hi - lo + 1} values; a value -> query-mask "
+                             f"table covers at most {cls.MAX_DOMAIN}")
         keys = torch.arange(lo, hi + 1, dtype=torch.int32, device=dev)
         return dict(key=keys, filter=keys, n=hi - lo + 1, key_min=lo, key_max=hi, fk_col=fk_col)
 

@@ -2,12 +2,14 @@
 
     python -m paper_2003_01178_amd.rocprof_summary stats  <kernel_stats.csv> <out.md> <title> <command>
     python -m paper_2003_01178_amd.rocprof_summary traffic <out.json> <kernel substring> \
-        <fetch_dir> <write_dir> <copy_fetch_dir> <copy_write_dir> <copy_bytes> <command...>
+        <fetch_dir> <write_dir> <copy_fetch_dir> <copy_write_dir> <copy_bytes> [sources=a.hip,b.hpp] <command...>
 
 `traffic` scales the per-dispatch FETCH_SIZE and WRITE_SIZE of a kernel by
 what the same counters read for a plain device copy of known size (bytes
 read = bytes written = copy_bytes), and records the hash of the kernel
-sources they were taken with, so a later change of the kernel voids them.
+sources they were taken with, so a later change of the kernel voids them
+(the star kernel's sources unless `sources=` names others, relative to the
+package directory).
 """
 from __future__ import annotations
 
@@ -68,7 +70,16 @@ def stats(csv_path, out_md, title, command):
         f.write("\n".join(lines) + "\n")
 
 
-def traffic(out_json, kernel, fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_bytes, command):
+def file_hash(files):
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(HERE, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic(out_json, kernel, fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_bytes, command,
+            sources=None):
     copy_bytes = int(copy_bytes)
     cf, _ = per_dispatch(copy_fetch_dir, "copyBuffer", "FETCH_SIZE")
     cw, _ = per_dispatch(copy_write_dir, "copyBuffer", "WRITE_SIZE")
@@ -80,7 +91,8 @@ def traffic(out_json, kernel, fetch_dir, write_dir, copy_fetch_dir, copy_write_d
            "dispatches": [nf, nw], "copy_bytes": copy_bytes, "copy_fetch_kib": cf, "copy_write_kib": cw,
            "fetch_scale": f_scale, "write_scale": w_scale,
            "traffic_bytes": kf * 1024.0 * f_scale + kw * 1024.0 * w_scale,
-           "source_hash": source_hash(), "command": command}
+           "source_hash": source_hash() if not sources else file_hash(sources),
+           "sources": list(sources) if sources else [*STAR_SOURCES, STAR_DECLS[0]], "command": command}
     with open(out_json, "w") as f:
         json.dump(rec, f, indent=1)
     print(json.dumps(rec))
@@ -90,6 +102,11 @@ if __name__ == "__main__":
     if sys.argv[1] == "stats":
         stats(sys.argv[2], sys.argv[3], sys.argv[4], " ".join(sys.argv[5:]))
     elif sys.argv[1] == "traffic":
-        traffic(*sys.argv[2:9], " ".join(sys.argv[9:]))
+        rest = sys.argv[9:]
+        srcs = None
+        if rest and rest[0].startswith("sources="):
+            srcs = rest[0][len("sources="):].split(",")
+            rest = rest[1:]
+        traffic(*sys.argv[2:9], " ".join(rest), sources=srcs)
     else:
         raise SystemExit(__doc__)

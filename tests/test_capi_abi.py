@@ -34,7 +34,7 @@ def test_every_declared_symbol_is_exported(cx):
 
 def test_struct_layout_matches_binding(cx):
     lib = cx.load()
-    assert lib.crystal_abi_version() == 6
+    assert lib.crystal_abi_version() == 7
     for which, ty in enumerate((cx.Range, cx.HT, cx.Pred, cx.Join, cx.StarQueryC, cx.QmaskTableC,
                                 cx.BatchQueryC, cx.BatchC, cx.ServerTemplateC, cx.ServerConfigC,
                                 cx.ServerStatsC, cx.BuildItemC, cx.ColFormatC, cx.QmaskBuildItemC)):
@@ -266,3 +266,4 @@ def test_shared_scan_tuning_classes(cx):
         assert lib.crystal_tune_set(cx.K_SHARED_SCAN_SCALAR, -1, -1, 1024, 3, 0) == cx.EINVAL
     finally:
         cx.tune_reset()
+

@@ -48,46 +48,48 @@ def test_q11_6M_exact():
 
 
 @pytest.mark.parametrize("sigma", [0.0, 0.5, 1.0])
-def test_select_2pow29_fingerprint(sigma):
-    """Count exact; the multiset fingerprinted by sum and sum of squares (mod 2^64)
-    and every output inside the range; the stable form equal element by element
-    on a strided sample of positions."""
+def test_select_2pow29_exact(sigma):
+    """Count exact; the unstable output equal to the oracle's as a sorted
+    multiset (both sorted on the device by torch.sort, compared in full);
+    the stable output equal to the oracle's element by element."""
     announce("full select", sigma)
     n = 1 << 29
     y = datagen.select_column(n)
     lo, hi = datagen.select_threshold_range(sigma)
     x = dev(y)
-    out, cnt = cx.select(x, lo, hi)
-    c = int(cnt.item())
     want = oracle.select(y, lo, hi)
-    assert c == want.size
+    c = want.size
+    out, cnt = cx.select(x, lo, hi)
+    assert int(cnt.item()) == c
     if c:
-        got = out[:c]
-        assert bool(((got >= lo) & (got <= hi)).all().item())
-        g64 = got.to(torch.int64)
-        assert int(g64.sum().item()) == int(want.astype(np.int64).sum())
-        assert int((g64 * g64).sum().item()) == int((want.astype(np.int64) ** 2).sum())
-    del out
+        got_sorted = torch.sort(out[:c]).values
+        del out
+        want_sorted = torch.sort(dev(want)).values
+        assert torch.equal(got_sorted, want_sorted)
+        del got_sorted, want_sorted
+    else:
+        del out
     out, cnt = cx.select(x, lo, hi, stable=True)
     assert int(cnt.item()) == c
     if c:
-        idx = np.linspace(0, c - 1, 100_003).astype(np.int64)
-        assert np.array_equal(out[torch.from_numpy(idx).cuda()].cpu().numpy(), want[idx])
+        assert np.array_equal(out[:c].cpu().numpy(), want)
 
 
-def test_project_2pow29_sampled():
+def test_project_2pow29_exact():
+    """Every one of the 2^29 outputs against the oracle, within the
+    tolerance derived for two fp32 roundings."""
     announce("full project")
     n = 1 << 29
     x1, x2 = datagen.project_columns(n)
-    got = cx.project(dev(x1), dev(x2), 2.0, 3.0)
-    idx = np.random.default_rng(0).integers(0, n, size=1_000_000)
-    idx[:3] = [0, n - 1, n // 2]
-    g = got[torch.from_numpy(idx).cuda()].cpu().numpy()
-    w = oracle.project(x1[idx], x2[idx], 2.0, 3.0)
-    assert project_close(g, w, x1[idx], x2[idx], 2.0, 3.0)
+    got = cx.project(dev(x1), dev(x2), 2.0, 3.0).cpu().numpy()
+    want = oracle.project(x1, x2, 2.0, 3.0)
+    step = 1 << 26
+    for a in range(0, n, step):
+        b = a + step
+        assert project_close(got[a:b], want[a:b], x1[a:b], x2[a:b], 2.0, 3.0), a
 
 
-@pytest.mark.parametrize("d", [1 << 13, 1 << 20, 1 << 27])
+@pytest.mark.parametrize("d", [1 << 13, 1 << 16, 1 << 20, 1 << 24, 1 << 27])
 def test_join_2pow28_probes_exact(d):
     announce("full join", d)
     t = datagen.join_tables(d, n_probe=1 << 28)

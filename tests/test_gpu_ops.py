@@ -61,6 +61,26 @@ def test_select_tile_shapes(block, ipt):
         check_select(out, cnt, y, 0, 2 ** 30, stable)
 
 
+@pytest.mark.parametrize("shape", [(512, 16, 1), (256, 8, 1)])
+@pytest.mark.parametrize("sigma", [0.1, 0.5, 1.0])
+def test_select_persistent_flushes(shape, sigma):
+    """One workgroup per CU over 32M rows: each workgroup compacts many tiles
+    (at least 16, asserted from the host) into its two-tile LDS buffer and
+    reserves output space mid-loop whenever the buffer could not take
+    another tile.  The output is compared with the oracle as a sorted
+    multiset."""
+    block, ipt, gpc = shape
+    n = (1 << 25) + 12_345
+    tiles = (n + block * ipt - 1) // (block * ipt)
+    assert tiles / (gpc * torch.cuda.get_device_properties(0).multi_processor_count) >= 16
+    announce("select persistent", shape, sigma)
+    cx.tune_set(cx.K_SELECT, block, ipt, gpc)
+    y = datagen.select_column(n, workload=2000)
+    lo, hi = datagen.select_threshold_range(sigma)
+    out, cnt = cx.select(dev(y), lo, hi)
+    check_select(out, cnt, y, lo, hi, stable=False)
+
+
 def test_select_unordered_keeps_tiles_contiguous():
     """Each tile's matches form one contiguous run in input order."""
     announce("select runs")

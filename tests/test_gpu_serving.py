@@ -118,3 +118,34 @@ def test_segment_sizes_do_not_change_results(setup):
     for a, b, c in zip(answers[0], answers[1], consts):
         assert np.array_equal(a, b)
         assert np.array_equal(a, star_oracle(t, c)[0])
+
+
+def test_device_error_is_reported_not_served(setup):
+    """A dimension key outside its query-mask table's span makes the mask
+    build set CRYSTAL_ERANGE in the server's device status word: poll and
+    stats report that code instead of releasing a wrong answer."""
+    announce("serve device error")
+    t, sv = setup
+    star = dict(sv.server_templates()[0])
+    dims = list(star["dims"])
+    keys, filt, n, qm = dims[0]
+    bad = keys.clone()
+    bad[3] = int(keys.max().item()) + 1                  # one key past the table's span
+    dims[0] = (bad, filt, n, qm)
+    star["dims"] = dims
+    srv = cx.Server([star], slots=4, segment_rows=262_144, max_queue=16, inflight=2)
+    c = t.consts
+    tk = srv.submit(0, filters=[(c[j], c[j]) for j in queries.DEFAULT_JOIN_ORDER])
+    with pytest.raises(cx.CrystalError) as e:
+        t0 = time.time()
+        while time.time() - t0 < 30:
+            done, _, _ = srv.poll(tk)
+            assert not done, "an answer was released despite the device error"
+            time.sleep(0.001)
+    assert e.value.code == cx.ERANGE
+    with pytest.raises(cx.CrystalError) as e:
+        srv.stats()
+    assert e.value.code == cx.ERANGE
+    with pytest.raises(cx.CrystalError) as e:
+        srv.close()
+    assert e.value.code == cx.ERANGE

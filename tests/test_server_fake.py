@@ -138,3 +138,92 @@ def test_invalid_configurations():
     finally:
         srv.close()
     assert lib.crystal_server_create(None, None) == cx.EINVAL
+
+
+
+def test_poll_capacity_is_checked_against_the_tickets_template():
+    """The result size comes from the ticket's own template: a buffer sized
+    for a smaller template is rejected (nothing copied, the ticket kept),
+    and the binding sizes its buffer from the ticket."""
+    srv = cx.Server([dict(plan=pred_plan(512, n_groups=7000)), dict(plan=pred_plan(512, n_groups=1))], slots=2,
+                    segment_rows=256, max_queue=8, inflight=1, fake_step_ns=1_000_000)
+    try:
+        lib = cx.load()
+        tk = srv.submit(0, preds=[(0, 1)])
+        assert wait_for(lambda: srv.stats()["completed"] == 1)
+        small = (ctypes.c_int64 * 1)()
+        done, lat = ctypes.c_int32(), ctypes.c_int64()
+        assert lib.crystal_server_poll(srv.h, tk, small, 1, ctypes.byref(done), ctypes.byref(lat)) == cx.EINVAL
+        with pytest.raises(cx.CrystalError) as e:
+            srv.poll(tk, 1)                                    # the other template's size: too small
+        assert e.value.code == cx.EINVAL
+        ok, res, ns = srv.poll(tk)                             # sized from the ticket: 7000 values
+        assert ok and res.size == 7000 and ns > 0
+        # released once read: the ticket is unknown now
+        assert lib.crystal_server_poll(srv.h, tk, None, 0, ctypes.byref(done), ctypes.byref(lat)) == cx.EINVAL
+    finally:
+        srv.close()
+
+
+def test_deadline_drops_queued_and_running_queries():
+    """One slot, 4 segments of 20 ms: a running query whose deadline falls
+    mid-cycle is dropped and frees its slot; a queued query that cannot get
+    the slot before its deadline is dropped from the queue; both poll as
+    CRYSTAL_ETIMEDOUT, and a query without a deadline behind them completes."""
+    srv = cx.Server([dict(plan=pred_plan(1000))], slots=1, segment_rows=256, max_queue=8, inflight=1,
+                    fake_step_ns=STEP_NS)
+    try:
+        a = srv.submit(0, preds=[(0, 1)], deadline_ns=int(2.5 * STEP_NS))    # times out while running
+        b = srv.submit(0, preds=[(0, 1)], deadline_ns=int(1.5 * STEP_NS))    # times out in the queue
+        c = srv.submit(0, preds=[(0, 1)])
+        outcome = {}
+
+        def poll_all():
+            for t in (a, b, c):
+                if t in outcome:
+                    continue
+                try:
+                    done, res, ns = srv.poll(t)
+                    if done:
+                        outcome[t] = ("done", ns)
+                except cx.CrystalError as e:
+                    outcome[t] = (e.code, None)
+            return len(outcome) == 3
+        assert wait_for(poll_all, timeout=20)
+        assert outcome[a][0] == cx.ETIMEDOUT
+        assert outcome[b][0] == cx.ETIMEDOUT
+        assert outcome[c][0] == "done"
+        # c took the slot once a was dropped, not after a's full cycle
+        assert outcome[c][1] < 4 * STEP_NS + 4 * STEP_NS
+        st = srv.stats()
+        assert st["timed_out"] == 2 and st["completed"] == 1 and st["admitted"] == 2
+    finally:
+        srv.close()
+
+
+def test_cancel_queued_running_and_finished():
+    srv = cx.Server([dict(plan=pred_plan(1000))], slots=1, segment_rows=256, max_queue=8, inflight=1,
+                    fake_step_ns=STEP_NS)
+    try:
+        a = srv.submit(0, preds=[(0, 1)])
+        b = srv.submit(0, preds=[(0, 1)])
+        assert wait_for(lambda: srv.stats()["steps"] >= 1)          # a is running, b queued
+        srv.cancel(b)                                               # queued
+        srv.cancel(a)                                               # running: frees the slot
+        d = srv.submit(0, preds=[(0, 1)])
+        t0 = time.time()
+        assert wait_for(lambda: srv.poll(d)[0], timeout=20)
+        assert time.time() - t0 < 4 * 4 * STEP_NS / 1e9             # d did not wait for a's cycle
+        e = srv.submit(0, preds=[(0, 1)])
+        assert wait_for(lambda: srv.stats()["completed"] == 2, timeout=20)
+        srv.cancel(e)                                               # finished, not polled: discarded
+        for t in (a, b, e):
+            with pytest.raises(cx.CrystalError) as err:
+                srv.poll(t)
+            assert err.value.code == cx.EINVAL                      # released
+        with pytest.raises(cx.CrystalError):
+            srv.cancel(12345)
+        st = srv.stats()
+        assert st["cancelled"] == 3 and st["completed"] == 2
+    finally:
+        srv.close()
