@@ -298,6 +298,26 @@ crystal_status crystal_run_star_query_accumulate(const crystal_star_query *q, in
                                                  int32_t *status, void *scratch, size_t scratch_bytes,
                                                  void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * query and result as crystal_run_star_query, with no caller scratch.  The
+ * per-workgroup partials of a scalar result go to a fixed array of
+ * CRYSTAL_STAR_NOALLOC_PARTIALS int64 words (64 KiB) that the library holds
+ * in each device's memory until the process ends; its address is looked up
+ * once per device, on the first call made with that device current.
+ * Nothing is allocated, here or later.  Limit: a scalar plan whose
+ * crystal_star_query_scratch_bytes exceeds 64 KiB (more than
+ * CRYSTAL_STAR_NOALLOC_PARTIALS workgroups, i.e. above about 1.3e11 rows on a
+ * 256-CU device) returns CRYSTAL_ESCRATCH and launches nothing.  Grouped
+ * plans use no scratch.  Every call on one device shares that device's
+ * array: scalar-result calls that overlap on one device (other streams, other
+ * threads) race and must be ordered by the caller.  Each workgroup writes its
+ * own partial before the finalize kernel reads it, so no clearing is needed
+ * between calls. */
+#define CRYSTAL_STAR_NOALLOC_PARTIALS 8192
+crystal_status crystal_run_star_query_noalloc(const crystal_star_query *q, int64_t *out, int32_t *status,
+                                              void *stream);
+
 /* Write a narrow column: out[i] = in[i] - base as a `width`-byte unsigned
  * value (width 1 or 2).  in: device int32[n], 16-byte aligned; out: device,
  * n * width bytes, 16-byte aligned.  A value outside [base, base + 2^(8 width)

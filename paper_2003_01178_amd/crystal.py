@@ -136,6 +136,7 @@ def _declare(lib):
         "crystal_star_query_scratch_bytes": (ctypes.c_size_t, [P(StarQueryC)]),
         "crystal_run_star_query": (c_i32, [P(StarQueryC), c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp]),
         "crystal_run_star_query_accumulate": (c_i32, [P(StarQueryC), c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp]),
+        "crystal_run_star_query_noalloc": (c_i32, [P(StarQueryC), c_vp, c_vp, c_vp]),
         "crystal_pack_column": (c_i32, [c_vp, c_i64, c_i32, c_i32, c_vp, c_vp, c_vp]),
         "crystal_qmask_bytes": (ctypes.c_size_t, [c_i64]),
         "crystal_qmask_ranked_bytes": (ctypes.c_size_t, [c_i64, c_i32]),
@@ -453,6 +454,17 @@ class StarQuery:
         fn = lib.crystal_run_star_query_accumulate if accumulate else lib.crystal_run_star_query
         _check(fn(ctypes.byref(self.c), _ptr(out), _ptr(status), _ptr(self.scratch), self.scratch_bytes,
                   _stream(stream)), "crystal_run_star_query")
+        return out, status
+
+    def run_noalloc(self, out, status, stream=None):
+        """Run the query into out (overwritten) through the entry point that
+        allocates nothing: a scalar result's partials go to the library's
+        fixed per-device array instead of this plan's scratch.  out (int64,
+        n_groups) and status (int32, 1) are the caller's device tensors."""
+        if out.dtype != torch.int64 or out.numel() < self.n_groups or status.dtype != torch.int32:
+            raise ValueError("out must hold n_groups int64 values and status one int32")
+        _check(load().crystal_run_star_query_noalloc(ctypes.byref(self.c), _ptr(out), _ptr(status),
+                                                     _stream(stream)), "crystal_run_star_query_noalloc")
         return out, status
 
 

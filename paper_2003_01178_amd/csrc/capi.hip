@@ -403,6 +403,22 @@ crystal_status crystal_run_star_query_accumulate(const crystal_star_query *q, in
     return run_star(q, out, status, scratch, scratch_bytes, stream, true);
 }
 
+crystal_status crystal_run_star_query_noalloc(const crystal_star_query *q, int64_t *out, int32_t *status,
+                                              void *stream) {
+    if (!q || !out || !status) return CRYSTAL_EINVAL;
+    StarPlanDev d;
+    crystal_status st = star_plan_to_dev(*q, d);
+    if (st != CRYSTAL_OK) return st;
+    uint64_t *partials = nullptr;
+    if (d.scalar) {
+        if (star_max_grid(q->n_rows) > kStarNoallocPartials) return CRYSTAL_ESCRATCH;
+        const hipError_t e = star_noalloc_partials(&partials);
+        if (e != hipSuccess) return from_hip(e);
+    }
+    return from_hip(launch_star(tune_lookup(CRYSTAL_K_STAR, q->n_rows), d, (uint64_t *)out, status, partials,
+                                false, as_stream(stream)));
+}
+
 crystal_status crystal_pack_column(const int32_t *in, int64_t n, int32_t base, int32_t width, void *out,
                                    int32_t *status, void *stream) {
     if (n < 0 || (width != 1 && width != 2) || !status || (n > 0 && (!in || !out || !aligned16(in) || !aligned16(out))))

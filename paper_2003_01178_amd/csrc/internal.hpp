@@ -129,6 +129,12 @@ struct StarPlanDev {
 constexpr int kStarMaxGridPerCu = 32;
 // Largest grid the star kernel launches for n rows (sizes the scalar partials).
 int64_t star_max_grid(int64_t n_rows);
+// Capacity of the per-device partials array used by
+// crystal_run_star_query_noalloc: star_max_grid() on a 256-CU device.
+constexpr int64_t kStarNoallocPartials = CRYSTAL_STAR_NOALLOC_PARTIALS;
+// Device address of that array on the current device (looked up once per
+// device with hipGetSymbolAddress).
+hipError_t star_noalloc_partials(uint64_t **ptr);
 
 crystal_status star_plan_to_dev(const crystal_star_query &q, StarPlanDev &d);
 

@@ -26,6 +26,8 @@
 // (BlockAggregate) into a partial in scratch memory and summed by a one-
 // workgroup finalize kernel, which avoids same-address atomics from every
 // workgroup.
+#include <mutex>
+
 #include "block.hpp"
 #include "internal.hpp"
 #include "variants.hpp"
@@ -476,6 +478,32 @@ static hipError_t star_t(const LaunchCfg &cfg, StarPlanDev p, uint64_t *out, int
     if (e != hipSuccess || !p.scalar) return e;
     hipLaunchKernelGGL(star_finalize_kernel, dim3(1), dim3(256), 0, s, partials, grid, out, accumulate ? 1 : 0);
     return hipGetLastError();
+}
+
+// Partials of scalar queries run without caller scratch
+// (crystal_run_star_query_noalloc): one array per device, which the device
+// holds until the process ends.  In host code `scratch` names a host-side
+// stand-in, so kernels only ever receive the device address that
+// hipGetSymbolAddress returned for the device current at the time.
+static __device__ __align__(256) uint64_t scratch[kStarNoallocPartials];
+
+hipError_t star_noalloc_partials(uint64_t **ptr) {
+    static std::mutex mu;
+    static uint64_t *addr[64];
+    int d = -1;
+    hipError_t e = hipGetDevice(&d);
+    if (e != hipSuccess) return e;
+    if (d < 0 || d >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[d]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[d] = (uint64_t *)p;
+    }
+    *ptr = addr[d];
+    return hipSuccess;
 }
 
 hipError_t launch_star(const LaunchCfg &cfg, const StarPlanDev &plan, uint64_t *out, int32_t *status,

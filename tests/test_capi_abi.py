@@ -267,3 +267,25 @@ def test_shared_scan_tuning_classes(cx):
     finally:
         cx.tune_reset()
 
+
+def test_star_noalloc_host_errors(cx):
+    """The allocation-free star entry point checks its arguments and its fixed
+    partials array's limit on the host, before anything is launched."""
+    lib = cx.load()
+    q = cx.StarQueryC()
+    fake = ctypes.c_void_p(1 << 20)
+    q.n_cols, q.n_groups, q.agg, q.agg_col0 = 1, 1, cx.AGG_SUM, 0
+    q.cols[0] = 1 << 20
+    st, out = ctypes.c_void_p(1 << 21), ctypes.c_void_p(1 << 22)
+    # above CRYSTAL_STAR_NOALLOC_PARTIALS workgroups of 256 x 65535 rows: rejected
+    q.n_rows = 8192 * 256 * 65535 + 1
+    assert lib.crystal_run_star_query_noalloc(ctypes.byref(q), out, st, None) == cx.ESCRATCH
+    # the ordinary entry point would need more than the fixed 64 KiB for it
+    assert lib.crystal_star_query_scratch_bytes(ctypes.byref(q)) > 8192 * 8
+    assert lib.crystal_run_star_query_noalloc(None, out, st, None) == cx.EINVAL
+    assert lib.crystal_run_star_query_noalloc(ctypes.byref(q), None, st, None) == cx.EINVAL
+    assert lib.crystal_run_star_query_noalloc(ctypes.byref(q), out, None, None) == cx.EINVAL
+    q.cols[0] = (1 << 20) + 4                                                    # misaligned column
+    q.n_rows = 100
+    assert lib.crystal_run_star_query_noalloc(ctypes.byref(q), out, st, None) == cx.EINVAL
+    del fake
