@@ -438,7 +438,7 @@ def main():
         sys.exit(3)
     cx.load()
     kernel_id = {"star": cx.K_STAR, "q11": cx.K_STAR, "select": cx.K_SELECT, "project": cx.K_PROJECT,
-                 "join": cx.K_HT_PROBE, "copy": cx.K_SELECT, "serve": cx.K_SHARED_SCAN,
+                 "join": cx.K_HT_PROBE, "copy": cx.K_SELECT, "serve": cx.K_SHARED_SCAN, "pass": cx.K_SHARED_SCAN,
                  "partition": cx.K_RADIX, "sort": cx.K_RADIX, "groupby": cx.K_GROUPBY}[args.workload]
     if args.tune:
         b, i, g = (int(x) for x in args.tune.split(","))
