@@ -80,9 +80,11 @@ size_t crystal_struct_size(int32_t which);
 /*   in        device, n int32 values                                        */
 /*   out       device, capacity for every match (n values always suffice)    */
 /*   out_count device int64; cleared, then the number of matches             */
-/* Output order: the matches of a tile are contiguous and in input order;    */
-/* tiles follow the order in which their reservations completed, which       */
-/* varies between runs.  The multiset of values and the count are exact.     */
+/* Output order: the matches of a tile are contiguous, in a fixed order      */
+/* within the tile (wave by wave; within a wave, item slot by item slot,     */
+/* lane by lane); tiles follow the order in which their reservations         */
+/* completed, which varies between runs.  The multiset of values and the     */
+/* count are exact.                                                          */
 /* ------------------------------------------------------------------------ */
 crystal_status crystal_select(const int32_t *in, int64_t n, crystal_range pred,
                               int32_t *out, int64_t *out_count, void *stream);

@@ -206,13 +206,22 @@ hipError_t launch_ht_build(const crystal_ht &ht, const int32_t *keys, const int3
     return hipGetLastError();
 }
 
+// A tile's probe keys (and probe payloads) in registers.
+template <int IPT, bool PP>
+struct ProbeRegs {
+    int32_t key[IPT];
+    int32_t pv[PP ? IPT : 1];
+};
+
 // --------------------------------------------------------------- probe ----
 // Query Q4: BlockLoad a tile of probe keys (and probe payloads), probe every
 // item, keep a per-thread sum and match count, BlockAggregate, and add the
 // workgroup's totals with two 64-bit atomics.  MODE 0: linear probing in
 // global memory; MODE 1: linear probing in a copy of the table staged in LDS
-// once per workgroup; MODE 2: direct table.
-template <int BLOCK, int IPT, int MODE>
+// once per workgroup; MODE 2: direct table.  PP: probe rows carry a payload
+// (pp is not null), a separate instance so that the payload registers exist
+// only when used.
+template <int BLOCK, int IPT, int MODE, bool PP>
 __global__ __launch_bounds__(BLOCK) void ht_probe_kernel(DevTable t, const int32_t *__restrict__ fk,
                                                          const int32_t *__restrict__ pp, int64_t n,
                                                          uint64_t *__restrict__ out_sum,
@@ -231,11 +240,10 @@ __global__ __launch_bounds__(BLOCK) void ht_probe_kernel(DevTable t, const int32
         slots = reinterpret_cast<const v2i *>(lds_raw);
     }
     uint64_t sum = 0, cnt = 0;
-    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+    // one tile: the probes of its (already loaded) keys
+    auto probe_tile = [&](int64_t tile, const ProbeRegs<IPT, PP> &r) {
+        const int32_t(&key)[IPT] = r.key;
         const int64_t base = tile * T::ITEMS;
-        int32_t key[IPT], pv[IPT];
-        block_load<BLOCK, IPT, true>(fk, base, n, key);
-        if (pp) block_load<BLOCK, IPT, true>(pp, base, n, pv);
         const uint32_t valid = valid_mask<BLOCK, IPT>(base, n);
         uint32_t hit = 0;
         int32_t pay[IPT];
@@ -303,9 +311,41 @@ __global__ __launch_bounds__(BLOCK) void ht_probe_kernel(DevTable t, const int32
 #pragma unroll
         for (int k = 0; k < IPT; ++k)
             if ((hit >> k) & 1u) {
-                sum += (uint64_t)(int64_t)pay[k] + (pp ? (uint64_t)(int64_t)pv[k] : 0ull);
+                uint64_t add = (uint64_t)(int64_t)pay[k];
+                if constexpr (PP) add += (uint64_t)(int64_t)r.pv[k];
+                sum += add;
                 cnt += 1;
             }
+    };
+    auto load = [&](int64_t tile, ProbeRegs<IPT, PP> &r) {
+        block_load<BLOCK, IPT, true>(fk, tile * T::ITEMS, n, r.key);
+        if constexpr (PP) block_load<BLOCK, IPT, true>(pp, tile * T::ITEMS, n, r.pv);
+    };
+    int64_t tile = blockIdx.x;
+    if constexpr (PP) {
+        // probe payloads too: one buffer (a second one would spill at 16 items per thread)
+        ProbeRegs<IPT, PP> r;
+        for (; tile < n_tiles; tile += gridDim.x) {
+            load(tile, r);
+            probe_tile(tile, r);
+        }
+    } else {
+    // the next tile's keys are loaded while the current tile is probed, in
+    // alternating register buffers so that a buffer receiving loads is never
+    // copied
+    ProbeRegs<IPT, PP> ra, rb;
+    if (tile < n_tiles) load(tile, ra);
+    while (tile < n_tiles) {
+        int64_t nxt = tile + gridDim.x;
+        if (nxt < n_tiles) load(nxt, rb);
+        probe_tile(tile, ra);
+        tile = nxt;
+        if (tile >= n_tiles) break;
+        nxt = tile + gridDim.x;
+        if (nxt < n_tiles) load(nxt, ra);
+        probe_tile(tile, rb);
+        tile = nxt;
+    }
     }
     const uint64_t bs = block_sum_u64<BLOCK>(sum, red);
     __syncthreads();
@@ -314,6 +354,27 @@ __global__ __launch_bounds__(BLOCK) void ht_probe_kernel(DevTable t, const int32
         if (bs) atomic_add_u64(out_sum, bs);
         if (bc) atomic_add_u64(out_cnt, bc);
     }
+}
+
+template <int BLOCK, int IPT, bool PP>
+static hipError_t probe_launch(const crystal_ht &ht, const DevTable &t, bool stage, int64_t table_bytes,
+                               int64_t grid, const int32_t *fk, const int32_t *pp, int64_t n, uint64_t *out,
+                               uint64_t *cnt, int64_t n_tiles, hipStream_t s) {
+    if (ht.kind == CRYSTAL_HT_DIRECT) {
+        hipLaunchKernelGGL((ht_probe_kernel<BLOCK, IPT, 2, PP>), dim3((unsigned)grid), dim3(BLOCK), 0, s,
+                           t, fk, pp, n, out, cnt, n_tiles);
+    } else if (stage) {
+        auto fn = ht_probe_kernel<BLOCK, IPT, 1, PP>;
+        hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)table_bytes);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(BLOCK), (size_t)table_bytes, s, t, fk, pp, n,
+                           out, cnt, n_tiles);
+    } else {
+        hipLaunchKernelGGL((ht_probe_kernel<BLOCK, IPT, 0, PP>), dim3((unsigned)grid), dim3(BLOCK), 0, s,
+                           t, fk, pp, n, out, cnt, n_tiles);
+    }
+    return hipGetLastError();
 }
 
 template <int BLOCK, int IPT>
@@ -328,21 +389,9 @@ static hipError_t probe_t(const LaunchCfg &cfg_in, const crystal_ht &ht, const i
     if (stage && cfg.grid_per_cu <= 0) cfg.grid_per_cu = 1;  // stage once per resident workgroup
     const int64_t grid = grid_for(n_tiles, cfg);
     if (grid == 0) return hipSuccess;
-    if (ht.kind == CRYSTAL_HT_DIRECT) {
-        hipLaunchKernelGGL((ht_probe_kernel<BLOCK, IPT, 2>), dim3((unsigned)grid), dim3(BLOCK), 0, s,
-                           t, fk, pp, n, out, cnt, n_tiles);
-    } else if (stage) {
-        auto fn = ht_probe_kernel<BLOCK, IPT, 1>;
-        hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)table_bytes);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(BLOCK), (size_t)table_bytes, s, t, fk, pp, n,
-                           out, cnt, n_tiles);
-    } else {
-        hipLaunchKernelGGL((ht_probe_kernel<BLOCK, IPT, 0>), dim3((unsigned)grid), dim3(BLOCK), 0, s,
-                           t, fk, pp, n, out, cnt, n_tiles);
-    }
-    return hipGetLastError();
+    if (pp)
+        return probe_launch<BLOCK, IPT, true>(ht, t, stage, table_bytes, grid, fk, pp, n, out, cnt, n_tiles, s);
+    return probe_launch<BLOCK, IPT, false>(ht, t, stage, table_bytes, grid, fk, pp, n, out, cnt, n_tiles, s);
 }
 
 hipError_t launch_ht_probe(const LaunchCfg &cfg, const crystal_ht &ht, const int32_t *fk,

@@ -246,12 +246,21 @@ __global__ __launch_bounds__(BLOCK) void select_kernel(const int32_t *__restrict
 }
 
 // Unstable selection with buffered reservations.  Persistent workgroups
-// stride over the tiles; each compacts a tile's matches (BlockScan +
-// BlockShuffle, in input order within the tile) into an LDS buffer of two
-// tiles and reserves output space with one atomic only when the buffer could
-// not take another tile, then writes the whole buffer out.  Fewer
-// reservations than one per tile (they serialise on one address), and the
-// next tile's loads are in flight while the current one is compacted.
+// stride over the tiles and compact each tile's matches into an LDS buffer of
+// two tiles; output space is reserved with one atomic only when the buffer
+// could not take another tile, then the whole buffer is written out with
+// 16-byte stores.  Fewer reservations than one per tile (they serialise on
+// one address), and the loads of the next two tiles are in flight while the
+// current one is compacted.
+//
+// Compaction (BlockScan + BlockShuffle): for every item slot k, a ballot of
+// the wave's flags gives each matching lane its rank among the wave's matches
+// in that slot (mbcnt), so a wave's matches are laid out slot by slot, lane
+// by lane, and each LDS store instruction writes consecutive words.  The
+// waves' totals are exchanged once per tile.  Within a tile the order is
+// therefore slot-major, not input order; the tile's matches stay contiguous.
+// A non-matching item is stored to a per-thread spare word, so the scatter
+// has no branches.
 template <int BLOCK, int IPT>
 __global__ __launch_bounds__(BLOCK) void select_buffered_kernel(const int32_t *__restrict__ in, int64_t n,
                                                                 int32_t lo, int32_t hi,
@@ -259,11 +268,10 @@ __global__ __launch_bounds__(BLOCK) void select_buffered_kernel(const int32_t *_
                                                                 int64_t *__restrict__ count_out,
                                                                 int64_t n_tiles) {
     using T = TileShape<BLOCK, IPT>;
-    constexpr int C = T::CHUNKS, W = T::WAVES, V = T::VEC;
-    constexpr int VBITS = V == 1 ? 1 : V == 2 ? 2 : 3;
+    constexpr int W = T::WAVES;
     constexpr uint32_t CAP = 2 * T::ITEMS;
-    extern __shared__ int32_t buf[];  // CAP entries
-    __shared__ uint32_t chunk_tot[C * W];
+    extern __shared__ int32_t buf[];  // CAP entries, then one spare word per thread
+    __shared__ uint32_t wave_tot[W];
     __shared__ uint64_t flush_off;
     const int w = threadIdx.x / kWave;
     const uint32_t lane = lane_id();
@@ -272,8 +280,18 @@ __global__ __launch_bounds__(BLOCK) void select_buffered_kernel(const int32_t *_
     auto flush = [&]() {
         if (threadIdx.x == 0) flush_off = atomic_add_u64((uint64_t *)count_out, fill);
         __syncthreads();
-        const uint64_t ob = flush_off;
-        for (uint32_t i = threadIdx.x; i < fill; i += BLOCK) __builtin_nontemporal_store(buf[i], out + ob + i);
+        int32_t *dst = out + flush_off;
+        // scalar stores up to a 16-byte boundary, vectors, then the tail
+        uint32_t head = (uint32_t)(((16u - ((uint32_t)(uintptr_t)dst & 15u)) & 15u) >> 2);
+        if (head > fill) head = fill;
+        if (threadIdx.x < head) __builtin_nontemporal_store(buf[threadIdx.x], dst + threadIdx.x);
+        const uint32_t nvec = (fill - head) >> 2;
+        for (uint32_t i = threadIdx.x; i < nvec; i += BLOCK) {
+            const uint32_t b = head + 4 * i;
+            const v4i x = {buf[b], buf[b + 1], buf[b + 2], buf[b + 3]};
+            __builtin_nontemporal_store(x, reinterpret_cast<v4i *>(dst + b));
+        }
+        for (uint32_t i = head + 4 * nvec + threadIdx.x; i < fill; i += BLOCK) __builtin_nontemporal_store(buf[i], dst + i);
         __syncthreads();  // buf and flush_off are reused
         fill = 0;
     };
@@ -281,50 +299,50 @@ __global__ __launch_bounds__(BLOCK) void select_buffered_kernel(const int32_t *_
     auto compact = [&](int64_t tile, const int32_t(&v)[IPT]) {
         const int64_t base = tile * T::ITEMS;
         const uint32_t flags = block_pred_range<IPT>(v, valid_mask<BLOCK, IPT>(base, n), lo, hi);
-        uint32_t pre[C];
+        uint32_t pos[IPT];
+        uint32_t wt = 0;  // the wave's matches so far (uniform)
 #pragma unroll
-        for (int c = 0; c < C; ++c) {
-            uint32_t wt;
-            pre[c] = wave_exclusive_scan_small<VBITS>((uint32_t)__popc((flags >> (c * V)) & T::VMASK), wt);
-            if (lane == 0) chunk_tot[c * W + w] = wt;
+        for (int k = 0; k < IPT; ++k) {
+            const uint64_t m = ballot((flags >> k) & 1u);
+            pos[k] = wt + count_below(m);
+            wt += (uint32_t)__popcll(m);
         }
+        if (lane == 0) wave_tot[w] = wt;
         __syncthreads();
-        uint32_t cbase[C];
-        uint32_t total = 0;
+        uint32_t before = 0, total = 0;
 #pragma unroll
-        for (int c = 0; c < C; ++c)
-#pragma unroll
-            for (int ww = 0; ww < W; ++ww) {
-                const uint32_t t = chunk_tot[c * W + ww];
-                if (ww == w) cbase[c] = total;
-                total += t;
-            }
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-            uint32_t pos = fill + cbase[c] + pre[c];
-#pragma unroll
-            for (int e = 0; e < V; ++e)
-                if ((flags >> (c * V + e)) & 1u) buf[pos++] = v[c * V + e];
+        for (int i = 0; i < W; ++i) {
+            const uint32_t t = wave_tot[i];
+            before += i < w ? t : 0u;
+            total += t;
         }
+        const uint32_t b0 = fill + before;
+        const uint32_t spare = CAP + threadIdx.x;
+#pragma unroll
+        for (int k = 0; k < IPT; ++k) buf[((flags >> k) & 1u) ? b0 + pos[k] : spare] = v[k];
         fill += total;
-        __syncthreads();  // chunk_tot is rewritten by the next tile; buf is complete
+        __syncthreads();  // wave_tot is rewritten by the next tile; buf is complete
         if (fill + T::ITEMS > CAP) flush();
     };
 
-    int32_t va[IPT], vb[IPT];
+    // three register buffers, rotated so that a buffer receiving loads is never copied
+    int32_t va[IPT], vb[IPT], vc[IPT];
     int64_t tile = blockIdx.x;
+    const int64_t g = gridDim.x;
     if (tile < n_tiles) block_load<BLOCK, IPT, true>(in, tile * T::ITEMS, n, va);
-    // unrolled by two so that the buffer receiving the next tile's loads is never copied
+    if (tile + g < n_tiles) block_load<BLOCK, IPT, true>(in, (tile + g) * T::ITEMS, n, vb);
     while (tile < n_tiles) {
-        int64_t nxt = tile + gridDim.x;
-        if (nxt < n_tiles) block_load<BLOCK, IPT, true>(in, nxt * T::ITEMS, n, vb);
+        if (tile + 2 * g < n_tiles) block_load<BLOCK, IPT, true>(in, (tile + 2 * g) * T::ITEMS, n, vc);
         compact(tile, va);
-        tile = nxt;
+        tile += g;
         if (tile >= n_tiles) break;
-        nxt = tile + gridDim.x;
-        if (nxt < n_tiles) block_load<BLOCK, IPT, true>(in, nxt * T::ITEMS, n, va);
+        if (tile + 2 * g < n_tiles) block_load<BLOCK, IPT, true>(in, (tile + 2 * g) * T::ITEMS, n, va);
         compact(tile, vb);
-        tile = nxt;
+        tile += g;
+        if (tile >= n_tiles) break;
+        if (tile + 2 * g < n_tiles) block_load<BLOCK, IPT, true>(in, (tile + 2 * g) * T::ITEMS, n, vb);
+        compact(tile, vc);
+        tile += g;
     }
     if (fill) flush();
 }
@@ -348,7 +366,7 @@ static hipError_t select_t(const LaunchCfg &cfg, const int32_t *in, int64_t n, i
         e = fill_u64((uint64_t *)count, 1, 0ull, s);
         if (e != hipSuccess) return e;
         // persistent: as many workgroups per CU as waves and the two-tile LDS buffer allow (or as tuned)
-        const size_t lds = (size_t)2 * T::ITEMS * sizeof(int32_t);
+        const size_t lds = ((size_t)2 * T::ITEMS + BLOCK) * sizeof(int32_t);
         int64_t per_cu = cfg.grid_per_cu > 0 ? cfg.grid_per_cu : (2048 / BLOCK > 0 ? 2048 / BLOCK : 1);
         const int64_t lds_cap = device_lds_per_cu() / (int64_t)(lds + 1024);
         if (per_cu > lds_cap) per_cu = lds_cap > 0 ? lds_cap : 1;
