@@ -57,7 +57,7 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-graph", action="store_true", help="star: launch eagerly instead of replaying HIP graphs")
     p.add_argument("--narrow", action="store_true",
-                   help="star: store the two dense-phase foreign keys as 16-bit offsets (compressed columns)")
+                   help="star: bit-packed dense-phase foreign keys: date keys as 12-bit day codes, fk1 as 16 bits")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
     p.add_argument("--tune", default="", help="kernel block,ipt,grid_per_cu override, e.g. 256,16,0")
     p.add_argument("--rates", default="50,200,500,1000,2000", help="serve: Poisson arrival rates (q/s)")
@@ -83,8 +83,17 @@ def host_info():
     return model, os.cpu_count()
 
 
-def lines_touched(mask: np.ndarray, item_bytes: int = 4, line: int = FETCH_BYTES) -> int:
-    """Number of `line`-byte lines of a column holding at least one live item."""
+def lines_touched(mask: np.ndarray, item_bytes: int = 4, line: int = FETCH_BYTES, bits: int = 0) -> int:
+    """Number of `line`-byte lines of a column holding at least one live item
+    (bits > 0: a bit-packed column; a field that straddles two lines touches
+    both)."""
+    if bits:
+        idx = np.flatnonzero(mask).astype(np.int64)
+        lb = 8 * line
+        touched = np.zeros((mask.size * bits + lb - 1) // lb + 1, dtype=bool)
+        touched[(idx * bits) // lb] = True
+        touched[(idx * bits + bits - 1) // lb] = True
+        return int(touched.sum())
     per = line // item_bytes
     n = mask.size
     pad = (-n) % per
@@ -93,16 +102,16 @@ def lines_touched(mask: np.ndarray, item_bytes: int = 4, line: int = FETCH_BYTES
     return int(mask.reshape(-1, per).any(axis=1).sum())
 
 
-def star_algorithmic_bytes(t, order, line=FETCH_BYTES, widths=None):
+def star_algorithmic_bytes(t, order, line=FETCH_BYTES, bits=None):
     """Bytes the selective scan must fetch: column s is read at the lines that
     hold an item still alive before step s; the measure at the survivors.
-    widths[j]: bytes per stored value of foreign-key column j (default 4)."""
+    bits[j]: bits per stored value of foreign-key column j (default 32)."""
     alive = np.ones(t.n, dtype=bool)
     total = 0
     for j in order:
         d = t.dims[j]
-        w = 4 if widths is None else widths[j]
-        total += lines_touched(alive, item_bytes=w, line=line) * line
+        b = 32 if bits is None else bits[j]
+        total += lines_touched(alive, line=line, bits=b if b != 32 else 0) * line
         kmin = int(d.key.min())
         keep = np.zeros(int(d.key.max()) - kmin + 1, dtype=bool)
         keep[d.key[d.filter == t.consts[j]] - kmin] = True
@@ -461,37 +470,67 @@ def main():
         t = datagen.star_tables(n=n, workload=3)
         print(f"# generated {n} fact rows in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
         s = queries.StarSchema(t)
-        plan = s.plan(order)
-        widths = None
+        bits = None
         if args.narrow:
-            # compressed layout: fk0 (date keys, span 61,130) and fk1 (0..39,999) as uint16 offsets
-            fk0, st0 = cx.pack_column(s.fk[0], int(t.dims[0].key.min()), 2)
-            fk1, st1 = cx.pack_column(s.fk[1], 0, 2)
+            # compressed layout (bit-packed): the date keys as 12-bit dictionary codes (the day's index
+            # from 1992-01-01, with the date table keyed by that code) and fk1 (0..39,999) as 16 bits
+            fk0, st0 = cx.pack_column_bits(queries.to_dev(datagen.day_codes(t.fk[0])), 0, 12)
+            fk1, st1 = cx.pack_column_bits(s.fk[1], 0, 16)
             cx.check_status(st0)
             cx.check_status(st1)
-            plan = cx.StarQuery([fk0, fk1, s.fk[2], s.fk[3], s.m1, s.m2], n_groups=queries.STAR_GROUPS,
-                                joins=plan.joins, agg=cx.AGG_SUM, agg_cols=(4, 0))
-            widths = [2, 2, 4, 4]
+            codes0 = queries.to_dev(datagen.day_codes(t.dims[0].key))
+            bits = [12, 16, 32, 32]
+
+        def table_set():
+            """One set of the four dimension tables, their filtered build items and the plan over them."""
+            tables = s.new_tables()
+            items = s.build_items(tables=tables)
+            plan = s.plan(order, tables=tables)
+            if args.narrow:
+                d0 = s.dims[0]
+                tables[0] = cx.HashTable(cx.HT_DIRECT, d0["n"], 0, datagen.N_DAYS - 1, has_payload=True)
+                items[0] = (tables[0], codes0, d0["year"], d0["filter"], (t.consts[0], t.consts[0]))
+                joins = [dict(jj, table=tables[0]) if jj["fk_col"] == 0 else jj for jj in plan.joins]
+                plan = cx.StarQuery([fk0, fk1, s.fk[2], s.fk[3], s.m1, s.m2], n_groups=queries.STAR_GROUPS,
+                                    joins=joins, agg=cx.AGG_SUM, agg_cols=(4, 0))
+            return tables, items, plan
+
+        # Two table sets used in turn: a step's single build launch builds one set (cleared by the
+        # previous step), clears the other set for the next step and zeroes the group array; the
+        # fused kernel then adds into it.  A step is two launches instead of four.
+        sets = [table_set(), table_set()]
         out = torch.empty(queries.STAR_GROUPS, dtype=torch.int64, device="cuda")
         status = cx.new_status()
         stream = torch.cuda.Stream()
         torch.cuda.synchronize()
+        k_step = [0]
+
+        def run_step(p):
+            tables, items, plan = sets[p]
+            cx.build_tables_fused(items, clear=sets[1 - p][0], zero=out, status=s.status, stream=stream)
+            plan.run(out=out, status=status, stream=stream, accumulate=True)
+
         with torch.cuda.stream(stream):
-            s.build(stream=stream)                      # eager first: caches device attributes
-            plan.run(out=out, status=status, stream=stream)
+            cx.build_tables_fused([], clear=sets[0][0] + sets[1][0], status=s.status, stream=stream)
+            run_step(0)                                 # eager first: caches device attributes
+            run_step(1)
             use_graph = not args.no_graph
             if use_graph:
-                # a step = the four filtered builds, then the fused kernel, replayed as one HIP graph
-                with cx.Graph.capture(stream) as g_step:
-                    s.build(stream=stream)
-                    plan.run(out=out, status=status, stream=stream)
+                # a step = the four filtered builds (with the other set's clear and the output's),
+                # then the fused kernel, replayed as one HIP graph per table set
+                graphs = []
+                for p in (0, 1):
+                    with cx.Graph.capture(stream) as g:
+                        run_step(p)
+                    graphs.append(g)
 
             def step():
+                p = k_step[0] % 2
+                k_step[0] += 1
                 if use_graph:
-                    g_step.launch(stream)
+                    graphs[p].launch(stream)
                 else:
-                    s.build(stream=stream)
-                    plan.run(out=out, status=status, stream=stream)
+                    run_step(p)
 
             for _ in range(W):
                 step()
@@ -504,6 +543,7 @@ def main():
             # the kernel's own duration: HIP events on its stream around K back-to-back eager
             # launches of the fused kernel alone (the query accumulates into the group array,
             # so nothing else runs between the events), averaged per launch
+            plan = sets[(k_step[0] - 1) % 2][2]                 # the set the last step built
             timer = Timer(torch)
             timer.run(lambda: [plan.run(out=out, status=status, stream=stream, accumulate=True)
                                for _ in range(K)], stream)
@@ -513,8 +553,8 @@ def main():
         cx.check_status(status)
         cx.check_status(s.status)
         kern_ms = timer.mean_ms() / K
-        alg_bytes, survivors = star_algorithmic_bytes(t, order, widths=widths)
-        alg_bytes_c64, _ = star_algorithmic_bytes(t, order, line=64, widths=widths)
+        alg_bytes, survivors = star_algorithmic_bytes(t, order, bits=bits)
+        alg_bytes_c64, _ = star_algorithmic_bytes(t, order, line=64, bits=bits)
         gpu_out = out.cpu().numpy()
         result.update(metric="fact rows/s & % HBM peak (fused star query); served queries/s + p99 latency",
                       value=n * K / elapsed, unit="rows/s", ms_per_step=elapsed / K * 1e3, dtype="int32",
@@ -523,9 +563,11 @@ def main():
                                           "to ~1/25 each, group by (year, dim3.group) -> 7000 int64",
                               "fact_rows": n, "join_order": list(order), "survivors": survivors,
                               "tile": list(cx.tune_get(cx.K_STAR, n)),
-                              "step": "4 filtered dimension builds + fused probe/aggregate kernel",
+                              "step": "4 filtered dimension builds (one launch, which also clears the other "
+                                      "table set and the group array) + fused probe/aggregate kernel",
                               "launch": "one hip graph per step" if use_graph else "eager",
-                              "columns": "fk0, fk1 uint16 offsets; others int32" if args.narrow else "int32"})
+                              "columns": ("fk0 12-bit date codes, fk1 16-bit, bit-packed; others int32" if args.narrow
+                                          else "int32")})
         roof.update(kernel="crystal::star_kernel", achieved=alg_bytes / (kern_ms * 1e-3) / 1e9,
                     algorithmic_bytes=alg_bytes, bytes_per_row=alg_bytes / n, kernel_ms=kern_ms,
                     kernel_rows_per_s=n / (kern_ms * 1e-3), algorithmic_bytes_c64=alg_bytes_c64,
@@ -565,7 +607,7 @@ def main():
         result["paper_context"] = ("SSB q2.1 (3 joins, 120M rows) on V100: 3.86 ms = 3.1e10 rows/s; "
                                    "GPU/CPU 25x on SSB (different hardware and workload)")
         if not args.no_serve:
-            del s, plan, t
+            del s, plan, t, sets
             torch.cuda.synchronize()
             torch.cuda.empty_cache()
             result["serving"] = serve(args, torch, cx, datagen, queries)

@@ -59,7 +59,7 @@ typedef struct crystal_range {
 const char *crystal_status_string(int32_t status);
 
 /* ABI version of this header (incremented on any layout change). */
-#define CRYSTAL_ABI_VERSION 7
+#define CRYSTAL_ABI_VERSION 9
 int32_t crystal_abi_version(void);
 
 /* sizeof of the ABI structs as compiled into the library, so a binding can
@@ -187,6 +187,27 @@ typedef struct {
 crystal_status crystal_ht_build_batch(const crystal_ht_build_item *items, int32_t n_items, int32_t *status,
                                       void *stream);
 
+/* The build phase of a repeated star query in one launch (section 5.3: the
+ * dimension builds before the probe kernel), for a caller that alternates
+ * between two sets of tables: the items' tables must already be clear (an
+ * earlier call listed them in `clear`), and the same launch
+ *   - builds every item, with the same result as crystal_ht_build_batch,
+ *   - clears the n_clear tables in `clear` (the other set, for the next call),
+ *   - sets the zero_n int64 at `zero` to 0 (e.g. the group array that a
+ *     following crystal_run_star_query_accumulate adds into; NULL when
+ *     zero_n is 0).
+ * So one step of a repeated query is two launches (this and the fused
+ * kernel) instead of four (clear, build, output clear, kernel).
+ * To start, clear both sets with a call that has no items.
+ * Errors (CRYSTAL_EINVAL, nothing launched): n_items or n_clear outside
+ * 0..CRYSTAL_MAX_BUILD_BATCH, an invalid descriptor, zero_n < 0, zero NULL
+ * or not 8-byte aligned with zero_n > 0, or any two of the items' tables, the cleared tables and
+ * the zeroed range sharing memory.  `clear` and the descriptors are host
+ * memory; table memory, columns, `zero` and `status` are device memory. */
+crystal_status crystal_ht_build_batch_fused(const crystal_ht_build_item *items, int32_t n_items,
+                                            const crystal_ht *const *clear, int32_t n_clear, int64_t *zero,
+                                            int64_t zero_n, int32_t *status, void *stream);
+
 crystal_status crystal_ht_probe(const crystal_ht *ht, const int32_t *fk,
                                 const int32_t *probe_payload, int64_t n,
                                 int64_t *out_sum, int64_t *out_matches, void *stream);
@@ -254,12 +275,17 @@ typedef struct crystal_join {
 } crystal_join;
 
 /* Storage of one fact column (compressed columns, section 5.5's outlook:
- * fewer HBM bytes for a little ALU).  width 0 or 4: int32 values; width 2
- * or 1: uint16 or uint8 offsets from `base` (frame of reference), value =
- * base + stored.  crystal_pack_column writes such a column. */
+ * fewer HBM bytes for a little ALU).  bits == 0: width 0 or 4 means int32
+ * values; width 2 or 1 means uint16 or uint8 offsets from `base` (frame of
+ * reference), value = base + stored; crystal_pack_column writes such a
+ * column.  bits in 1..16 (width 0): a bit-packed column, written by
+ * crystal_pack_column_bits: value = base + the `bits`-bit field of the row
+ * (layout below). */
 typedef struct crystal_col_format {
     int32_t width;
     int32_t base;
+    int32_t bits;
+    int32_t reserved;
 } crystal_col_format;
 
 typedef struct crystal_star_query {
@@ -328,6 +354,22 @@ crystal_status crystal_run_star_query_noalloc(const crystal_star_query *q, int64
  * shared-scan batch and the server take int32 columns only (CRYSTAL_EINVAL). */
 crystal_status crystal_pack_column(const int32_t *in, int64_t n, int32_t base, int32_t width, void *out,
                                    int32_t *status, void *stream);
+
+/* Bit-packed frame-of-reference column.  The packed form is a stream of
+ * 32-bit words, least significant bit first: row i's field in[i] - base
+ * occupies stream bits [i * bits, (i + 1) * bits), and stream bit j is bit
+ * (j mod 32) of word floor(j / 32).  The buffer holds
+ * ceil(n * bits / 32) words and four zero words of padding (readers load
+ * whole words past a row's last bit):
+ * crystal_packed_column_bytes(n, bits) bytes, 0 when bits is outside 1..16
+ * or n < 0.  in: device int32[n], 16-byte aligned; out: device, 16-byte
+ * aligned, that many bytes, fully written.  A value outside
+ * [base, base + 2^bits - 1] is stored truncated to its low bits and sets
+ * *status (device) to CRYSTAL_ERANGE.  Read by
+ * crystal_run_star_query(_accumulate) through crystal_col_format.bits. */
+size_t crystal_packed_column_bytes(int64_t n, int32_t bits);
+crystal_status crystal_pack_column_bits(const int32_t *in, int64_t n, int32_t base, int32_t bits, void *out,
+                                        int32_t *status, void *stream);
 
 /* ------------------------------------------------------------------------ */
 /* Shared-scan batches: up to CRYSTAL_MAX_BATCH queries of one star-query    */

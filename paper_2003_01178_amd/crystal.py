@@ -55,7 +55,7 @@ MAX_BUILD_BATCH = 8
 
 
 class ColFormatC(ctypes.Structure):
-    _fields_ = [("width", c_i32), ("base", c_i32)]
+    _fields_ = [("width", c_i32), ("base", c_i32), ("bits", c_i32), ("reserved", c_i32)]
 
 
 class StarQueryC(ctypes.Structure):
@@ -131,6 +131,7 @@ def _declare(lib):
         "crystal_ht_bytes": (ctypes.c_size_t, [P(HT)]),
         "crystal_ht_build": (c_i32, [P(HT), c_vp, c_vp, c_vp, Range, c_i64, c_vp, c_vp]),
         "crystal_ht_build_batch": (c_i32, [P(BuildItemC), c_i32, c_vp, c_vp]),
+        "crystal_ht_build_batch_fused": (c_i32, [P(BuildItemC), c_i32, P(P(HT)), c_i32, c_vp, c_i64, c_vp, c_vp]),
         "crystal_ht_probe": (c_i32, [P(HT), c_vp, c_vp, c_i64, c_vp, c_vp, c_vp]),
         "crystal_groupby_agg": (c_i32, [c_vp, c_vp, c_i64, c_i64, c_vp, c_vp, c_vp]),
         "crystal_star_query_scratch_bytes": (ctypes.c_size_t, [P(StarQueryC)]),
@@ -138,6 +139,8 @@ def _declare(lib):
         "crystal_run_star_query_accumulate": (c_i32, [P(StarQueryC), c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp]),
         "crystal_run_star_query_noalloc": (c_i32, [P(StarQueryC), c_vp, c_vp, c_vp]),
         "crystal_pack_column": (c_i32, [c_vp, c_i64, c_i32, c_i32, c_vp, c_vp, c_vp]),
+        "crystal_packed_column_bytes": (ctypes.c_size_t, [c_i64, c_i32]),
+        "crystal_pack_column_bits": (c_i32, [c_vp, c_i64, c_i32, c_i32, c_vp, c_vp, c_vp]),
         "crystal_qmask_bytes": (ctypes.c_size_t, [c_i64]),
         "crystal_qmask_ranked_bytes": (ctypes.c_size_t, [c_i64, c_i32]),
         "crystal_qmask_rank": (c_i32, [P(QmaskTableC), c_vp, c_i64, c_vp, c_vp]),
@@ -327,17 +330,10 @@ class HashTable:
         return out
 
 
-def build_tables(items, status=None, stream=None):
-    """Build several tables with one clear launch and one build launch.
-
-    items: (HashTable, keys, payload or None, filter_col or None, (lo, hi)) per table."""
-    lib = load()
-    if not items:
-        return status
+def _build_items(items):
     if len(items) > MAX_BUILD_BATCH:
         raise ValueError("at most 8 tables per batch")
-    arr = (BuildItemC * len(items))()
-    keep = []
+    arr = (BuildItemC * max(1, len(items)))()
     for i, (ht, keys, payload, filter_col, rng) in enumerate(items):
         for extra in (payload, filter_col):
             if extra is not None and extra.numel() != keys.numel():
@@ -348,10 +344,42 @@ def build_tables(items, status=None, stream=None):
         arr[i].filter_col = _col(filter_col) if filter_col is not None else None
         arr[i].filter = Range(int(rng[0]), int(rng[1]))
         arr[i].n = keys.numel()
-        keep.append(ht)
+    return arr
+
+
+def build_tables(items, status=None, stream=None):
+    """Build several tables with one clear launch and one build launch.
+
+    items: (HashTable, keys, payload or None, filter_col or None, (lo, hi)) per table."""
+    lib = load()
+    if not items:
+        return status
+    arr = _build_items(items)
     dev = items[0][1].device
     status = new_status(dev) if status is None else status
     _check(lib.crystal_ht_build_batch(arr, len(items), _ptr(status), _stream(stream)), "crystal_ht_build_batch")
+    return status
+
+
+def build_tables_fused(items, clear=(), zero=None, status=None, stream=None):
+    """One launch: build `items` into tables that are already clear, clear the
+    HashTables in `clear`, and zero the int64 tensor `zero` (if given)."""
+    lib = load()
+    if len(clear) > MAX_BUILD_BATCH:
+        raise ValueError("at most 8 tables to clear")
+    arr = _build_items(items)
+    carr = (ctypes.POINTER(HT) * max(1, len(clear)))()
+    for i, ht in enumerate(clear):
+        carr[i] = ctypes.pointer(ht.desc)
+    if zero is not None and zero.dtype != torch.int64:
+        raise ValueError("zero must be an int64 tensor")
+    if status is None:
+        dev = items[0][1].device if items else (zero.device if zero is not None else clear[0].mem.device)
+        status = new_status(dev)
+    _check(lib.crystal_ht_build_batch_fused(arr, len(items), carr, len(clear),
+                                            _ptr(zero) if zero is not None else None,
+                                            zero.numel() if zero is not None else 0, _ptr(status),
+                                            _stream(stream)), "crystal_ht_build_batch_fused")
     return status
 
 
@@ -368,16 +396,38 @@ def groupby_agg(group, value, n_groups, out=None, status=None, stream=None):
 
 class Narrow:
     """A narrow fact column: stored uint8 or uint16 offsets (a uint8 or int16
-    tensor holding the bits) from `base`."""
+    tensor holding the bits) from `base`, or, with `bits`, a bit-packed
+    stream of `bits`-bit offsets (an int32 tensor of words) for n rows."""
 
-    def __init__(self, data, base):
-        if data.dtype not in (torch.uint8, torch.int16):
-            raise TypeError("narrow columns hold uint8 or 16-bit data")
-        self.data, self.base = data, int(base)
-        self.width = 1 if data.dtype == torch.uint8 else 2
+    def __init__(self, data, base, bits=0, n=None):
+        self.data, self.base, self.bits = data, int(base), int(bits)
+        if self.bits:
+            if data.dtype != torch.int32 or n is None:
+                raise TypeError("bit-packed columns hold int32 words and a row count")
+            self.width, self.n = 0, int(n)
+        else:
+            if data.dtype not in (torch.uint8, torch.int16):
+                raise TypeError("narrow columns hold uint8 or 16-bit data")
+            self.width, self.n = (1 if data.dtype == torch.uint8 else 2), data.numel()
 
     def numel(self):
-        return self.data.numel()
+        return self.n
+
+
+def pack_column_bits(x, base, bits, status=None, stream=None):
+    """Bit-packed copy of an int32 column: `bits`-bit offsets from `base`
+    (1 <= bits <= 16).  Returns (Narrow, status); status is CRYSTAL_ERANGE if
+    a value does not fit."""
+    lib = load()
+    n = x.numel()
+    nbytes = lib.crystal_packed_column_bytes(n, int(bits))
+    if nbytes == 0:
+        raise ValueError("bits must be in 1..16")
+    data = torch.empty(nbytes // 4, dtype=torch.int32, device=x.device)
+    status = new_status(x.device) if status is None else status
+    _check(lib.crystal_pack_column_bits(_col(x), n, int(base), int(bits), c_vp(data.data_ptr()), _ptr(status),
+                                        _stream(stream)), "crystal_pack_column_bits")
+    return Narrow(data, base, bits=bits, n=n), status
 
 
 def pack_column(x, base, width, status=None, stream=None):
@@ -415,7 +465,7 @@ class StarQuery:
         for i, c in enumerate(cols):
             if isinstance(c, Narrow):
                 q.cols[i] = c.data.data_ptr()
-                q.formats[i] = ColFormatC(c.width, c.base)
+                q.formats[i] = ColFormatC(c.width, c.base, c.bits, 0)
             else:
                 q.cols[i] = c.data_ptr()
         q.n_rows, q.n_cols, q.n_preds, q.n_joins = n, len(cols), len(preds), len(joins)

@@ -184,6 +184,89 @@ __device__ __forceinline__ void block_load_sel_narrow(const E *__restrict__ col,
     }
 }
 
+// Bit-packed (frame-of-reference) columns: a stream of 32-bit words, least
+// significant bit first; row i's field occupies stream bits
+// [i * bits, (i + 1) * bits), bits <= 16.  The buffer carries four zero words
+// after the last field, so a reader may load whole words past it.
+
+// Field of one row: the two words that hold it, funnel-shifted.
+__device__ __forceinline__ int32_t packed_value(const uint32_t *__restrict__ w, int32_t cbase, uint32_t bits,
+                                                int64_t row) {
+    const uint64_t o = (uint64_t)row * bits;
+    const uint32_t *p = w + (o >> 5);
+    const uint32_t f = __builtin_amdgcn_alignbit(p[1], p[0], (uint32_t)o & 31u);
+    return cbase + (int32_t)(f & ((1u << bits) - 1u));
+}
+
+// Four consecutive fields whose first starts at bit s (< 32) of the window
+// x2:x1:x0 (4 * bits <= 64, so three words hold them).  Two funnel shifts
+// move the window to bit 0 (fields at 0, b, 2b, 3b of y1:y0); one 64-bit
+// shift by 2b <= 32 brings fields 2 and 3 down to 0 and b of z.  Only the
+// low five bits of s are used.
+__device__ __forceinline__ void decode_packed_vec4(uint32_t x0, uint32_t x1, uint32_t x2, uint32_t s, uint32_t bits,
+                                                   int32_t cbase, int32_t *dst) {
+    const uint32_t y0 = __builtin_amdgcn_alignbit(x1, x0, s);
+    const uint32_t y1 = __builtin_amdgcn_alignbit(x2, x1, s);
+    const uint32_t z = (uint32_t)((((uint64_t)y1 << 32) | y0) >> (2u * bits));
+    const uint32_t mask = (1u << bits) - 1u;
+    dst[0] = cbase + (int32_t)(y0 & mask);
+    dst[1] = cbase + (int32_t)((y0 >> bits) & mask);
+    dst[2] = cbase + (int32_t)(z & mask);
+    dst[3] = cbase + (int32_t)((z >> bits) & mask);
+}
+
+// VEC = 4 consecutive rows starting at r0.
+template <bool NT>
+__device__ __forceinline__ void load_packed_vec4(const uint32_t *__restrict__ w, int32_t cbase, uint32_t bits,
+                                                 int64_t r0, int32_t *dst) {
+    const uint64_t o = (uint64_t)r0 * bits;
+    const uint32_t *p = w + (o >> 5);
+    const uint32_t x0 = NT ? __builtin_nontemporal_load(p) : p[0];
+    const uint32_t x1 = NT ? __builtin_nontemporal_load(p + 1) : p[1];
+    const uint32_t x2 = NT ? __builtin_nontemporal_load(p + 2) : p[2];
+    decode_packed_vec4(x0, x1, x2, (uint32_t)o, bits, cbase, dst);
+}
+
+// BlockLoad / BlockLoadSel of a bit-packed column (VEC = 4 tiles only).
+template <int BLOCK, int IPT, bool NT>
+__device__ __forceinline__ void block_load_packed(const uint32_t *__restrict__ w, int32_t cbase, uint32_t bits,
+                                                  int64_t base, int64_t n, int32_t (&v)[IPT]) {
+    using T = TileShape<BLOCK, IPT>;
+    static_assert(T::VEC == 4, "bit-packed columns are read four rows at a time");
+    if (base + T::ITEMS <= n) {
+#pragma unroll
+        for (int c = 0; c < T::CHUNKS; ++c) load_packed_vec4<NT>(w, cbase, bits, T::index(base, c, 0), &v[c * 4]);
+    } else {
+#pragma unroll
+        for (int c = 0; c < T::CHUNKS; ++c)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t i = T::index(base, c, e);
+                v[c * 4 + e] = i < n ? packed_value(w, cbase, bits, i) : 0;
+            }
+    }
+}
+
+template <int BLOCK, int IPT, bool NT>
+__device__ __forceinline__ void block_load_sel_packed(const uint32_t *__restrict__ w, int32_t cbase, uint32_t bits,
+                                                      int64_t base, int64_t n, uint32_t flags, int32_t (&v)[IPT]) {
+    using T = TileShape<BLOCK, IPT>;
+    static_assert(T::VEC == 4, "bit-packed columns are read four rows at a time");
+    const bool full = base + T::ITEMS <= n;
+#pragma unroll
+    for (int c = 0; c < T::CHUNKS; ++c) {
+        const uint32_t m = (flags >> (c * 4)) & 0xFu;
+        if (!m) continue;
+        if (full) {
+            load_packed_vec4<NT>(w, cbase, bits, T::index(base, c, 0), &v[c * 4]);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (m & (1u << e)) v[c * 4 + e] = packed_value(w, cbase, bits, T::index(base, c, e));
+        }
+    }
+}
+
 // ---------------------------------------------------------- BlockPred ------
 __device__ __forceinline__ bool in_range(int32_t x, int32_t lo, int32_t hi) {
     return x >= lo && x <= hi;

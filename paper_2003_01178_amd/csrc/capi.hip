@@ -151,10 +151,12 @@ crystal_status star_plan_to_dev(const crystal_star_query &q, StarPlanDev &d) {
     for (int c = 0; c < q.n_cols; ++c) {
         if (q.cols[c] && !aligned16(q.cols[c])) return CRYSTAL_EINVAL;
         d.col[c].p = q.cols[c];
-        const int32_t w = q.formats[c].width;
+        const int32_t w = q.formats[c].width, nb = q.formats[c].bits;
         if (w != 0 && w != 1 && w != 2 && w != 4) return CRYSTAL_EINVAL;
-        d.col[c].width = w == 0 ? 4 : w;
-        d.col[c].base = w == 1 || w == 2 ? q.formats[c].base : 0;
+        if (nb < 0 || nb > 16 || (nb > 0 && w != 0)) return CRYSTAL_EINVAL;
+        d.col[c].width = nb > 0 ? 0 : w == 0 ? 4 : w;
+        d.col[c].bits = nb;
+        d.col[c].base = nb > 0 || w == 1 || w == 2 ? q.formats[c].base : 0;
     }
     for (int c = q.n_cols; c < CRYSTAL_MAX_COLS; ++c) d.col[c].width = 4;
     d.n_rows = q.n_rows;
@@ -354,6 +356,38 @@ crystal_status crystal_ht_build_batch(const crystal_ht_build_item *items, int32_
     return from_hip(launch_ht_build_batch(items, n_items, status, as_stream(stream)));
 }
 
+crystal_status crystal_ht_build_batch_fused(const crystal_ht_build_item *items, int32_t n_items,
+                                            const crystal_ht *const *clear, int32_t n_clear, int64_t *zero,
+                                            int64_t zero_n, int32_t *status, void *stream) {
+    if (!status || n_items < 0 || n_items > CRYSTAL_MAX_BUILD_BATCH || n_clear < 0 ||
+        n_clear > CRYSTAL_MAX_BUILD_BATCH || (n_items > 0 && !items) || (n_clear > 0 && !clear) || zero_n < 0 ||
+        (zero_n > 0 && (!zero || ((uintptr_t)zero & 7u))))
+        return CRYSTAL_EINVAL;
+    // every memory range the launch writes: the items' tables, the cleared tables, the zeroed words
+    struct Span {
+        uintptr_t lo, hi;
+    };
+    Span spans[2 * CRYSTAL_MAX_BUILD_BATCH + 1];
+    int n_spans = 0;
+    for (int i = 0; i < n_items; ++i) {
+        const crystal_ht_build_item &it = items[i];
+        if (!it.ht || !ht_valid(*it.ht) || it.n < 0 || (it.n > 0 && !it.keys) ||
+            (it.ht->has_payload && it.n > 0 && !it.payload))
+            return CRYSTAL_EINVAL;
+        spans[n_spans++] = {(uintptr_t)it.ht->mem, (uintptr_t)it.ht->mem + crystal_ht_bytes(it.ht)};
+    }
+    for (int i = 0; i < n_clear; ++i) {
+        if (!clear[i] || !ht_valid(*clear[i])) return CRYSTAL_EINVAL;
+        spans[n_spans++] = {(uintptr_t)clear[i]->mem, (uintptr_t)clear[i]->mem + crystal_ht_bytes(clear[i])};
+    }
+    if (zero_n > 0) spans[n_spans++] = {(uintptr_t)zero, (uintptr_t)zero + (uintptr_t)zero_n * 8};
+    for (int i = 0; i < n_spans; ++i)
+        for (int j = 0; j < i; ++j)
+            if (spans[i].lo < spans[j].hi && spans[j].lo < spans[i].hi) return CRYSTAL_EINVAL;
+    return from_hip(launch_ht_build_batch_fused(items, n_items, clear, n_clear, zero, zero_n, status,
+                                                as_stream(stream)));
+}
+
 crystal_status crystal_ht_probe(const crystal_ht *ht, const int32_t *fk, const int32_t *probe_payload,
                                 int64_t n, int64_t *out_sum, int64_t *out_matches, void *stream) {
     if (!ht || !ht_valid(*ht) || n < 0 || !out_sum || !out_matches || (n > 0 && (!fk || !aligned16(fk))) ||
@@ -417,6 +451,19 @@ crystal_status crystal_run_star_query_noalloc(const crystal_star_query *q, int64
     }
     return from_hip(launch_star(tune_lookup(CRYSTAL_K_STAR, q->n_rows), d, (uint64_t *)out, status, partials,
                                 false, as_stream(stream)));
+}
+
+size_t crystal_packed_column_bytes(int64_t n, int32_t bits) {
+    if (n < 0 || bits < 1 || bits > 16) return 0;
+    return (size_t)(((n * bits + 31) / 32 + 4) * 4);
+}
+
+crystal_status crystal_pack_column_bits(const int32_t *in, int64_t n, int32_t base, int32_t bits, void *out,
+                                        int32_t *status, void *stream) {
+    if (n < 0 || bits < 1 || bits > 16 || !status || !out || !aligned16(out) || (n > 0 && (!in || !aligned16(in))))
+        return CRYSTAL_EINVAL;
+    const int64_t words = (int64_t)crystal_packed_column_bytes(n, bits) / 4;
+    return from_hip(launch_pack_column_bits(in, n, base, bits, (uint32_t *)out, words, status, as_stream(stream)));
 }
 
 crystal_status crystal_pack_column(const int32_t *in, int64_t n, int32_t base, int32_t width, void *out,

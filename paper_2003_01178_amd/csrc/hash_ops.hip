@@ -104,16 +104,36 @@ struct ClearRange {
     uint64_t value;
 };
 
+// up to kMaxBuildBatch tables, and one more range (an output to zero)
 struct ClearBatch {
     int32_t count;
-    ClearRange r[kMaxBuildBatch];
+    ClearRange r[kMaxBuildBatch + 1];
 };
 
-__global__ __launch_bounds__(256) void clear_batch_kernel(ClearBatch b) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// the clears, spread over `blocks` workgroups of which this is `block`
+__device__ __forceinline__ void clear_part(const ClearBatch &b, int64_t block, int64_t blocks) {
+    const int64_t stride = blocks * blockDim.x;
+    const int64_t g0 = block * blockDim.x + threadIdx.x;
     for (int r = 0; r < b.count; ++r)
         for (int64_t i = g0; i < b.r[r].n; i += stride) b.r[r].p[i] = b.r[r].value;
+}
+
+__global__ __launch_bounds__(256) void clear_batch_kernel(ClearBatch b) {
+    clear_part(b, blockIdx.x, gridDim.x);
+}
+
+// clear memory of a table, as crystal_ht_clear would leave it
+ClearRange table_clear_range(const crystal_ht &ht) {
+    ClearRange c;
+    c.p = (uint64_t *)ht.mem;
+    if (ht.kind == CRYSTAL_HT_DIRECT) {
+        c.n = direct_bitmap_words(ht.capacity) / 2;  // an even number of 32-bit words
+        c.value = 0;
+    } else {
+        c.n = ht.capacity;
+        c.value = kEmptySlot;
+    }
+    return c;
 }
 
 struct BuildItemDev {
@@ -131,12 +151,13 @@ struct BuildBatch {
     BuildItemDev it[kMaxBuildBatch];
 };
 
-__global__ __launch_bounds__(256) void build_batch_kernel(BuildBatch b, int32_t *status) {
+// workgroup `block` of the build part: its item's range of workgroups strides over that item's rows
+__device__ __forceinline__ void build_part(const BuildBatch &b, int64_t block, int32_t *status) {
     int r = 0;
-    while (r + 1 < b.count && (int64_t)blockIdx.x >= b.it[r + 1].block0) ++r;
+    while (r + 1 < b.count && block >= b.it[r + 1].block0) ++r;
     const BuildItemDev &it = b.it[r];
     const int64_t stride = it.blocks * blockDim.x;
-    for (int64_t i = ((int64_t)blockIdx.x - it.block0) * blockDim.x + threadIdx.x; i < it.n; i += stride) {
+    for (int64_t i = (block - it.block0) * blockDim.x + threadIdx.x; i < it.n; i += stride) {
         if (it.t.kind == CRYSTAL_HT_DIRECT)
             build_row<CRYSTAL_HT_DIRECT>(it.t, it.keys, it.payload, it.filter, it.flo, it.fhi, i, status);
         else
@@ -144,25 +165,29 @@ __global__ __launch_bounds__(256) void build_batch_kernel(BuildBatch b, int32_t 
     }
 }
 
-hipError_t launch_ht_build_batch(const crystal_ht_build_item *items, int n_items, int32_t *status,
-                                 hipStream_t s) {
-    ClearBatch cb = {};
-    BuildBatch bb = {};
-    int64_t clear_words = 0, blocks = 0;
+__global__ __launch_bounds__(256) void build_batch_kernel(BuildBatch b, int32_t *status) {
+    build_part(b, blockIdx.x, status);
+}
+
+// Builds into tables that are already clear, and, in other workgroups of the
+// same launch, clears of memory no build touches: the first build_blocks
+// workgroups build, the rest clear.
+__global__ __launch_bounds__(256) void build_clear_kernel(BuildBatch b, ClearBatch c, int64_t build_blocks,
+                                                          int32_t *status) {
+    const int64_t block = blockIdx.x;
+    if (block < build_blocks)
+        build_part(b, block, status);
+    else
+        clear_part(c, block - build_blocks, (int64_t)gridDim.x - build_blocks);
+}
+
+// build items of a batch with their workgroup ranges; returns the workgroups used
+static int64_t fill_build_batch(const crystal_ht_build_item *items, int n_items, BuildBatch &bb) {
+    int64_t blocks = 0;
     const int64_t cap = (int64_t)device_cu_count() * 32;
     for (int i = 0; i < n_items; ++i) {
-        const crystal_ht &ht = *items[i].ht;
-        ClearRange &c = cb.r[cb.count++];
-        c.p = (uint64_t *)ht.mem;
-        if (ht.kind == CRYSTAL_HT_DIRECT) {
-            c.n = direct_bitmap_words(ht.capacity) / 2;  // an even number of 32-bit words
-            c.value = 0;
-        } else {
-            c.n = ht.capacity;
-            c.value = kEmptySlot;
-        }
-        clear_words = c.n > clear_words ? c.n : clear_words;
         if (items[i].n == 0) continue;
+        const crystal_ht &ht = *items[i].ht;
         BuildItemDev &d = bb.it[bb.count++];
         d.t = to_dev(ht);
         d.keys = items[i].keys;
@@ -177,14 +202,58 @@ hipError_t launch_ht_build_batch(const crystal_ht_build_item *items, int n_items
         d.blocks = nb;
         blocks += nb;
     }
+    return blocks;
+}
+
+// workgroups for clearing `words` 64-bit words at most per range
+static int64_t clear_grid(int64_t words) {
+    const int64_t cap = (int64_t)device_cu_count() * 32;
+    int64_t g = (words + 255) / 256;
+    if (g > cap) g = cap;
+    return g < 1 ? 1 : g;
+}
+
+hipError_t launch_ht_build_batch(const crystal_ht_build_item *items, int n_items, int32_t *status,
+                                 hipStream_t s) {
+    ClearBatch cb = {};
+    BuildBatch bb = {};
+    int64_t clear_words = 0;
+    for (int i = 0; i < n_items; ++i) {
+        ClearRange &c = cb.r[cb.count++];
+        c = table_clear_range(*items[i].ht);
+        clear_words = c.n > clear_words ? c.n : clear_words;
+    }
     if (cb.count == 0) return hipSuccess;
-    int64_t cgrid = (clear_words + 255) / 256;
-    if (cgrid > cap) cgrid = cap;
-    if (cgrid < 1) cgrid = 1;
-    hipLaunchKernelGGL(clear_batch_kernel, dim3((unsigned)cgrid), dim3(256), 0, s, cb);
+    const int64_t blocks = fill_build_batch(items, n_items, bb);
+    hipLaunchKernelGGL(clear_batch_kernel, dim3((unsigned)clear_grid(clear_words)), dim3(256), 0, s, cb);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || bb.count == 0) return e;
     hipLaunchKernelGGL(build_batch_kernel, dim3((unsigned)blocks), dim3(256), 0, s, bb, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_ht_build_batch_fused(const crystal_ht_build_item *items, int n_items, const crystal_ht *const *clear,
+                                       int n_clear, int64_t *zero, int64_t zero_n, int32_t *status, hipStream_t s) {
+    ClearBatch cb = {};
+    BuildBatch bb = {};
+    int64_t clear_words = 0;
+    for (int i = 0; i < n_clear; ++i) {
+        ClearRange &c = cb.r[cb.count++];
+        c = table_clear_range(*clear[i]);
+        clear_words = c.n > clear_words ? c.n : clear_words;
+    }
+    if (zero_n > 0) {
+        ClearRange &c = cb.r[cb.count++];
+        c.p = (uint64_t *)zero;
+        c.n = zero_n;
+        c.value = 0;
+        clear_words = c.n > clear_words ? c.n : clear_words;
+    }
+    const int64_t build_blocks = fill_build_batch(items, n_items, bb);
+    const int64_t clear_blocks = cb.count ? clear_grid(clear_words) : 0;
+    if (build_blocks + clear_blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(build_clear_kernel, dim3((unsigned)(build_blocks + clear_blocks)), dim3(256), 0, s, bb, cb,
+                       build_blocks, status);
     return hipGetLastError();
 }
 

@@ -48,6 +48,8 @@ hipError_t fill_u32(uint32_t *p, int64_t n, uint32_t value, hipStream_t s);
 // Zero two separate 64-bit words with one launch.
 hipError_t zero_pair(uint64_t *a, uint64_t *b, hipStream_t s);
 
+hipError_t launch_pack_column_bits(const int32_t *in, int64_t n, int32_t base, int32_t bits, uint32_t *out,
+                                   int64_t words, int32_t *status, hipStream_t s);
 hipError_t launch_pack_column(const int32_t *in, int64_t n, int32_t base, int32_t width, void *out,
                               int32_t *status, hipStream_t s);
 hipError_t launch_select(const LaunchCfg &cfg, const int32_t *in, int64_t n, int32_t lo, int32_t hi,
@@ -66,6 +68,10 @@ hipError_t launch_ht_build(const crystal_ht &ht, const int32_t *keys, const int3
 constexpr int kMaxBuildBatch = CRYSTAL_MAX_BUILD_BATCH;
 hipError_t launch_ht_build_batch(const crystal_ht_build_item *items, int n_items, int32_t *status,
                                  hipStream_t s);
+// The builds of a batch into tables that are already clear, the clears of
+// other tables and the zeroing of zero_n int64 words, in one launch.
+hipError_t launch_ht_build_batch_fused(const crystal_ht_build_item *items, int n_items, const crystal_ht *const *clear,
+                                       int n_clear, int64_t *zero, int64_t zero_n, int32_t *status, hipStream_t s);
 hipError_t launch_ht_probe(const LaunchCfg &cfg, const crystal_ht &ht, const int32_t *fk,
                            const int32_t *probe_payload, int64_t n, uint64_t *sum, uint64_t *count,
                            hipStream_t s);
@@ -102,8 +108,10 @@ struct StarJoinDev {
 // the kernel argument in the kernel-argument segment.)
 struct ColDev {
     const int32_t *p;
-    int32_t width;
+    int32_t width;  // bytes per stored value (4, 2 or 1); 0 for a bit-packed column
     int32_t base;
+    int32_t bits;   // bit-packed: bits per value (1..16); 0 otherwise
+    int32_t reserved;
 };
 
 struct StarPlanDev {

@@ -502,6 +502,46 @@ __global__ __launch_bounds__(256) void pack_column_kernel(const int32_t *__restr
     if (bad) set_status(status, CRYSTAL_ERANGE);
 }
 
+// Bit-packed column: each thread assembles whole output words, so no word is
+// written twice and no atomics are needed.  A row's range check is made by
+// the word that holds its first bit; the padding words are written as zero.
+__global__ __launch_bounds__(256) void pack_bits_kernel(const int32_t *__restrict__ in, int64_t n, int32_t base,
+                                                        uint32_t bits, uint32_t *__restrict__ out, int64_t words,
+                                                        int32_t *status) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const uint32_t mask = (1u << bits) - 1u;  // bits <= 16
+    bool bad = false;
+    for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < words; w += stride) {
+        const int64_t b0 = w * 32;  // the stream bits of word w: [b0, b0 + 32)
+        int64_t i0 = b0 / bits, i1 = (b0 + 32 + bits - 1) / bits;
+        if (i1 > n) i1 = n;
+        uint32_t word = 0;
+        for (int64_t i = i0; i < i1; ++i) {
+            const uint32_t d = (uint32_t)in[i] - (uint32_t)base;
+            const int64_t sh = i * (int64_t)bits - b0;  // > -bits and < 32
+            if (sh >= 0) {
+                bad |= in[i] < base || d > mask;
+                word |= (d & mask) << sh;
+            } else {
+                word |= (d & mask) >> (-sh);
+            }
+        }
+        out[w] = word;
+    }
+    if (bad) set_status(status, CRYSTAL_ERANGE);
+}
+
+hipError_t launch_pack_column_bits(const int32_t *in, int64_t n, int32_t base, int32_t bits, uint32_t *out,
+                                   int64_t words, int32_t *status, hipStream_t s) {
+    int64_t grid = (words + 255) / 256;
+    const int64_t cap = (int64_t)device_cu_count() * 16;
+    if (grid > cap) grid = cap;
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(pack_bits_kernel, dim3((unsigned)grid), dim3(256), 0, s, in, n, base, (uint32_t)bits, out,
+                       words, status);
+    return hipGetLastError();
+}
+
 hipError_t launch_pack_column(const int32_t *in, int64_t n, int32_t base, int32_t width, void *out,
                               int32_t *status, hipStream_t s) {
     int64_t grid = (n + 255) / 256;

@@ -41,7 +41,8 @@ __device__ __forceinline__ int step_col(const StarPlanDev &p, int s) {
 // Column access for int32 and narrow (uint16 / uint8 offset) columns; the
 // width is uniform, so the dispatch is a scalar branch.
 __device__ __forceinline__ int32_t col_value(const StarPlanDev &p, int c, int64_t row) {
-    const ColDev &cd = p.col[c];
+    const ColDev cd = p.col[c];  // a copy: keeps the plan in the kernel-argument segment
+    if (cd.bits) return packed_value(reinterpret_cast<const uint32_t *>(cd.p), cd.base, (uint32_t)cd.bits, row);
     if (cd.width == 2) return cd.base + (int32_t)reinterpret_cast<const uint16_t *>(cd.p)[row];
     if (cd.width == 1) return cd.base + (int32_t)reinterpret_cast<const uint8_t *>(cd.p)[row];
     return cd.p[row];
@@ -49,9 +50,10 @@ __device__ __forceinline__ int32_t col_value(const StarPlanDev &p, int c, int64_
 
 // Tile loads of a dense-phase column.  The descriptor is passed by value (read
 // once per kernel), which keeps the plan in the kernel-argument segment.
-// NARROW 0: int32 columns; 2: both dense columns uint16 offsets; 1: any
-// widths, dispatched at run time.  Separate kernel instances, so that the
-// common layouts carry no width dispatch in the pipelined loop.
+// NARROW 0: int32 columns; 2: both dense columns uint16 offsets; 3: both
+// dense columns bit-packed (each its own width); 1: any formats, dispatched
+// at run time.  Separate kernel instances, so that the common layouts carry
+// no format dispatch in the pipelined loop.
 template <int BLOCK, int IPT, int NARROW>
 __device__ __forceinline__ void load_col_tile(const ColDev cd, int64_t n_rows, int64_t base, int32_t (&v)[IPT]) {
     if constexpr (NARROW == 0)
@@ -59,6 +61,12 @@ __device__ __forceinline__ void load_col_tile(const ColDev cd, int64_t n_rows, i
     else if constexpr (NARROW == 2)
         block_load_narrow<BLOCK, IPT, uint16_t, true>(reinterpret_cast<const uint16_t *>(cd.p), cd.base, base,
                                                       n_rows, v);
+    else if constexpr (NARROW == 3)
+        block_load_packed<BLOCK, IPT, true>(reinterpret_cast<const uint32_t *>(cd.p), cd.base, (uint32_t)cd.bits,
+                                            base, n_rows, v);
+    else if (cd.bits)
+        block_load_packed<BLOCK, IPT, true>(reinterpret_cast<const uint32_t *>(cd.p), cd.base, (uint32_t)cd.bits,
+                                            base, n_rows, v);
     else if (cd.width == 2)
         block_load_narrow<BLOCK, IPT, uint16_t, true>(reinterpret_cast<const uint16_t *>(cd.p), cd.base, base,
                                                       n_rows, v);
@@ -77,6 +85,12 @@ __device__ __forceinline__ void load_col_tile_sel(const ColDev cd, int64_t n_row
     else if constexpr (NARROW == 2)
         block_load_sel_narrow<BLOCK, IPT, uint16_t, true>(reinterpret_cast<const uint16_t *>(cd.p), cd.base, base,
                                                           n_rows, flags, v);
+    else if constexpr (NARROW == 3)
+        block_load_sel_packed<BLOCK, IPT, true>(reinterpret_cast<const uint32_t *>(cd.p), cd.base,
+                                                (uint32_t)cd.bits, base, n_rows, flags, v);
+    else if (cd.bits)
+        block_load_sel_packed<BLOCK, IPT, true>(reinterpret_cast<const uint32_t *>(cd.p), cd.base,
+                                                (uint32_t)cd.bits, base, n_rows, flags, v);
     else if (cd.width == 2)
         block_load_sel_narrow<BLOCK, IPT, uint16_t, true>(reinterpret_cast<const uint16_t *>(cd.p), cd.base, base,
                                                           n_rows, flags, v);
@@ -85,6 +99,92 @@ __device__ __forceinline__ void load_col_tile_sel(const ColDev cd, int64_t n_row
                                                          n_rows, flags, v);
     else
         block_load_sel<BLOCK, IPT, true>(cd.p, base, n_rows, flags, v);
+}
+
+// Dense-phase columns as loaded, carried across pipeline iterations and
+// decoded where the step uses them.  Decoding a narrow or bit-packed column
+// right after its loads are issued would make the wave wait for them there,
+// so the next tiles' loads could not stay in flight while the current tile
+// is processed.  NARROW 2: pairs of uint16 offsets per word; NARROW 3: the
+// three stream words that hold each thread's 4-row vector.  The int32 and
+// run-time dispatched instances (NARROW 0 and 1) keep values in registers.
+template <int IPT, int NARROW>
+struct RawTile {
+    static_assert(NARROW == 2 || NARROW == 3, "raw tiles are narrow or bit-packed");
+    uint32_t w[NARROW == 2 ? IPT / 2 : IPT / 4 * 3];  // stored words
+};
+
+template <int BLOCK, int IPT, int NARROW>
+__device__ __forceinline__ void load_raw_tile(const ColDev cd, int64_t n_rows, int64_t base, bool sel, uint32_t flags,
+                                              RawTile<IPT, NARROW> &r) {
+    using T = TileShape<BLOCK, IPT>;
+    if constexpr (NARROW == 2 || NARROW == 3) {
+        static_assert(T::VEC == 4, "narrow tiles are read four rows at a time");
+        const bool full = base + T::ITEMS <= n_rows;
+#pragma unroll
+        for (int c = 0; c < T::CHUNKS; ++c) {
+            const uint32_t m = (flags >> (c * 4)) & 0xFu;
+            if (sel && !m) continue;
+            const int64_t r0 = T::index(base, c, 0);
+            if constexpr (NARROW == 2) {
+                const uint16_t *col = reinterpret_cast<const uint16_t *>(cd.p);
+                if (full) {
+                    typedef uint32_t u2 __attribute__((ext_vector_type(2)));
+                    const u2 x = __builtin_nontemporal_load(reinterpret_cast<const u2 *>(col + r0));
+                    r.w[c * 2] = x[0];
+                    r.w[c * 2 + 1] = x[1];
+                } else {
+                    uint32_t lo = 0, hi = 0;
+                    if (r0 < n_rows) lo |= col[r0];
+                    if (r0 + 1 < n_rows) lo |= (uint32_t)col[r0 + 1] << 16;
+                    if (r0 + 2 < n_rows) hi |= col[r0 + 2];
+                    if (r0 + 3 < n_rows) hi |= (uint32_t)col[r0 + 3] << 16;
+                    r.w[c * 2] = lo;
+                    r.w[c * 2 + 1] = hi;
+                }
+            } else {
+                // bit offset of the chunk's first row: a uniform part (the
+                // tile's and the chunk's) plus the thread's, so the word index
+                // is a scalar base plus a 32-bit per-thread offset; the
+                // stream's padding makes the three words readable for any row < n
+                const uint64_t u = (uint64_t)(base + (int64_t)c * BLOCK * T::VEC) * (uint32_t)cd.bits;
+                const uint32_t off = ((uint32_t)u & 31u) + threadIdx.x * (uint32_t)(T::VEC * cd.bits);
+                const uint32_t *q = reinterpret_cast<const uint32_t *>(cd.p) + (u >> 5) + (off >> 5);
+                if (full || r0 < n_rows) {
+                    r.w[c * 3] = __builtin_nontemporal_load(q);
+                    r.w[c * 3 + 1] = __builtin_nontemporal_load(q + 1);
+                    r.w[c * 3 + 2] = __builtin_nontemporal_load(q + 2);
+                } else {
+                    r.w[c * 3] = r.w[c * 3 + 1] = r.w[c * 3 + 2] = 0u;
+                }
+            }
+        }
+    }
+}
+
+// Values of a raw tile (rows past n_rows decode to arbitrary values; they are
+// never alive).
+template <int BLOCK, int IPT, int NARROW>
+__device__ __forceinline__ void decode_tile(const ColDev cd, int64_t base, const RawTile<IPT, NARROW> &r,
+                                            int32_t (&v)[IPT]) {
+    using T = TileShape<BLOCK, IPT>;
+    if constexpr (NARROW == 2) {
+#pragma unroll
+        for (int k = 0; k < IPT / 2; ++k) {
+            v[2 * k] = cd.base + (int32_t)(r.w[k] & 0xFFFFu);
+            v[2 * k + 1] = cd.base + (int32_t)(r.w[k] >> 16);
+        }
+    } else {
+        static_assert(NARROW == 3, "raw tiles are narrow or bit-packed");
+        const uint32_t bits = (uint32_t)cd.bits;
+#pragma unroll
+        for (int c = 0; c < T::CHUNKS; ++c) {
+            // the low five bits of the chunk's bit offset, as in load_raw_tile
+            const uint32_t s = (uint32_t)(base + (int64_t)c * BLOCK * T::VEC) * bits +
+                               threadIdx.x * (uint32_t)T::VEC * bits;
+            decode_packed_vec4(r.w[c * 3], r.w[c * 3 + 1], r.w[c * 3 + 2], s, bits, cd.base, &v[c * 4]);
+        }
+    }
 }
 
 __device__ __forceinline__ bool star_probe(const StarJoinDev &j, int32_t key, int32_t &payload) {
@@ -311,50 +411,13 @@ __global__ __launch_bounds__(BLOCK) void star_kernel(const StarPlanDev p, uint64
     // t_{k+1} .. t_{k+PF} are in flight.  Loads land in alternating register
     // buffers (the loop is unrolled by two), so no buffer is copied while
     // its loads are still outstanding.
-    int32_t a0[IPT], a1[IPT];  // first-step column of upcoming tiles
-    int32_t b0[IPT], b1[IPT];  // second-step column of the current and the next tile
     int64_t t_cur = blockIdx.x;
     uint32_t k_cur = 0;        // position of t_cur in this workgroup's tile sequence
     uint32_t alive_c = 0;
-    if (t_cur < n_tiles) {
-        alive_c = valid_mask<BLOCK, IPT>(t_cur * T::ITEMS, p.n_rows);
-        if (dense >= 1) {
-            load_col_tile<BLOCK, IPT, NARROW>(cd0, p.n_rows, t_cur * T::ITEMS, a0);
-            alive_c = star_step_tile<IPT>(p, 0, lds, so0, a0, alive_c);
-        }
-        if (dense >= 2) load_col_tile_sel<BLOCK, IPT, NARROW>(cd1, p.n_rows, t_cur * T::ITEMS, alive_c, b0);
-        if (dense >= 1 && t_cur + stride < n_tiles)
-            load_col_tile<BLOCK, IPT, NARROW>(cd0, p.n_rows, (t_cur + stride) * T::ITEMS, a0);
-        if (PF == 2 && dense >= 1 && t_cur + 2 * stride < n_tiles)
-            load_col_tile<BLOCK, IPT, NARROW>(cd0, p.n_rows, (t_cur + 2 * stride) * T::ITEMS, a1);
-    }
 
-    // One pipeline iteration.  `an` holds the first-step column of t_nxt;
-    // `bc` the second-step column of t_cur; `bn` receives that of t_nxt.
-    auto iterate = [&](int32_t (&an)[IPT], int32_t (&bc)[IPT], int32_t (&bn)[IPT]) -> bool {
-        const int64_t t_nxt = t_cur + stride;
-        const bool has_nxt = t_nxt < n_tiles;
-        uint32_t alive_n = 0;
-        if (has_nxt) {
-            alive_n = valid_mask<BLOCK, IPT>(t_nxt * T::ITEMS, p.n_rows);
-            const int64_t t_pf = t_nxt + PF * stride;
-            if (dense >= 1 && so0 >= 0) {
-                // staged first step: issue its LDS reads, then reuse the key
-                // registers for the prefetch before testing the bits
-                StagedProbe<IPT> pr;
-                pr.begin(lds, so0, p.joins[0].key_min, bitmap_words_of(p.joins[0].span), an, alive_n);
-                if (t_pf < n_tiles) load_col_tile<BLOCK, IPT, NARROW>(cd0, p.n_rows, t_pf * T::ITEMS, an);
-                alive_n = pr.end();
-            } else {
-                if (dense >= 1) alive_n = star_step_tile<IPT>(p, 0, lds, so0, an, alive_n);
-                if (dense >= 1 && t_pf < n_tiles)
-                    load_col_tile<BLOCK, IPT, NARROW>(cd0, p.n_rows, t_pf * T::ITEMS, an);
-            }
-            if (dense >= 2) load_col_tile_sel<BLOCK, IPT, NARROW>(cd1, p.n_rows, t_nxt * T::ITEMS, alive_n, bn);
-        }
-        if (dense >= 2) alive_c = star_step_tile<IPT>(p, 1, lds, so1, bc, alive_c);
-
-        // compact the wave's live rows of this tile into its queue
+    // compact the wave's live rows of the current tile into its queue, and
+    // finish the queue 64 rows at a time
+    auto enqueue = [&]() {
         uint32_t total;
         const uint32_t off = wave_exclusive_scan_small<T::CBITS>((uint32_t)__popc(alive_c), total);
         if (total) {
@@ -377,16 +440,118 @@ __global__ __launch_bounds__(BLOCK) void star_kernel(const StarPlanDev p, uint64
             }
             __builtin_amdgcn_wave_barrier();
         }
-        if (!has_nxt) return false;
-        t_cur = t_nxt;
-        ++k_cur;
-        alive_c = alive_n;
-        return true;
     };
-    if (t_cur < n_tiles) {
-        for (;;) {
-            if (!iterate(a0, b0, b1)) break;
-            if (!iterate(PF == 2 ? a1 : a0, b1, b0)) break;
+
+    if constexpr (NARROW == 2 || NARROW == 3) {
+        // narrow and bit-packed columns: the buffers hold the loaded words,
+        // decoded where a step uses them
+        using Raw = RawTile<IPT, NARROW>;
+        Raw a0, a1, b0, b1;
+        if (t_cur < n_tiles) {
+            alive_c = valid_mask<BLOCK, IPT>(t_cur * T::ITEMS, p.n_rows);
+            if (dense >= 1) {
+                load_raw_tile<BLOCK, IPT, NARROW>(cd0, p.n_rows, t_cur * T::ITEMS, false, 0u, a0);
+                int32_t v[IPT];
+                decode_tile<BLOCK, IPT, NARROW>(cd0, t_cur * T::ITEMS, a0, v);
+                alive_c = star_step_tile<IPT>(p, 0, lds, so0, v, alive_c);
+            }
+            if (dense >= 2) load_raw_tile<BLOCK, IPT, NARROW>(cd1, p.n_rows, t_cur * T::ITEMS, true, alive_c, b0);
+            if (dense >= 1 && t_cur + stride < n_tiles)
+                load_raw_tile<BLOCK, IPT, NARROW>(cd0, p.n_rows, (t_cur + stride) * T::ITEMS, false, 0u, a0);
+            if (PF == 2 && dense >= 1 && t_cur + 2 * stride < n_tiles)
+                load_raw_tile<BLOCK, IPT, NARROW>(cd0, p.n_rows, (t_cur + 2 * stride) * T::ITEMS, false, 0u, a1);
+        }
+        auto iterate = [&](Raw &an, Raw &bc, Raw &bn) -> bool {
+            const int64_t t_nxt = t_cur + stride;
+            const bool has_nxt = t_nxt < n_tiles;
+            uint32_t alive_n = 0;
+            if (has_nxt) {
+                alive_n = valid_mask<BLOCK, IPT>(t_nxt * T::ITEMS, p.n_rows);
+                const int64_t t_pf = t_nxt + PF * stride;
+                int32_t v[IPT];
+                if (dense >= 1) decode_tile<BLOCK, IPT, NARROW>(cd0, t_nxt * T::ITEMS, an, v);
+                if (dense >= 1 && so0 >= 0) {
+                    StagedProbe<IPT> pr;
+                    pr.begin(lds, so0, p.joins[0].key_min, bitmap_words_of(p.joins[0].span), v, alive_n);
+                    if (t_pf < n_tiles)
+                        load_raw_tile<BLOCK, IPT, NARROW>(cd0, p.n_rows, t_pf * T::ITEMS, false, 0u, an);
+                    alive_n = pr.end();
+                } else {
+                    if (dense >= 1) alive_n = star_step_tile<IPT>(p, 0, lds, so0, v, alive_n);
+                    if (dense >= 1 && t_pf < n_tiles)
+                        load_raw_tile<BLOCK, IPT, NARROW>(cd0, p.n_rows, t_pf * T::ITEMS, false, 0u, an);
+                }
+                if (dense >= 2) load_raw_tile<BLOCK, IPT, NARROW>(cd1, p.n_rows, t_nxt * T::ITEMS, true, alive_n, bn);
+            }
+            if (dense >= 2) {
+                int32_t v[IPT];
+                decode_tile<BLOCK, IPT, NARROW>(cd1, t_cur * T::ITEMS, bc, v);
+                alive_c = star_step_tile<IPT>(p, 1, lds, so1, v, alive_c);
+            }
+            enqueue();
+            if (!has_nxt) return false;
+            t_cur = t_nxt;
+            ++k_cur;
+            alive_c = alive_n;
+            return true;
+        };
+        if (t_cur < n_tiles) {
+            for (;;) {
+                if (!iterate(a0, b0, b1)) break;
+                if (!iterate(PF == 2 ? a1 : a0, b1, b0)) break;
+            }
+        }
+    } else {
+        int32_t a0[IPT], a1[IPT];  // first-step column of upcoming tiles
+        int32_t b0[IPT], b1[IPT];  // second-step column of the current and the next tile
+        if (t_cur < n_tiles) {
+            alive_c = valid_mask<BLOCK, IPT>(t_cur * T::ITEMS, p.n_rows);
+            if (dense >= 1) {
+                load_col_tile<BLOCK, IPT, NARROW>(cd0, p.n_rows, t_cur * T::ITEMS, a0);
+                alive_c = star_step_tile<IPT>(p, 0, lds, so0, a0, alive_c);
+            }
+            if (dense >= 2) load_col_tile_sel<BLOCK, IPT, NARROW>(cd1, p.n_rows, t_cur * T::ITEMS, alive_c, b0);
+            if (dense >= 1 && t_cur + stride < n_tiles)
+                load_col_tile<BLOCK, IPT, NARROW>(cd0, p.n_rows, (t_cur + stride) * T::ITEMS, a0);
+            if (PF == 2 && dense >= 1 && t_cur + 2 * stride < n_tiles)
+                load_col_tile<BLOCK, IPT, NARROW>(cd0, p.n_rows, (t_cur + 2 * stride) * T::ITEMS, a1);
+        }
+        // One pipeline iteration.  `an` holds the first-step column of t_nxt;
+        // `bc` the second-step column of t_cur; `bn` receives that of t_nxt.
+        auto iterate = [&](int32_t(&an)[IPT], int32_t(&bc)[IPT], int32_t(&bn)[IPT]) -> bool {
+            const int64_t t_nxt = t_cur + stride;
+            const bool has_nxt = t_nxt < n_tiles;
+            uint32_t alive_n = 0;
+            if (has_nxt) {
+                alive_n = valid_mask<BLOCK, IPT>(t_nxt * T::ITEMS, p.n_rows);
+                const int64_t t_pf = t_nxt + PF * stride;
+                if (dense >= 1 && so0 >= 0) {
+                    // staged first step: issue its LDS reads, then reuse the key
+                    // registers for the prefetch before testing the bits
+                    StagedProbe<IPT> pr;
+                    pr.begin(lds, so0, p.joins[0].key_min, bitmap_words_of(p.joins[0].span), an, alive_n);
+                    if (t_pf < n_tiles) load_col_tile<BLOCK, IPT, NARROW>(cd0, p.n_rows, t_pf * T::ITEMS, an);
+                    alive_n = pr.end();
+                } else {
+                    if (dense >= 1) alive_n = star_step_tile<IPT>(p, 0, lds, so0, an, alive_n);
+                    if (dense >= 1 && t_pf < n_tiles)
+                        load_col_tile<BLOCK, IPT, NARROW>(cd0, p.n_rows, t_pf * T::ITEMS, an);
+                }
+                if (dense >= 2) load_col_tile_sel<BLOCK, IPT, NARROW>(cd1, p.n_rows, t_nxt * T::ITEMS, alive_n, bn);
+            }
+            if (dense >= 2) alive_c = star_step_tile<IPT>(p, 1, lds, so1, bc, alive_c);
+            enqueue();
+            if (!has_nxt) return false;
+            t_cur = t_nxt;
+            ++k_cur;
+            alive_c = alive_n;
+            return true;
+        };
+        if (t_cur < n_tiles) {
+            for (;;) {
+                if (!iterate(a0, b0, b1)) break;
+                if (!iterate(PF == 2 ? a1 : a0, b1, b0)) break;
+            }
         }
     }
     if (lane < tail - head) {
@@ -459,14 +624,17 @@ static hipError_t star_t(const LaunchCfg &cfg, StarPlanDev p, uint64_t *out, int
     if (grid > n_tiles) grid = n_tiles;
     if (grid < 1) grid = 1;
     // prefetch depth one tile (a second register buffer costs more waves than it gains)
-    int n4 = 0, n2 = 0;
+    int n4 = 0, n2 = 0, nb = 0;
     for (int d = 0; d < dense; ++d) {
         const int c = d < p.n_preds ? p.pred_col[d] : p.joins[d - p.n_preds].fk_col;
         n4 += p.col[c].width == 4;
         n2 += p.col[c].width == 2;
+        nb += p.col[c].bits > 0;
     }
-    auto fn = n4 == dense ? star_kernel<BLOCK, IPT, 1, 0>
-                          : n2 == dense ? star_kernel<BLOCK, IPT, 1, 2> : star_kernel<BLOCK, IPT, 1, 1>;
+    auto fn = n4 == dense   ? star_kernel<BLOCK, IPT, 1, 0>
+              : n2 == dense ? star_kernel<BLOCK, IPT, 1, 2>
+              : nb == dense ? star_kernel<BLOCK, IPT, 1, 3>
+                            : star_kernel<BLOCK, IPT, 1, 1>;
     if (lds_bytes > 65536) {
         hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            (int)lds_bytes);

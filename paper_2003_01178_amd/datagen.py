@@ -59,6 +59,16 @@ def date_key(year: int, month: int, day: int, plus_days: int = 0) -> int:
     return y * 10000 + m * 100 + dd
 
 
+def day_codes(keys) -> np.ndarray:
+    """Dictionary code of yyyymmdd date keys: the day's index from 1992-01-01
+    (0..2555 over the seven years, 12 bits)."""
+    all_keys, _ = day_keys()
+    codes = np.searchsorted(all_keys, np.asarray(keys))
+    if np.any(codes >= all_keys.size) or np.any(all_keys[np.minimum(codes, all_keys.size - 1)] != keys):
+        raise ValueError("not a date key of the seven years")
+    return codes.astype(np.int32)
+
+
 # Packed dimension payload of the flight templates: bits 0..9 the group
 # attribute (the date dimension: year - 1992), bits 16..20 the filter attribute.
 PACK_FILTER_SHIFT = 16

@@ -76,25 +76,32 @@ class StarSchema:
                                   key_min=int(d.key.min()), key_max=int(d.key.max()), n=d.n))
         self.consts = list(t.consts)
         self.device = device
-        # one perfect-hash table per dimension; payload: year (dim 0), group (dim 2)
-        self.tables = []
-        for j, d in enumerate(self.dims):
-            self.tables.append(cx.HashTable(cx.HT_DIRECT, d["n"], d["key_min"], d["key_max"],
-                                            has_payload=j in (0, 2), device=device))
+        self.tables = self.new_tables()
         self.status = cx.new_status(device)
+
+    def new_tables(self):
+        """One perfect-hash table per dimension; payload: year (dim 0), group (dim 2)."""
+        return [cx.HashTable(cx.HT_DIRECT, d["n"], d["key_min"], d["key_max"], has_payload=j in (0, 2),
+                             device=self.device) for j, d in enumerate(self.dims)]
 
     @property
     def fact_cols(self):
         return [*self.fk, self.m1, self.m2]
 
-    def build(self, consts=None, stream=None, batched=True):
-        """Filtered builds: dimension j keeps rows with filter == consts[j].
-        batched: all four tables in one clear and one build launch."""
+    def build_items(self, consts=None, tables=None):
+        """Filtered builds: dimension j keeps rows with filter == consts[j]."""
         consts = self.consts if consts is None else consts
+        tables = self.tables if tables is None else tables
         items = []
         for j, d in enumerate(self.dims):
             payload = d["year"] if j == 0 else (d["group"] if j == 2 else None)
-            items.append((self.tables[j], d["key"], payload, d["filter"], (consts[j], consts[j])))
+            items.append((tables[j], d["key"], payload, d["filter"], (consts[j], consts[j])))
+        return items
+
+    def build(self, consts=None, stream=None, batched=True):
+        """Filtered builds into self.tables.
+        batched: all four tables in one clear and one build launch."""
+        items = self.build_items(consts)
         if batched:
             cx.build_tables(items, status=self.status, stream=stream)
         else:
@@ -102,10 +109,11 @@ class StarSchema:
                 ht.build(keys, payload=payload, filter_col=filt, filter=rng, status=self.status, stream=stream)
         return self.tables
 
-    def plan(self, order=DEFAULT_JOIN_ORDER):
+    def plan(self, order=DEFAULT_JOIN_ORDER, tables=None):
+        tables = self.tables if tables is None else tables
         joins = []
         for j in order:
-            jj = dict(table=self.tables[j], fk_col=j)
+            jj = dict(table=tables[j], fk_col=j)
             if j == 0:
                 jj["group"] = (32, 0, datagen.FIRST_YEAR, GROUPS_PER_YEAR)
             if j == 2:

@@ -34,7 +34,7 @@ def test_every_declared_symbol_is_exported(cx):
 
 def test_struct_layout_matches_binding(cx):
     lib = cx.load()
-    assert lib.crystal_abi_version() == 7
+    assert lib.crystal_abi_version() == 9
     for which, ty in enumerate((cx.Range, cx.HT, cx.Pred, cx.Join, cx.StarQueryC, cx.QmaskTableC,
                                 cx.BatchQueryC, cx.BatchC, cx.ServerTemplateC, cx.ServerConfigC,
                                 cx.ServerStatsC, cx.BuildItemC, cx.ColFormatC, cx.QmaskBuildItemC)):
@@ -187,6 +187,47 @@ def test_build_batch_and_pack_host_errors(cx):
     assert lib.crystal_pack_column(None, 0, 0, 1, None, st, None) == cx.OK
 
 
+def test_build_batch_fused_host_errors(cx):
+    """crystal_ht_build_batch_fused rejects bad counts, descriptors, zero
+    ranges and any overlap between the memory it writes, before any device
+    work."""
+    lib = cx.load()
+    st = ctypes.c_void_p(1 << 20)
+    f = lib.crystal_ht_build_batch_fused
+    none = (ctypes.POINTER(cx.HT) * 1)()
+    items = (cx.BuildItemC * 9)()
+    assert f(items, 9, none, 0, None, 0, st, None) == cx.EINVAL                  # more than 8 builds
+    assert f(items, -1, none, 0, None, 0, st, None) == cx.EINVAL
+    assert f(None, 1, none, 0, None, 0, st, None) == cx.EINVAL
+    assert f(items, 0, none, 9, None, 0, st, None) == cx.EINVAL                  # more than 8 clears
+    assert f(items, 0, None, 1, None, 0, st, None) == cx.EINVAL
+    assert f(items, 0, none, 1, None, 0, st, None) == cx.EINVAL                  # no clear descriptor
+    assert f(items, 0, none, 0, None, 0, None, None) == cx.EINVAL                # no status word
+    assert f(items, 0, none, 0, None, -1, st, None) == cx.EINVAL
+    assert f(items, 0, none, 0, None, 4, st, None) == cx.EINVAL                  # zero range without memory
+    assert f(items, 0, none, 0, ctypes.c_void_p((1 << 24) + 4), 4, st, None) == cx.EINVAL  # misaligned
+    assert f(items, 0, none, 0, None, 0, st, None) == cx.OK                      # nothing to do
+    a, b = cx.HT(), cx.HT()
+    for ht, mem in ((a, 1 << 20), (b, 1 << 21)):
+        assert lib.crystal_ht_init(ctypes.byref(ht), cx.HT_DIRECT, 1000, 0, 999, 1) == cx.OK
+        ht.mem = mem
+    nbytes = lib.crystal_ht_bytes(ctypes.byref(a))
+    items[0].ht = ctypes.pointer(a)
+    items[0].keys = items[0].payload = 1 << 23
+    items[0].n = 1000
+    clear = (ctypes.POINTER(cx.HT) * 2)(ctypes.pointer(a), ctypes.pointer(b))
+    clear_b = (ctypes.POINTER(cx.HT) * 1)(ctypes.pointer(b))
+    assert f(items, 1, clear, 1, None, 0, st, None) == cx.EINVAL                 # builds into a cleared table
+    # the zeroed range overlaps the built table's last bytes, then the cleared table's first
+    assert f(items, 1, clear_b, 1, ctypes.c_void_p((1 << 20) + nbytes - 8),
+             4, st, None) == cx.EINVAL
+    assert f(items, 0, clear, 2, ctypes.c_void_p((1 << 21) - 16), 4, st, None) == cx.EINVAL
+    items[1] = items[0]
+    assert f(items, 2, none, 0, None, 0, st, None) == cx.EINVAL                  # the same table twice
+    b.mem = (1 << 20) + nbytes - 16                                            # b starts inside a
+    assert f(items, 1, clear_b, 1, None, 0, st, None) == cx.EINVAL
+
+
 def test_star_query_format_validation(cx):
     """Column formats other than int32, uint16 and uint8 are rejected."""
     lib = cx.load()
@@ -289,3 +330,20 @@ def test_star_noalloc_host_errors(cx):
     q.n_rows = 100
     assert lib.crystal_run_star_query_noalloc(ctypes.byref(q), out, st, None) == cx.EINVAL
     del fake
+
+
+def test_bitpacked_format_host_checks(cx):
+    """Bit widths 1..16 only, and only with width 0; the packed size is the
+    stream's words plus four words of padding."""
+    lib = cx.load()
+    assert lib.crystal_packed_column_bytes(10, 12) == (4 + 4) * 4      # 120 bits: 4 words, then padding
+    assert lib.crystal_packed_column_bytes(0, 5) == 16
+    assert lib.crystal_packed_column_bytes(10, 0) == 0 and lib.crystal_packed_column_bytes(10, 17) == 0
+    st, fake = ctypes.c_void_p(1 << 21), ctypes.c_void_p(1 << 20)
+    assert lib.crystal_pack_column_bits(fake, 10, 0, 17, fake, st, None) == cx.EINVAL
+    assert lib.crystal_pack_column_bits(fake, 10, 0, 4, ctypes.c_void_p((1 << 20) + 4), st, None) == cx.EINVAL
+    q = cx.StarQueryC()
+    q.n_cols, q.n_rows, q.n_groups, q.agg = 1, 0, 1, cx.AGG_COUNT
+    for width, bits in ((0, 17), (2, 4), (0, -1)):
+        q.formats[0] = cx.ColFormatC(width, 0, bits, 0)
+        assert lib.crystal_run_star_query(ctypes.byref(q), ctypes.c_void_p(1 << 21), st, None, 0, None) == cx.EINVAL

@@ -141,3 +141,105 @@ def test_shared_scan_rejects_narrow_columns(star_small):
     with pytest.raises(cx.CrystalError) as e:
         scan.run([[(0, 5)]], outs)
     assert e.value.code == cx.EINVAL
+
+
+# ------------------------------------------------------------ bit-packed ---
+def decode_bits(words, n, bits, base):
+    """Host decoder of the documented layout: an LSB-first stream of 32-bit
+    words, row i's field at stream bits [i * bits, (i + 1) * bits)."""
+    w = words.astype(np.uint64) & np.uint64(0xFFFFFFFF)
+    off = np.arange(n, dtype=np.uint64) * np.uint64(bits)
+    q = (off >> np.uint64(5)).astype(np.int64)
+    two = w[q] | (w[q + 1] << np.uint64(32))
+    f = (two >> (off & np.uint64(31))) & np.uint64((1 << bits) - 1)
+    return f.astype(np.int64) + base
+
+
+@pytest.mark.parametrize("bits", [1, 3, 7, 12, 16])
+@pytest.mark.parametrize("n", [0, 1, 5, 4097, 1_000_003])
+def test_pack_bits_round_trip(bits, n):
+    announce("pack bits", bits, n)
+    rng = np.random.default_rng(7 * n + bits)
+    base = -123_456
+    x = (rng.integers(0, 1 << bits, size=n, dtype=np.int64) + base).astype(np.int32)
+    col, st = cx.pack_column_bits(dev(x), base, bits)
+    cx.check_status(st)
+    words = col.data.cpu().numpy().view(np.uint32)
+    n_words = (n * bits + 31) // 32
+    assert words.size == n_words + 4 and not np.any(words[n_words:])      # four zero words of padding
+    assert np.array_equal(decode_bits(words, n, bits, base), x.astype(np.int64))
+
+
+def test_pack_bits_out_of_range():
+    announce("pack bits erange")
+    x = np.array([10, 11, 10 + 63, 10 + 64, 9, 12], dtype=np.int32)       # 6 bits from 10: 74 and 9 are out
+    col, st = cx.pack_column_bits(dev(x), 10, 6)
+    assert int(st.item()) == cx.ERANGE
+    got = decode_bits(col.data.cpu().numpy().view(np.uint32), 6, 6, 10)
+    assert got[0] == 10 and got[1] == 11 and got[2] == 73 and got[5] == 12
+    for bad in (0, 17):
+        with pytest.raises(ValueError):
+            cx.pack_column_bits(dev(x), 10, bad)
+
+
+def bitpacked_star(t, s):
+    """fk0 as 12-bit date codes (day index, with the date table keyed by code)
+    and fk1 as 16-bit offsets; the rest int32.  Returns (cols, tables)."""
+    codes, st0 = cx.pack_column_bits(dev(datagen.day_codes(t.fk[0])), 0, 12)
+    fk1, st1 = cx.pack_column_bits(s.fk[1], 0, 16)
+    cx.check_status(st0)
+    cx.check_status(st1)
+    d0 = s.dims[0]
+    ht0 = cx.HashTable(cx.HT_DIRECT, d0["n"], 0, datagen.N_DAYS - 1, has_payload=True)
+    ht0.build(dev(datagen.day_codes(t.dims[0].key)), payload=d0["year"], filter_col=d0["filter"],
+              filter=(t.consts[0], t.consts[0]), status=s.status)
+    tables = [ht0] + list(s.tables[1:])
+    return [codes, fk1, s.fk[2], s.fk[3], s.m1, s.m2], tables
+
+
+@pytest.mark.parametrize("order", [(1, 0, 2, 3), (0, 2, 1, 3), (2, 3, 1, 0), (3, 1, 0, 2)])
+def test_star_with_bitpacked_keys_matches_oracle(star_small, order):
+    """Both dense steps bit-packed (1, 0, ...), one bit-packed and one int32
+    (0, 2, ...), and bit-packed keys in the sparse steps and group fields
+    (2, 3, 1, 0), against the oracle on the original int32 date keys."""
+    announce("bitpacked star", order)
+    t, s = star_small
+    s.status.zero_()
+    s.build()
+    cols, tables = bitpacked_star(t, s)
+    joins = []
+    for j in order:
+        jj = dict(table=tables[j], fk_col=j)
+        if j == 0:
+            jj["group"] = (32, 0, datagen.FIRST_YEAR, queries.GROUPS_PER_YEAR)
+        if j == 2:
+            jj["group"] = (32, 0, 0, 1)
+        joins.append(jj)
+    for shape in [None, (256, 4, 0), (1024, 16, 2)]:
+        cx.tune_reset()
+        if shape:
+            cx.tune_set(cx.K_STAR, *shape)
+        q = cx.StarQuery(cols, n_groups=STAR_GROUPS, joins=joins, agg=cx.AGG_SUM, agg_cols=(4, 0))
+        out, st = q.run()
+        cx.check_status(st)
+        cx.check_status(s.status)
+        want, _ = star_oracle(t)
+        assert np.array_equal(out.cpu().numpy(), want), (order, shape)
+
+
+@pytest.mark.parametrize("n", [4097, 3_000_001])
+def test_q11_bitpacked_matches_oracle(n):
+    """Q1.1 over datekey (16 bits from 1992-01-01), discount (4 bits),
+    quantity (6 bits from 1) and int32 price."""
+    announce("bitpacked q11", n)
+    f = datagen.q11_fact(n, workload=95 + n % 7)
+    dk, s0 = cx.pack_column_bits(dev(f.datekey), 19920101, 16)
+    disc, s1 = cx.pack_column_bits(dev(f.discount), 0, 4)
+    qty, s2 = cx.pack_column_bits(dev(f.quantity), 1, 6)
+    for st in (s0, s1, s2):
+        cx.check_status(st)
+    for year, d, q in [(1994, 1, 24), (1992, 0, 50), (1998, 8, 2)]:
+        plan = queries.Q11Plan(dk, disc, qty, dev(f.price), year=year, disc=(d, d + 2), qty_max=q)
+        out, st = plan.run()
+        cx.check_status(st)
+        assert int(out.item()) == q11_oracle(f, year, (d, d + 2), q)

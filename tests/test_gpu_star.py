@@ -122,6 +122,73 @@ def test_star_random_constants(star_small):
         assert np.array_equal(out.cpu().numpy(), want), (trial, consts)
 
 
+def _bitmap_bytes(ht):
+    """Bytes of a direct table's presence bitmap (the table memory before its payloads)."""
+    return ht.nbytes - (4 * ht.desc.capacity if ht.desc.has_payload else 0)
+
+
+def test_star_fused_builds_over_two_table_sets(star_small):
+    """crystal_ht_build_batch_fused: steps alternate between two table sets;
+    each step's one launch builds its set, clears the other and zeroes the
+    group array, and the accumulating kernel then gives the oracle's answer.
+    Constants change every step, so a table left unclear would show."""
+    t, s = star_small
+    sets = [s.new_tables(), s.new_tables()]
+    plans = [s.plan(tables=tb) for tb in sets]
+    status = cx.new_status()
+    s.status.zero_()
+    for tb in sets:   # garbage in every table, so only the clear makes them usable
+        for ht in tb:
+            ht.mem.fill_(0xA5)
+    cx.build_tables_fused([], clear=sets[0] + sets[1], status=s.status)
+    out = torch.full((STAR_GROUPS,), 7, dtype=torch.int64, device="cuda")
+    rng = np.random.default_rng(19)
+    for step in range(6):
+        consts = datagen.random_star_constants(rng)
+        announce("fused build step", step, consts)
+        p = step % 2
+        cx.build_tables_fused(s.build_items(consts, tables=sets[p]), clear=sets[1 - p], zero=out, status=s.status)
+        plans[p].run(out=out, status=status, accumulate=True)
+        cx.check_status(status)
+        cx.check_status(s.status)
+        want, _ = star_oracle(t, consts)
+        assert np.array_equal(out.cpu().numpy(), want), (step, consts)
+        for ht in sets[1 - p]:
+            assert int(ht.mem[:_bitmap_bytes(ht)].count_nonzero()) == 0
+
+
+def test_star_fused_builds_graph_replays(star_small):
+    """The two-launch step captured as one HIP graph per table set and
+    replayed alternately, with eager work between replays: every replay
+    gives the oracle's answer."""
+    t, s = star_small
+    want, _ = star_oracle(t)
+    sets = [s.new_tables(), s.new_tables()]
+    plans = [s.plan(tables=tb) for tb in sets]
+    status = cx.new_status()
+    s.status.zero_()
+    out = torch.empty(STAR_GROUPS, dtype=torch.int64, device="cuda")
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        cx.build_tables_fused([], clear=sets[0] + sets[1], status=s.status, stream=stream)
+        graphs = []
+        for p in (0, 1):
+            with cx.Graph.capture(stream) as g:
+                cx.build_tables_fused(s.build_items(tables=sets[p]), clear=sets[1 - p], zero=out, status=s.status,
+                                      stream=stream)
+                plans[p].run(out=out, status=status, stream=stream, accumulate=True)
+            graphs.append(g)
+        for r in range(6):
+            announce("fused build graph replay", r)
+            graphs[r % 2].launch(stream)
+            stream.synchronize()
+            assert np.array_equal(out.cpu().numpy(), want), r
+            out.add_(3)        # eager work between replays
+    cx.check_status(status)
+    cx.check_status(s.status)
+
+
 @pytest.mark.parametrize("block,ipt,gpc", [(64, 4, 0), (128, 16, 0), (256, 8, 3), (1024, 16, 1)])
 def test_star_tile_shapes(star_small, block, ipt, gpc):
     announce("star shape", block, ipt, gpc)
