@@ -347,35 +347,62 @@ __global__ __launch_bounds__(BLOCK) void ht_probe_kernel(DevTable t, const int32
                     hit |= 1u << k;
             }
         } else {
-            // table staged in LDS: linear probing in rounds, the next slot of every
-            // item still searching read at once, so a tile's probes overlap
+            // table staged in LDS: every item's home slot is read at once and
+            // compared without branches; only items whose home slot holds
+            // another key continue, in rounds that read the next slot of every
+            // item still searching at once (at fill rate 1/2 most items end in
+            // the first round)
             uint32_t slot[IPT];
             uint32_t pending = 0;
-#pragma unroll
-            for (int k = 0; k < IPT; ++k) {
-                slot[k] = hash_slot(key[k], t.shift);
-                pay[k] = 0;
-                pending |= (uint32_t)(((valid >> k) & 1u) && key[k] != kEmptyKey) << k;
-            }
-            for (uint32_t step = 0; pending && step <= t.mask; ++step) {
+            {
                 v2i e[IPT];
 #pragma unroll
-                for (int k = 0; k < IPT; ++k)
-                    if ((pending >> k) & 1u) e[k] = slots[slot[k]];
+                for (int k = 0; k < IPT; ++k) {
+                    slot[k] = hash_slot(key[k], t.shift);
+                    e[k] = slots[slot[k]];
+                }
 #pragma unroll
                 for (int k = 0; k < IPT; ++k) {
-                    if (!((pending >> k) & 1u)) continue;
-                    if (e[k].x == key[k]) {
-                        hit |= 1u << k;
-                        pay[k] = e[k].y;
-                        pending &= ~(1u << k);
-                    } else if (e[k].x == kEmptyKey) {
-                        pending &= ~(1u << k);
-                    } else {
-                        slot[k] = (slot[k] + 1u) & t.mask;
+                    const bool ok = ((valid >> k) & 1u) && key[k] != kEmptyKey;
+                    const bool h = ok && e[k].x == key[k];
+                    hit |= (uint32_t)h << k;
+                    pay[k] = h ? e[k].y : 0;
+                    pending |= (uint32_t)(ok && !h && e[k].x != kEmptyKey) << k;
+                }
+            }
+            if (pending) {
+#pragma unroll
+                for (int k = 0; k < IPT; ++k) slot[k] = (slot[k] + 1u) & t.mask;
+                for (uint32_t step = 1; pending && step <= t.mask; ++step) {
+                    v2i e[IPT];
+#pragma unroll
+                    for (int k = 0; k < IPT; ++k)
+                        if ((pending >> k) & 1u) e[k] = slots[slot[k]];
+#pragma unroll
+                    for (int k = 0; k < IPT; ++k) {
+                        if (!((pending >> k) & 1u)) continue;
+                        if (e[k].x == key[k]) {
+                            hit |= 1u << k;
+                            pay[k] = e[k].y;
+                            pending &= ~(1u << k);
+                        } else if (e[k].x == kEmptyKey) {
+                            pending &= ~(1u << k);
+                        } else {
+                            slot[k] = (slot[k] + 1u) & t.mask;
+                        }
                     }
                 }
             }
+        }
+        if constexpr (MODE == 1) {
+            // pay[k] is 0 for misses: the sum needs no per-item branch
+#pragma unroll
+            for (int k = 0; k < IPT; ++k) {
+                sum += (uint64_t)(int64_t)pay[k];
+                if constexpr (PP) sum += ((hit >> k) & 1u) ? (uint64_t)(int64_t)r.pv[k] : 0ull;
+            }
+            cnt += (uint64_t)__popc(hit);
+            return;
         }
 #pragma unroll
         for (int k = 0; k < IPT; ++k)
