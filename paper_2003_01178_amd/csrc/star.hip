@@ -26,6 +26,7 @@
 // (BlockAggregate) into a partial in scratch memory and summed by a one-
 // workgroup finalize kernel, which avoids same-address atomics from every
 // workgroup.
+#include <map>
 #include <mutex>
 
 #include "block.hpp"
@@ -368,7 +369,7 @@ __device__ __forceinline__ void finish_row(const StarPlanDev &p, int dense, int6
     aggregate_row(p, row, out, scalar_acc, bad_group);
 }
 
-template <int BLOCK, int IPT, int PF, int NARROW>
+template <int BLOCK, int IPT, int NARROW>
 __global__ __launch_bounds__(BLOCK) void star_kernel(const StarPlanDev p, uint64_t *__restrict__ out,
                                                      int32_t *status, int64_t n_tiles,
                                                      uint64_t *__restrict__ partials) {
@@ -406,151 +407,130 @@ __global__ __launch_bounds__(BLOCK) void star_kernel(const StarPlanDev p, uint64
     const ColDev cd0 = p.col[dense >= 1 ? step_col(p, 0) : 0];
     const ColDev cd1 = p.col[dense >= 2 ? step_col(p, 1) : 0];
 
-    // Pipeline over this workgroup's tiles t_0, t_1, ...: while tile t_k is
-    // finished, the second-step loads of t_{k+1} and the first-step loads of
-    // t_{k+1} .. t_{k+PF} are in flight.  Loads land in alternating register
-    // buffers (the loop is unrolled by two), so no buffer is copied while
-    // its loads are still outstanding.
+    // Pipeline over this workgroup's tiles t_0, t_1, ...: an iteration runs
+    // the first step of t_{k+1} and the second step of t_k, then issues the
+    // second-step loads of t_{k+1} and the first-step loads of t_{k+2}, and
+    // queues the rows of t_k still alive.  Each column has one register
+    // buffer, reloaded once the step that reads it is done, so that more
+    // waves fit on a SIMD.
     int64_t t_cur = blockIdx.x;
     uint32_t k_cur = 0;        // position of t_cur in this workgroup's tile sequence
     uint32_t alive_c = 0;
 
-    // compact the wave's live rows of the current tile into its queue, and
     // finish the queue 64 rows at a time
+    auto drain = [&]() {
+        __builtin_amdgcn_wave_barrier();
+        while (tail - head >= (uint32_t)kWave) {
+            const uint32_t e = queue[(head + lane) & qmask];
+            const int64_t row = ((int64_t)blockIdx.x + (int64_t)(e >> 16) * stride) * T::ITEMS + (e & 0xffffu);
+            finish_row(p, dense, row, out, scalar_acc, bad_group);
+            head += kWave;
+        }
+        __builtin_amdgcn_wave_barrier();
+    };
+    // compact the wave's live rows of the current tile into its queue, half a
+    // tile at a time, draining in between (so the queue holds fewer than 64
+    // rows plus half a tile's share of the wave)
     auto enqueue = [&]() {
-        uint32_t total;
-        const uint32_t off = wave_exclusive_scan_small<T::CBITS>((uint32_t)__popc(alive_c), total);
-        if (total) {
-            uint32_t pos = tail + off;
-            uint32_t m = alive_c;
-            while (m) {
-                const int k = __builtin_ctz(m);
-                m &= m - 1u;
-                const uint32_t local = (uint32_t)(((k / T::VEC) * BLOCK + threadIdx.x) * T::VEC + (k % T::VEC));
-                queue[pos & qmask] = (k_cur << 16) | local;
-                ++pos;
+        constexpr int HALF = IPT >= 8 ? IPT / 2 : IPT;
+#pragma unroll
+        for (int h = 0; h < IPT; h += HALF) {
+            const uint32_t part = alive_c & ((HALF == 32 ? 0xffffffffu : ((1u << HALF) - 1u)) << h);
+            uint32_t total;
+            const uint32_t off = wave_exclusive_scan_small<T::CBITS>((uint32_t)__popc(part), total);
+            if (total) {
+                uint32_t pos = tail + off;
+                uint32_t m = part;
+                while (m) {
+                    const int k = __builtin_ctz(m);
+                    m &= m - 1u;
+                    const uint32_t local = (uint32_t)(((k / T::VEC) * BLOCK + threadIdx.x) * T::VEC + (k % T::VEC));
+                    queue[pos & qmask] = (k_cur << 16) | local;
+                    ++pos;
+                }
+                tail += total;
+                drain();
             }
-            tail += total;
-            __builtin_amdgcn_wave_barrier();
-            while (tail - head >= (uint32_t)kWave) {
-                const uint32_t e = queue[(head + lane) & qmask];
-                const int64_t row = ((int64_t)blockIdx.x + (int64_t)(e >> 16) * stride) * T::ITEMS + (e & 0xffffu);
-                finish_row(p, dense, row, out, scalar_acc, bad_group);
-                head += kWave;
-            }
-            __builtin_amdgcn_wave_barrier();
         }
     };
 
     if constexpr (NARROW == 2 || NARROW == 3) {
         // narrow and bit-packed columns: the buffers hold the loaded words,
         // decoded where a step uses them
-        using Raw = RawTile<IPT, NARROW>;
-        Raw a0, a1, b0, b1;
+        RawTile<IPT, NARROW> a, b;
         if (t_cur < n_tiles) {
             alive_c = valid_mask<BLOCK, IPT>(t_cur * T::ITEMS, p.n_rows);
             if (dense >= 1) {
-                load_raw_tile<BLOCK, IPT, NARROW>(cd0, p.n_rows, t_cur * T::ITEMS, false, 0u, a0);
+                load_raw_tile<BLOCK, IPT, NARROW>(cd0, p.n_rows, t_cur * T::ITEMS, false, 0u, a);
                 int32_t v[IPT];
-                decode_tile<BLOCK, IPT, NARROW>(cd0, t_cur * T::ITEMS, a0, v);
+                decode_tile<BLOCK, IPT, NARROW>(cd0, t_cur * T::ITEMS, a, v);
                 alive_c = star_step_tile<IPT>(p, 0, lds, so0, v, alive_c);
             }
-            if (dense >= 2) load_raw_tile<BLOCK, IPT, NARROW>(cd1, p.n_rows, t_cur * T::ITEMS, true, alive_c, b0);
+            if (dense >= 2) load_raw_tile<BLOCK, IPT, NARROW>(cd1, p.n_rows, t_cur * T::ITEMS, true, alive_c, b);
             if (dense >= 1 && t_cur + stride < n_tiles)
-                load_raw_tile<BLOCK, IPT, NARROW>(cd0, p.n_rows, (t_cur + stride) * T::ITEMS, false, 0u, a0);
-            if (PF == 2 && dense >= 1 && t_cur + 2 * stride < n_tiles)
-                load_raw_tile<BLOCK, IPT, NARROW>(cd0, p.n_rows, (t_cur + 2 * stride) * T::ITEMS, false, 0u, a1);
+                load_raw_tile<BLOCK, IPT, NARROW>(cd0, p.n_rows, (t_cur + stride) * T::ITEMS, false, 0u, a);
         }
-        auto iterate = [&](Raw &an, Raw &bc, Raw &bn) -> bool {
-            const int64_t t_nxt = t_cur + stride;
-            const bool has_nxt = t_nxt < n_tiles;
-            uint32_t alive_n = 0;
-            if (has_nxt) {
-                alive_n = valid_mask<BLOCK, IPT>(t_nxt * T::ITEMS, p.n_rows);
-                const int64_t t_pf = t_nxt + PF * stride;
-                int32_t v[IPT];
-                if (dense >= 1) decode_tile<BLOCK, IPT, NARROW>(cd0, t_nxt * T::ITEMS, an, v);
-                if (dense >= 1 && so0 >= 0) {
-                    StagedProbe<IPT> pr;
-                    pr.begin(lds, so0, p.joins[0].key_min, bitmap_words_of(p.joins[0].span), v, alive_n);
-                    if (t_pf < n_tiles)
-                        load_raw_tile<BLOCK, IPT, NARROW>(cd0, p.n_rows, t_pf * T::ITEMS, false, 0u, an);
-                    alive_n = pr.end();
-                } else {
-                    if (dense >= 1) alive_n = star_step_tile<IPT>(p, 0, lds, so0, v, alive_n);
-                    if (dense >= 1 && t_pf < n_tiles)
-                        load_raw_tile<BLOCK, IPT, NARROW>(cd0, p.n_rows, t_pf * T::ITEMS, false, 0u, an);
-                }
-                if (dense >= 2) load_raw_tile<BLOCK, IPT, NARROW>(cd1, p.n_rows, t_nxt * T::ITEMS, true, alive_n, bn);
-            }
-            if (dense >= 2) {
-                int32_t v[IPT];
-                decode_tile<BLOCK, IPT, NARROW>(cd1, t_cur * T::ITEMS, bc, v);
-                alive_c = star_step_tile<IPT>(p, 1, lds, so1, v, alive_c);
-            }
-            enqueue();
-            if (!has_nxt) return false;
-            t_cur = t_nxt;
-            ++k_cur;
-            alive_c = alive_n;
-            return true;
-        };
         if (t_cur < n_tiles) {
             for (;;) {
-                if (!iterate(a0, b0, b1)) break;
-                if (!iterate(PF == 2 ? a1 : a0, b1, b0)) break;
+                const int64_t t_nxt = t_cur + stride;
+                const bool has_nxt = t_nxt < n_tiles;
+                uint32_t alive_n = 0;
+                if (has_nxt) {
+                    alive_n = valid_mask<BLOCK, IPT>(t_nxt * T::ITEMS, p.n_rows);
+                    if (dense >= 1) {
+                        int32_t v[IPT];
+                        decode_tile<BLOCK, IPT, NARROW>(cd0, t_nxt * T::ITEMS, a, v);
+                        if (t_nxt + stride < n_tiles)
+                            load_raw_tile<BLOCK, IPT, NARROW>(cd0, p.n_rows, (t_nxt + stride) * T::ITEMS, false, 0u, a);
+                        alive_n = star_step_tile<IPT>(p, 0, lds, so0, v, alive_n);
+                    }
+                }
+                if (dense >= 2) {
+                    int32_t v[IPT];
+                    decode_tile<BLOCK, IPT, NARROW>(cd1, t_cur * T::ITEMS, b, v);
+                    if (has_nxt) load_raw_tile<BLOCK, IPT, NARROW>(cd1, p.n_rows, t_nxt * T::ITEMS, true, alive_n, b);
+                    alive_c = star_step_tile<IPT>(p, 1, lds, so1, v, alive_c);
+                }
+                enqueue();
+                if (!has_nxt) break;
+                t_cur = t_nxt;
+                ++k_cur;
+                alive_c = alive_n;
             }
         }
     } else {
-        int32_t a0[IPT], a1[IPT];  // first-step column of upcoming tiles
-        int32_t b0[IPT], b1[IPT];  // second-step column of the current and the next tile
+        int32_t a[IPT];  // first-step column of the next tile
+        int32_t b[IPT];  // second-step column of the current tile
         if (t_cur < n_tiles) {
             alive_c = valid_mask<BLOCK, IPT>(t_cur * T::ITEMS, p.n_rows);
             if (dense >= 1) {
-                load_col_tile<BLOCK, IPT, NARROW>(cd0, p.n_rows, t_cur * T::ITEMS, a0);
-                alive_c = star_step_tile<IPT>(p, 0, lds, so0, a0, alive_c);
+                load_col_tile<BLOCK, IPT, NARROW>(cd0, p.n_rows, t_cur * T::ITEMS, a);
+                alive_c = star_step_tile<IPT>(p, 0, lds, so0, a, alive_c);
             }
-            if (dense >= 2) load_col_tile_sel<BLOCK, IPT, NARROW>(cd1, p.n_rows, t_cur * T::ITEMS, alive_c, b0);
+            if (dense >= 2) load_col_tile_sel<BLOCK, IPT, NARROW>(cd1, p.n_rows, t_cur * T::ITEMS, alive_c, b);
             if (dense >= 1 && t_cur + stride < n_tiles)
-                load_col_tile<BLOCK, IPT, NARROW>(cd0, p.n_rows, (t_cur + stride) * T::ITEMS, a0);
-            if (PF == 2 && dense >= 1 && t_cur + 2 * stride < n_tiles)
-                load_col_tile<BLOCK, IPT, NARROW>(cd0, p.n_rows, (t_cur + 2 * stride) * T::ITEMS, a1);
+                load_col_tile<BLOCK, IPT, NARROW>(cd0, p.n_rows, (t_cur + stride) * T::ITEMS, a);
         }
-        // One pipeline iteration.  `an` holds the first-step column of t_nxt;
-        // `bc` the second-step column of t_cur; `bn` receives that of t_nxt.
-        auto iterate = [&](int32_t(&an)[IPT], int32_t(&bc)[IPT], int32_t(&bn)[IPT]) -> bool {
-            const int64_t t_nxt = t_cur + stride;
-            const bool has_nxt = t_nxt < n_tiles;
-            uint32_t alive_n = 0;
-            if (has_nxt) {
-                alive_n = valid_mask<BLOCK, IPT>(t_nxt * T::ITEMS, p.n_rows);
-                const int64_t t_pf = t_nxt + PF * stride;
-                if (dense >= 1 && so0 >= 0) {
-                    // staged first step: issue its LDS reads, then reuse the key
-                    // registers for the prefetch before testing the bits
-                    StagedProbe<IPT> pr;
-                    pr.begin(lds, so0, p.joins[0].key_min, bitmap_words_of(p.joins[0].span), an, alive_n);
-                    if (t_pf < n_tiles) load_col_tile<BLOCK, IPT, NARROW>(cd0, p.n_rows, t_pf * T::ITEMS, an);
-                    alive_n = pr.end();
-                } else {
-                    if (dense >= 1) alive_n = star_step_tile<IPT>(p, 0, lds, so0, an, alive_n);
-                    if (dense >= 1 && t_pf < n_tiles)
-                        load_col_tile<BLOCK, IPT, NARROW>(cd0, p.n_rows, t_pf * T::ITEMS, an);
-                }
-                if (dense >= 2) load_col_tile_sel<BLOCK, IPT, NARROW>(cd1, p.n_rows, t_nxt * T::ITEMS, alive_n, bn);
-            }
-            if (dense >= 2) alive_c = star_step_tile<IPT>(p, 1, lds, so1, bc, alive_c);
-            enqueue();
-            if (!has_nxt) return false;
-            t_cur = t_nxt;
-            ++k_cur;
-            alive_c = alive_n;
-            return true;
-        };
         if (t_cur < n_tiles) {
             for (;;) {
-                if (!iterate(a0, b0, b1)) break;
-                if (!iterate(PF == 2 ? a1 : a0, b1, b0)) break;
+                const int64_t t_nxt = t_cur + stride;
+                const bool has_nxt = t_nxt < n_tiles;
+                uint32_t alive_n = 0;
+                if (has_nxt) {
+                    alive_n = valid_mask<BLOCK, IPT>(t_nxt * T::ITEMS, p.n_rows);
+                    if (dense >= 1) alive_n = star_step_tile<IPT>(p, 0, lds, so0, a, alive_n);
+                }
+                if (dense >= 2) alive_c = star_step_tile<IPT>(p, 1, lds, so1, b, alive_c);
+                if (has_nxt) {
+                    if (dense >= 2) load_col_tile_sel<BLOCK, IPT, NARROW>(cd1, p.n_rows, t_nxt * T::ITEMS, alive_n, b);
+                    if (dense >= 1 && t_nxt + stride < n_tiles)
+                        load_col_tile<BLOCK, IPT, NARROW>(cd0, p.n_rows, (t_nxt + stride) * T::ITEMS, a);
+                }
+                enqueue();
+                if (!has_nxt) break;
+                t_cur = t_nxt;
+                ++k_cur;
+                alive_c = alive_n;
             }
         }
     }
@@ -589,6 +569,24 @@ int64_t star_max_grid(int64_t n_rows) {
     return resident > by_index ? resident : by_index;
 }
 
+// Workgroups of a kernel instance resident on one CU at once, for a block
+// size and dynamic LDS bytes (cached per instance and LDS size).
+static hipError_t resident_per_cu(const void *fn, int block, int64_t lds_bytes, int64_t &out) {
+    static std::mutex mu;
+    static std::map<std::pair<const void *, int64_t>, int64_t> cache;
+    std::lock_guard<std::mutex> lk(mu);
+    const auto key = std::make_pair(fn, lds_bytes);
+    auto it = cache.find(key);
+    if (it == cache.end()) {
+        int n = 0;
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, block, (size_t)lds_bytes);
+        if (e != hipSuccess) return e;
+        it = cache.emplace(key, (int64_t)n).first;
+    }
+    out = it->second;
+    return hipSuccess;
+}
+
 template <int BLOCK, int IPT>
 static hipError_t star_t(const LaunchCfg &cfg, StarPlanDev p, uint64_t *out, int32_t *status,
                          uint64_t *partials, bool accumulate, hipStream_t s) {
@@ -606,24 +604,14 @@ static hipError_t star_t(const LaunchCfg &cfg, StarPlanDev p, uint64_t *out, int
         p.stage_off[d] = (int32_t)words;
         words += bitmap_bytes(j) / 4 + 4;  // the bitmap, then one zero 16-byte chunk
     }
-    // per-wave queue: up to one wave's tile share (64 * IPT rows) on top of
-    // fewer than 64 rows left from earlier tiles
+    // per-wave queue: half a tile's share of the wave (64 * IPT / 2 rows, or
+    // the whole share below 8 items per thread) on top of fewer than 64 rows
+    // left from earlier tiles
     int64_t qcap = 1;
-    while (qcap < kWave + kWave * IPT) qcap <<= 1;
+    while (qcap < kWave + kWave * (IPT >= 8 ? IPT / 2 : IPT)) qcap <<= 1;
     p.queue_off = (int32_t)words;
     p.queue_cap = (int32_t)qcap;
     const int64_t lds_bytes = (words + qcap * T::WAVES) * 4;
-    // workgroups: fill the CUs as far as waves and LDS allow, unless tuned
-    int64_t per_cu = cfg.grid_per_cu > 0 ? cfg.grid_per_cu : 2048 / BLOCK;
-    const int64_t lds_cap = device_lds_per_cu() / (lds_bytes + 1024);
-    if (per_cu > lds_cap) per_cu = lds_cap > 0 ? lds_cap : 1;
-    if (per_cu > kStarMaxGridPerCu) per_cu = kStarMaxGridPerCu;
-    int64_t grid = per_cu * device_cu_count();
-    const int64_t min_grid = (n_tiles + 65534) / 65535;  // queue entries hold a 16-bit tile index
-    if (grid < min_grid) grid = min_grid;
-    if (grid > n_tiles) grid = n_tiles;
-    if (grid < 1) grid = 1;
-    // prefetch depth one tile (a second register buffer costs more waves than it gains)
     int n4 = 0, n2 = 0, nb = 0;
     for (int d = 0; d < dense; ++d) {
         const int c = d < p.n_preds ? p.pred_col[d] : p.joins[d - p.n_preds].fk_col;
@@ -631,18 +619,32 @@ static hipError_t star_t(const LaunchCfg &cfg, StarPlanDev p, uint64_t *out, int
         n2 += p.col[c].width == 2;
         nb += p.col[c].bits > 0;
     }
-    auto fn = n4 == dense   ? star_kernel<BLOCK, IPT, 1, 0>
-              : n2 == dense ? star_kernel<BLOCK, IPT, 1, 2>
-              : nb == dense ? star_kernel<BLOCK, IPT, 1, 3>
-                            : star_kernel<BLOCK, IPT, 1, 1>;
+    auto fn = n4 == dense   ? star_kernel<BLOCK, IPT, 0>
+              : n2 == dense ? star_kernel<BLOCK, IPT, 2>
+              : nb == dense ? star_kernel<BLOCK, IPT, 3>
+                            : star_kernel<BLOCK, IPT, 1>;
     if (lds_bytes > 65536) {
         hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            (int)lds_bytes);
         if (e != hipSuccess) return e;
     }
+    // workgroups: as many per CU as are resident at once (registers and LDS
+    // permitting), or fewer if tuned; a persistent workgroup that is not
+    // resident would start late and finish its tiles last
+    int64_t per_cu = 0;
+    hipError_t e = resident_per_cu((const void *)fn, BLOCK, lds_bytes, per_cu);
+    if (e != hipSuccess) return e;
+    if (cfg.grid_per_cu > 0 && cfg.grid_per_cu < per_cu) per_cu = cfg.grid_per_cu;
+    if (per_cu > kStarMaxGridPerCu) per_cu = kStarMaxGridPerCu;
+    if (per_cu < 1) per_cu = 1;
+    int64_t grid = per_cu * device_cu_count();
+    const int64_t min_grid = (n_tiles + 65534) / 65535;  // queue entries hold a 16-bit tile index
+    if (grid < min_grid) grid = min_grid;
+    if (grid > n_tiles) grid = n_tiles;
+    if (grid < 1) grid = 1;
     hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(BLOCK), (size_t)lds_bytes, s, p, out, status, n_tiles,
                        partials);
-    hipError_t e = hipGetLastError();
+    e = hipGetLastError();
     if (e != hipSuccess || !p.scalar) return e;
     hipLaunchKernelGGL(star_finalize_kernel, dim3(1), dim3(256), 0, s, partials, grid, out, accumulate ? 1 : 0);
     return hipGetLastError();
