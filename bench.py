@@ -124,13 +124,14 @@ def star_algorithmic_bytes(t, order, line=FETCH_BYTES, bits=None):
     return total, int(alive.sum())
 
 
-def measured_traffic(order, n):
+def measured_traffic(order, n, packed=False):
     """HBM bytes per star-kernel launch from the committed rocprofv3 counter
     record (FETCH_SIZE and WRITE_SIZE scaled by a plain copy), or None when
     the record is missing, was taken on another workload, or the kernel
-    sources changed since."""
+    sources changed since.  packed: the bit-packed layout's record."""
     from paper_2003_01178_amd import rocprof_summary
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "star_kernel_120M_traffic.json")
+    name = "star_kernel_120M_bitpacked_traffic.json" if packed else "star_kernel_120M_traffic.json"
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", name)
     try:
         with open(path) as f:
             rec = json.load(f)
@@ -572,7 +573,7 @@ def main():
                     algorithmic_bytes=alg_bytes, bytes_per_row=alg_bytes / n, kernel_ms=kern_ms,
                     kernel_rows_per_s=n / (kern_ms * 1e-3), algorithmic_bytes_c64=alg_bytes_c64,
                     frac_c64=alg_bytes_c64 / (kern_ms * 1e-3) / 1e9 / HBM_PEAK_GBS)
-        roof["traffic"] = None if args.narrow else measured_traffic(order, n)
+        roof["traffic"] = measured_traffic(order, n, packed=args.narrow)
         if not args.no_cpu_baseline:
             import oracle
             from_cols = [*t.fk, t.m1, t.m2]

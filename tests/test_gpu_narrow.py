@@ -155,7 +155,7 @@ def decode_bits(words, n, bits, base):
     return f.astype(np.int64) + base
 
 
-@pytest.mark.parametrize("bits", [1, 3, 7, 12, 16])
+@pytest.mark.parametrize("bits", [1, 2, 3, 5, 7, 8, 9, 11, 12, 13, 15, 16])
 @pytest.mark.parametrize("n", [0, 1, 5, 4097, 1_000_003])
 def test_pack_bits_round_trip(bits, n):
     announce("pack bits", bits, n)
@@ -243,3 +243,36 @@ def test_q11_bitpacked_matches_oracle(n):
         out, st = plan.run()
         cx.check_status(st)
         assert int(out.item()) == q11_oracle(f, year, (d, d + 2), q)
+
+
+@pytest.mark.parametrize("bits", list(range(1, 17)))
+def test_bitpacked_predicates_every_width(bits):
+    """Three range predicates over bit-packed columns of widths b, 17 - b and
+    b (the first two are the dense steps, so every width runs through the
+    four-row decode at every bit alignment; the third is read row by row),
+    with bases that make the offsets span the whole width, then SUM(m):
+    equal to the oracle on the int32 values."""
+    announce("bitpacked predicates", bits)
+    n = 100_003
+    rng = np.random.default_rng(1000 + bits)
+    widths = (bits, 17 - bits, bits)
+    bases = [int(rng.integers(-(1 << 30), 1 << 30)) for _ in widths]
+    cols = [(rng.integers(0, 1 << w, size=n, dtype=np.int64) + b).astype(np.int32) for w, b in zip(widths, bases)]
+    m = rng.integers(-(1 << 20), 1 << 20, size=n, dtype=np.int64).astype(np.int32)
+    packed = []
+    for c, w, b in zip(cols, widths, bases):
+        col, st = cx.pack_column_bits(dev(c), b, w)
+        cx.check_status(st)
+        packed.append(col)
+    # each range keeps about three quarters of its column's values
+    preds = []
+    for k, (w, b) in enumerate(zip(widths, bases)):
+        span = 1 << w
+        lo = b + span // 8
+        hi = b + span - 1 - span // 8
+        preds.append((k, lo, hi))
+    plan = cx.StarQuery([*packed, dev(m)], n_groups=1, preds=preds, agg=cx.AGG_SUM, agg_cols=(3, 0))
+    out, st = plan.run()
+    cx.check_status(st)
+    want = oracle.star([*cols, m], 1, preds=preds, agg=oracle.AGG_SUM, agg_cols=(3, 0))
+    assert int(out.item()) == int(want[0])
