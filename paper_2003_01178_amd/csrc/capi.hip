@@ -5,7 +5,9 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <map>
 #include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "block.hpp"
@@ -46,6 +48,22 @@ int64_t device_lds_per_cu() {
         cache[d] = v;
     }
     return cache[d];
+}
+
+hipError_t resident_per_cu(const void *fn, int block, int64_t lds_bytes, int64_t &out) {
+    static std::mutex mu;
+    static std::map<std::tuple<int, const void *, int, int64_t>, int64_t> cache;
+    const auto key = std::make_tuple(cur_device(), fn, block, lds_bytes);
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(key);
+    if (it == cache.end()) {
+        int n = 0;
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, block, (size_t)lds_bytes);
+        if (e != hipSuccess) return e;
+        it = cache.emplace(key, (int64_t)n).first;
+    }
+    out = it->second;
+    return hipSuccess;
 }
 
 int64_t device_lds_per_block() {

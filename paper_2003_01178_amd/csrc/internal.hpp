@@ -20,6 +20,11 @@ int device_cu_count();
 int64_t device_lds_per_block();
 // LDS of one compute unit of the current device.
 int64_t device_lds_per_cu();
+// Workgroups of kernel `fn` resident on one CU of the current device at
+// once, for `block` threads and `lds_bytes` of dynamic LDS (the occupancy
+// query, cached per device, kernel and LDS size).  A persistent grid larger
+// than this per CU would start its extra workgroups late.
+hipError_t resident_per_cu(const void *fn, int block, int64_t lds_bytes, int64_t &out);
 
 // Workgroups to launch for n_tiles tiles under cfg.
 inline int64_t grid_for(int64_t n_tiles, const LaunchCfg &cfg) {

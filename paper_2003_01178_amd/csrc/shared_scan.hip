@@ -702,18 +702,21 @@ static hipError_t shared_t(const LaunchCfg &cfg_in, const BatchDev &b_in, int32_
         words32 += qwords;
     }
     const int64_t lds_bytes = words32 * 4;
-    if (words32 > acc_words32) {
-        const int64_t fit = device_lds_per_cu() / (lds_bytes + 1024);
-        if (cfg.grid_per_cu > fit) cfg.grid_per_cu = (int)fit;
-    }
-    const int64_t grid = grid_for(n_tiles, cfg);
-    if (grid == 0) return hipSuccess;
     const size_t lds = (size_t)lds_bytes;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute((const void *)shared_scan_kernel<BLOCK, IPT>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
+    // persistent workgroups: no more per CU than are resident at once
+    // (registers and LDS permitting)
+    int64_t fit = 0;
+    hipError_t e = resident_per_cu((const void *)shared_scan_kernel<BLOCK, IPT>, BLOCK, lds_bytes, fit);
+    if (e != hipSuccess) return e;
+    if (fit < 1) fit = 1;
+    if (cfg.grid_per_cu > fit) cfg.grid_per_cu = (int)fit;
+    const int64_t grid = grid_for(n_tiles, cfg);
+    if (grid == 0) return hipSuccess;
     hipLaunchKernelGGL((shared_scan_kernel<BLOCK, IPT>), dim3((unsigned)grid), dim3(BLOCK), lds, s, b, status,
                        n_tiles);
     return hipGetLastError();

@@ -26,7 +26,6 @@
 // (BlockAggregate) into a partial in scratch memory and summed by a one-
 // workgroup finalize kernel, which avoids same-address atomics from every
 // workgroup.
-#include <map>
 #include <mutex>
 
 #include "block.hpp"
@@ -567,24 +566,6 @@ int64_t star_max_grid(int64_t n_rows) {
     const int64_t resident = (int64_t)kStarMaxGridPerCu * device_cu_count();
     const int64_t by_index = ((n_rows + 255) / 256 + 65534) / 65535;
     return resident > by_index ? resident : by_index;
-}
-
-// Workgroups of a kernel instance resident on one CU at once, for a block
-// size and dynamic LDS bytes (cached per instance and LDS size).
-static hipError_t resident_per_cu(const void *fn, int block, int64_t lds_bytes, int64_t &out) {
-    static std::mutex mu;
-    static std::map<std::pair<const void *, int64_t>, int64_t> cache;
-    std::lock_guard<std::mutex> lk(mu);
-    const auto key = std::make_pair(fn, lds_bytes);
-    auto it = cache.find(key);
-    if (it == cache.end()) {
-        int n = 0;
-        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, block, (size_t)lds_bytes);
-        if (e != hipSuccess) return e;
-        it = cache.emplace(key, (int64_t)n).first;
-    }
-    out = it->second;
-    return hipSuccess;
 }
 
 template <int BLOCK, int IPT>

@@ -133,6 +133,10 @@ def test_q11_domains_cover_the_columns(banded):
     for dm, col in zip(sv.q11_domains, (t.fk[0], t.extra["discount"], t.extra["quantity"])):
         assert dm["key_min"] == int(col.min()) and dm["key_max"] == int(col.max())
     assert sv.q11_domains[1]["key_max"] == 15 and sv.q11_domains[2]["key_min"] == 0
+    # the date domain is the column's distinct values, in a rank-compressed table
+    date = sv.q11_domains[0]
+    assert np.array_equal(date["key"].cpu().numpy(), np.unique(t.fk[0]))
+    assert date["mask"].ranked == len(np.unique(t.fk[0]))
 
 
 def test_server_full_size_ragged_segments(banded):
