@@ -53,6 +53,7 @@ def parse():
     p.add_argument("--bits", type=int, default=8, help="partition: radix bits")
     p.add_argument("--shift", type=int, default=0, help="partition: start bit")
     p.add_argument("--unstable", action="store_true", help="partition: the unstable shuffle")
+    p.add_argument("--msb", action="store_true", help="sort: most significant digit first")
     p.add_argument("--order", default="1,0,2,3", help="star join order")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-graph", action="store_true", help="star: launch eagerly instead of replaying HIP graphs")
@@ -835,6 +836,11 @@ def main():
             call = lambda: cx.radix_partition(keys, args.shift, args.bits, vals=vals, out_keys=ok, out_vals=ov,
                                               part_offsets=offs, scratch=scratch, stable=not args.unstable)
             passes = 1
+        elif args.msb:
+            scratch = torch.empty(cx.load().crystal_sort_pairs_msb_scratch_bytes(n, 1), dtype=torch.uint8,
+                                  device="cuda")
+            call = lambda: cx.sort_pairs(keys, vals, out_keys=ok, out_vals=ov, scratch=scratch, msb=True)
+            passes = 2   # uniform keys: two partition levels, then the local sort (counted below)
         else:
             scratch = torch.empty(cx.load().crystal_sort_pairs_scratch_bytes(n, 1), dtype=torch.uint8,
                                   device="cuda")
@@ -851,11 +857,13 @@ def main():
         elapsed = time.perf_counter() - t0
         kern_ms = timer.mean_ms()
         # per pass: the histogram reads the keys (4n), the shuffle reads keys and
-        # values (8n) and writes them (8n)
-        b = passes * 20 * n
+        # values (8n) and writes them (8n); the MSB sort's local pass reads and
+        # writes every pair once more (16n)
+        b = passes * 20 * n + (16 * n if args.workload == "sort" and args.msb else 0)
         what = (f"radix partition ({'unstable' if args.unstable else 'stable'}) of 2^{n.bit_length() - 1} "
                 f"key/value pairs on {args.bits} bits at bit {args.shift}"
-                if args.workload == "partition" else f"radix sort of {n} 32-bit key/value pairs")
+                if args.workload == "partition" else
+                f"radix sort ({'MSB first' if args.msb else 'LSB first'}) of {n} 32-bit key/value pairs")
         result.update(metric="pairs/s", value=n * K / elapsed, unit="pairs/s", ms_per_step=elapsed / K * 1e3,
                       dtype="u32", config={"workload": what, "pairs": n, "passes": passes,
                                            "tile": list(cx.tune_get(cx.K_RADIX, n))})

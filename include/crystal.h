@@ -59,7 +59,7 @@ typedef struct crystal_range {
 const char *crystal_status_string(int32_t status);
 
 /* ABI version of this header (incremented on any layout change). */
-#define CRYSTAL_ABI_VERSION 9
+#define CRYSTAL_ABI_VERSION 10
 int32_t crystal_abi_version(void);
 
 /* sizeof of the ABI structs as compiled into the library, so a binding can
@@ -610,6 +610,20 @@ size_t crystal_sort_pairs_scratch_bytes(int64_t n, int32_t with_values);
 /* partition passes from the low byte up.  vals / out_vals as above.        */
 crystal_status crystal_sort_pairs(const uint32_t *keys, const uint32_t *vals, int64_t n, uint32_t *out_keys,
                                   uint32_t *out_vals, void *scratch, size_t scratch_bytes, void *stream);
+
+/* MSB radix sort (section 4.4: the GPU sort takes the most significant     */
+/* 8-bit digit first).  Same result as crystal_sort_pairs: the stable       */
+/* ascending order of the pairs by unsigned key.  Levels of stable 8-bit    */
+/* partitions split every segment longer than 8,192 pairs by its next digit */
+/* (the first level splits the whole input by the top byte); every shorter  */
+/* segment is then sorted in LDS by its remaining low bits by one           */
+/* workgroup.  Uniform keys take two partition levels and the local pass.   */
+/* Arguments, ownership and errors as crystal_sort_pairs; scratch (device,  */
+/* 256-byte aligned) of crystal_sort_pairs_msb_scratch_bytes(n, with_values) */
+/* bytes holds one copy of the pairs and the work lists.                    */
+size_t crystal_sort_pairs_msb_scratch_bytes(int64_t n, int32_t with_values);
+crystal_status crystal_sort_pairs_msb(const uint32_t *keys, const uint32_t *vals, int64_t n, uint32_t *out_keys,
+                                      uint32_t *out_vals, void *scratch, size_t scratch_bytes, void *stream);
 
 /* ------------------------------------------------------------------------ */
 /* Tile-size tuning (section 3.3: the tile is BLOCK threads x IPT items per */

@@ -75,9 +75,10 @@ def build_sanitized(out_dir: str, jobs: int | None = None) -> str:
 
     def one(src):
         obj = os.path.join(out_dir, os.path.basename(src).replace(".hip", ".o"))
-        # device code unoptimised where it compiles that way (the radix kernels pin
-        # values to scalar registers, which needs the optimiser to prove them uniform)
-        dev_opt = [] if os.path.basename(src) == "radix.hip" else ["-Xarch_device", "-O0"]
+        # device code unoptimised where it compiles that way (the radix and MSB sort
+        # kernels pin values to scalar registers, which needs the optimiser to prove
+        # them uniform)
+        dev_opt = [] if os.path.basename(src) in ("radix.hip", "msb_sort.hip") else ["-Xarch_device", "-O0"]
         r = subprocess.run([HIPCC, *SAN_FLAGS, *dev_opt, "-c", src, "-o", obj], capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError(f"hipcc failed on {src}:\n{r.stderr[-6000:]}")

@@ -166,6 +166,8 @@ def _declare(lib):
                                                      ctypes.c_size_t, c_vp]),
         "crystal_sort_pairs_scratch_bytes": (ctypes.c_size_t, [c_i64, c_i32]),
         "crystal_sort_pairs": (c_i32, [c_vp, c_vp, c_i64, c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp]),
+        "crystal_sort_pairs_msb_scratch_bytes": (ctypes.c_size_t, [c_i64, c_i32]),
+        "crystal_sort_pairs_msb": (c_i32, [c_vp, c_vp, c_i64, c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp]),
         "crystal_tune_variants": (c_i32, [c_i32, P(c_i32), P(c_i32), c_i32]),
         "crystal_tune_set": (c_i32, [c_i32, c_i32, c_i32, c_i32, c_i32, c_i32]),
         "crystal_tune_get": (c_i32, [c_i32, c_i64, P(c_i32), P(c_i32), P(c_i32)]),
@@ -833,18 +835,21 @@ def radix_partition(keys, shift, bits, vals=None, out_keys=None, out_vals=None, 
     return out_keys, out_vals, part_offsets
 
 
-def sort_pairs(keys, vals=None, out_keys=None, out_vals=None, scratch=None, stream=None):
-    """Section 4.4 sort: stable sort of (key, value) pairs by unsigned 32-bit key."""
+def sort_pairs(keys, vals=None, out_keys=None, out_vals=None, scratch=None, stream=None, msb=False):
+    """Section 4.4 sort: stable sort of (key, value) pairs by unsigned 32-bit key.
+    msb: most significant digit first (crystal_sort_pairs_msb), else four
+    passes from the low byte up (crystal_sort_pairs); the results are equal."""
     lib = load()
     n = keys.numel()
     dev = keys.device
     out_keys = torch.empty(max(n, 1), dtype=torch.int32, device=dev) if out_keys is None else out_keys
     if vals is not None and out_vals is None:
         out_vals = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
-    scratch = _scratch(lib.crystal_sort_pairs_scratch_bytes(n, int(vals is not None)), scratch, dev)
-    _check(lib.crystal_sort_pairs(_words(keys, n, "keys"), _words(vals, n, "vals"), n,
-                                  _words(out_keys, n, "out_keys"), _words(out_vals, n, "out_vals"), _ptr(scratch),
-                                  scratch.numel(), _stream(stream)), "crystal_sort_pairs")
+    name = "crystal_sort_pairs_msb" if msb else "crystal_sort_pairs"
+    scratch = _scratch(getattr(lib, name + "_scratch_bytes")(n, int(vals is not None)), scratch, dev)
+    _check(getattr(lib, name)(_words(keys, n, "keys"), _words(vals, n, "vals"), n,
+                              _words(out_keys, n, "out_keys"), _words(out_vals, n, "out_vals"), _ptr(scratch),
+                              scratch.numel(), _stream(stream)), name)
     return out_keys, out_vals
 
 

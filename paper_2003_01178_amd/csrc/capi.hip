@@ -735,6 +735,22 @@ crystal_status crystal_sort_pairs(const uint32_t *keys, const uint32_t *vals, in
     return CRYSTAL_OK;
 }
 
+size_t crystal_sort_pairs_msb_scratch_bytes(int64_t n, int32_t with_values) {
+    if (n <= 0) return 256;
+    return (size_t)msb_sort_scratch_bytes(n, with_values != 0);
+}
+
+crystal_status crystal_sort_pairs_msb(const uint32_t *keys, const uint32_t *vals, int64_t n, uint32_t *out_keys,
+                                      uint32_t *out_vals, void *scratch, size_t scratch_bytes, void *stream) {
+    if (!radix_args_ok(keys, vals, n, out_keys, out_vals)) return CRYSTAL_EINVAL;
+    if (n == 0) return CRYSTAL_OK;
+    if (!scratch || ((uintptr_t)scratch & 255u)) return scratch ? CRYSTAL_EINVAL : CRYSTAL_ESCRATCH;
+    if (scratch_bytes < crystal_sort_pairs_msb_scratch_bytes(n, vals != nullptr)) return CRYSTAL_ESCRATCH;
+    const LaunchCfg cfg = tune_lookup(CRYSTAL_K_RADIX, n);  // the first level's partition pass
+    if (!radix_variant_fits(cfg.block, cfg.ipt)) return CRYSTAL_EINVAL;
+    return from_hip(launch_msb_sort(keys, vals, n, out_keys, out_vals, scratch, as_stream(stream)));
+}
+
 // ----------------------------------------------------------------- tuning --
 int32_t crystal_tune_variants(int32_t kernel, int32_t *blocks, int32_t *ipts, int32_t max) {
     if (kernel < 0 || kernel >= CRYSTAL_K_COUNT) return 0;

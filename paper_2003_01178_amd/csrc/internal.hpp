@@ -73,6 +73,11 @@ hipError_t launch_ht_build(const crystal_ht &ht, const int32_t *keys, const int3
 constexpr int kMaxBuildBatch = CRYSTAL_MAX_BUILD_BATCH;
 hipError_t launch_ht_build_batch(const crystal_ht_build_item *items, int n_items, int32_t *status,
                                  hipStream_t s);
+// MSB radix sort of key/value pairs (vals, out_vals may be null together).
+int64_t msb_sort_scratch_bytes(int64_t n, bool with_values);
+hipError_t launch_msb_sort(const uint32_t *keys, const uint32_t *vals, int64_t n, uint32_t *out_keys,
+                           uint32_t *out_vals, void *scratch, hipStream_t s);
+
 // The builds of a batch into tables that are already clear, the clears of
 // other tables and the zeroing of zero_n int64 words, in one launch.
 hipError_t launch_ht_build_batch_fused(const crystal_ht_build_item *items, int n_items, const crystal_ht *const *clear,

@@ -34,7 +34,7 @@ def test_every_declared_symbol_is_exported(cx):
 
 def test_struct_layout_matches_binding(cx):
     lib = cx.load()
-    assert lib.crystal_abi_version() == 9
+    assert lib.crystal_abi_version() == 10
     for which, ty in enumerate((cx.Range, cx.HT, cx.Pred, cx.Join, cx.StarQueryC, cx.QmaskTableC,
                                 cx.BatchQueryC, cx.BatchC, cx.ServerTemplateC, cx.ServerConfigC,
                                 cx.ServerStatsC, cx.BuildItemC, cx.ColFormatC, cx.QmaskBuildItemC)):
@@ -145,6 +145,14 @@ def test_radix_host_errors(cx):
     assert lib.crystal_sort_pairs(fake_a, None, -1, fake_b, None, None, 0, None) == cx.EINVAL
     assert lib.crystal_sort_pairs(fake_a, None, 1 << 32, fake_b, None, None, 0, None) == cx.EINVAL
     assert lib.crystal_sort_pairs(None, None, 0, None, None, None, 0, None) == cx.OK
+    assert lib.crystal_sort_pairs_msb(fake_a, None, -1, fake_b, None, None, 0, None) == cx.EINVAL
+    assert lib.crystal_sort_pairs_msb(fake_a, None, 1 << 32, fake_b, None, None, 0, None) == cx.EINVAL
+    assert lib.crystal_sort_pairs_msb(fake_a, fake_a, 100, fake_b, None, None, 0, None) == cx.EINVAL
+    assert lib.crystal_sort_pairs_msb(fake_a, None, 100, fake_b, None, None, 0, None) == cx.ESCRATCH
+    assert lib.crystal_sort_pairs_msb(fake_a, None, 100, fake_b, None, ctypes.c_void_p((1 << 24) + 8), 1 << 20,
+                                      None) == cx.EINVAL
+    assert lib.crystal_sort_pairs_msb(None, None, 0, None, None, None, 0, None) == cx.OK
+    assert lib.crystal_sort_pairs_msb_scratch_bytes(1 << 28, 1) > 2 * 4 * (1 << 28)
     assert lib.crystal_radix_histogram(fake_a, 100, 0, 8, None, None) == cx.EINVAL
 
 

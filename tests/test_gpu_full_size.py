@@ -160,17 +160,18 @@ def test_partition_2pow28_properties():
     assert np.all(ov[1:][same] > ov[:-1][same])
 
 
-def test_sort_2pow28_properties():
+@pytest.mark.parametrize("msb", [False, True])
+def test_sort_2pow28_properties(msb):
     """2^28 pairs sorted: keys non-decreasing, values (input positions) a
     permutation that carries each key along, equal keys in input order --
     which characterises the stable sort the oracle defines.  A sample of
     2^20 pairs is also sorted by the oracle and compared exactly."""
-    announce("full radix sort 2^28")
+    announce("full radix sort 2^28", "msb" if msb else "lsb")
     n = 1 << 28
     k, _ = datagen.radix_pairs(n)
     k = k.view(np.uint32)
     v = np.arange(n, dtype=np.uint32)
-    ok, ov = cx.sort_pairs(dev(k.view(np.int32)), dev(v.view(np.int32)))
+    ok, ov = cx.sort_pairs(dev(k.view(np.int32)), dev(v.view(np.int32)), msb=msb)
     torch.cuda.synchronize()
     ok, ov = ok.cpu().numpy().view(np.uint32), ov.cpu().numpy().view(np.uint32)
     assert np.all(ok[1:] >= ok[:-1])
@@ -180,7 +181,7 @@ def test_sort_2pow28_properties():
     assert same.sum() > 0
     assert np.all(ov[1:][same] > ov[:-1][same])
     m = 1 << 20
-    sk, sv = cx.sort_pairs(dev(k[:m].view(np.int32)), dev(v[:m].view(np.int32)))
+    sk, sv = cx.sort_pairs(dev(k[:m].view(np.int32)), dev(v[:m].view(np.int32)), msb=msb)
     wk, wv = oracle.sort_pairs(k[:m], v[:m])
     assert np.array_equal(sk.cpu().numpy().view(np.uint32), wk)
     assert np.array_equal(sv.cpu().numpy().view(np.uint32), wv)

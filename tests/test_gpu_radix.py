@@ -168,6 +168,91 @@ def test_sort_repeated_calls_share_scratch():
         assert np.array_equal(u32(ok, n), wk) and np.array_equal(u32(ov, n), wv)
 
 
+# --------------------------------------------------------------- MSB sort --
+MSB_SIZES = [0, 1, 64, 8192, 8193, 3 * 8192 + 5, 200_003, 1_000_003, 3_000_017]
+
+
+@pytest.mark.parametrize("n", MSB_SIZES)
+@pytest.mark.parametrize("key_bits", [32, 20, 12])
+def test_msb_sort_matches_oracle(n, key_bits):
+    """Most significant digit first.  32-bit keys: two partition levels, then
+    local sorts (200,003 pairs: the first level's segments are short and are
+    grouped).  20- and 12-bit keys leave the top digits equal, so the input
+    stays one segment for several levels, and 12-bit keys reach the last
+    level with runs of equal keys that are copied.  Keys and values equal
+    the oracle's stable sort."""
+    announce("msb sort", n, key_bits)
+    k, v = pairs(n, 1300 + n + key_bits, key_bits=key_bits)
+    ok, ov = cx.sort_pairs(dev(k.view(np.int32)), dev(v.view(np.int32)), msb=True)
+    wk, wv = oracle.sort_pairs(k, v)
+    assert np.array_equal(u32(ok, n), wk)
+    assert np.array_equal(u32(ov, n), wv)
+
+
+@pytest.mark.parametrize("case", ["all_equal", "two_values", "top_byte_only", "sorted", "reversed", "one_big_rest_small"])
+def test_msb_sort_degenerate_inputs(case):
+    """Skewed digit distributions: every key equal (one segment down to the
+    last level, then one copy), two values, keys that differ only in the top
+    byte, presorted and reversed input, and one huge run of a key beside
+    many short segments."""
+    announce("msb sort degenerate", case)
+    n = 300_007
+    rng = np.random.default_rng(31)
+    v = rng.integers(0, 1 << 32, size=n, dtype=np.uint64).astype(np.uint32)
+    if case == "all_equal":
+        k = np.full(n, 0x9E3779B9, dtype=np.uint32)
+    elif case == "two_values":
+        k = np.where(rng.random(n) < 0.5, 7, 0xFFFFFFF0).astype(np.uint32)
+    elif case == "top_byte_only":
+        k = (rng.integers(0, 256, size=n).astype(np.uint32) << np.uint32(24))
+    elif case == "sorted":
+        k = np.sort(rng.integers(0, 1 << 32, size=n, dtype=np.uint64).astype(np.uint32))
+    elif case == "reversed":
+        k = np.sort(rng.integers(0, 1 << 32, size=n, dtype=np.uint64).astype(np.uint32))[::-1].copy()
+    else:
+        k = rng.integers(0, 1 << 32, size=n, dtype=np.uint64).astype(np.uint32)
+        k[rng.random(n) < 0.6] = 0x12345678
+    ok, ov = cx.sort_pairs(dev(k.view(np.int32)), dev(v.view(np.int32)), msb=True)
+    wk, wv = oracle.sort_pairs(k, v)
+    assert np.array_equal(u32(ok, n), wk)
+    assert np.array_equal(u32(ov, n), wv)
+
+
+def test_msb_sort_keys_only_equals_lsb_sort():
+    announce("msb sort keys only")
+    n = 2_000_003
+    k, _ = pairs(n, 1401)
+    ok, ov = cx.sort_pairs(dev(k.view(np.int32)), msb=True)
+    lk, _ = cx.sort_pairs(dev(k.view(np.int32)))
+    assert ov is None
+    assert np.array_equal(u32(ok, n), np.sort(k))
+    assert np.array_equal(u32(ok, n), u32(lk, n))
+
+
+def test_msb_sort_repeated_calls_share_scratch():
+    """Two sorts through one scratch buffer, the second smaller (the work
+    lists and counters of the first must not leak into the second)."""
+    announce("msb sort scratch reuse")
+    lib = cx.load()
+    n1, n2 = 1_500_001, 40_961
+    scratch = torch.empty(lib.crystal_sort_pairs_msb_scratch_bytes(n1, 1), dtype=torch.uint8, device="cuda")
+    for n in (n1, n2):
+        k, v = pairs(n, 1500 + n)
+        ok, ov = cx.sort_pairs(dev(k.view(np.int32)), dev(v.view(np.int32)), scratch=scratch, msb=True)
+        wk, wv = oracle.sort_pairs(k, v)
+        assert np.array_equal(u32(ok, n), wk) and np.array_equal(u32(ov, n), wv)
+
+
+def test_msb_sort_scratch_too_small():
+    lib = cx.load()
+    k = torch.zeros(100_000, dtype=torch.int32, device="cuda")
+    out = torch.empty_like(k)
+    small = torch.empty(1 << 16, dtype=torch.uint8, device="cuda")
+    rc = lib.crystal_sort_pairs_msb(cx._ptr(k), None, k.numel(), cx._ptr(out), None, cx._ptr(small),
+                                    small.numel(), cx._stream())
+    assert rc == cx.ESCRATCH
+
+
 # --------------------------------------------------------- unstable shuffle --
 def check_unstable(k, v, shift, bits):
     """The unstable pass orders equal digits arbitrarily: partition bounds are
