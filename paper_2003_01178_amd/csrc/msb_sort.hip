@@ -37,7 +37,9 @@ constexpr uint32_t kLocalMax = 8192;  // pairs one local-sort workgroup holds (5
 constexpr uint32_t kSmallSeg = 1024;  // sub-segments shorter than this are grouped into one task
 constexpr uint32_t kChunk = 65536;    // pairs per partition chunk (4 tiles)
 constexpr int kPartBlock = 1024, kPartIpt = 16;
-constexpr int kLocBlock = 512, kLocIpt = 16;
+constexpr int kLocBlock = 512, kLocIpt = 16;  // tasks up to kLocalMax pairs
+constexpr int kSmlBlock = 256, kSmlIpt = 17;  // tasks up to kSmallMax pairs, four workgroups per CU
+constexpr uint32_t kSmallMax = kSmlBlock * kSmlIpt;
 constexpr int kAuxBlock = 256;
 
 struct Seg {
@@ -51,11 +53,14 @@ struct ChunkD {
 struct Task {
     uint32_t start, len, bits, src;
 };
+// two task lists: 0 for tasks of at most kSmallMax pairs, 1 for the others
 struct Ctl {
     uint32_t n_big[2];
     uint32_t n_chunks;
-    uint32_t n_tasks;
+    uint32_t n_tasks[2];
 };
+
+__device__ __forceinline__ int task_list(uint32_t len, uint32_t bits) { return bits && len <= kSmallMax ? 0 : 1; }
 
 // Exclusive prefix over the block's threads in thread order; tmp: one word
 // per wave.  Ends with a barrier, after which tmp may be reused.
@@ -108,19 +113,15 @@ __device__ __forceinline__ uint32_t stable_rank(uint32_t d, bool valid, uint32_t
 }
 
 // ------------------------------------------------------------ work lists --
-__global__ void msb_init_kernel(Ctl *ctl, Seg *big0, Task *tasks, uint32_t n) {
+// An input of at most kLocalMax pairs: one task, the whole input, all 32 bits.
+__global__ void msb_init_kernel(Ctl *ctl, Task *tasks, uint32_t list_stride, uint32_t n) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    ctl->n_big[1] = 0;
+    ctl->n_big[0] = ctl->n_big[1] = 0;
     ctl->n_chunks = 0;
-    if (n > kLocalMax) {
-        ctl->n_big[0] = 1;
-        big0[0] = Seg{0u, n, 0u, 0u};
-        ctl->n_tasks = 0;
-    } else {
-        ctl->n_big[0] = 0;
-        tasks[0] = Task{0u, n, 32u, 0u};
-        ctl->n_tasks = 1;
-    }
+    const int l = task_list(n, 32u);
+    ctl->n_tasks[0] = ctl->n_tasks[1] = 0;
+    ctl->n_tasks[l] = 1;
+    tasks[(int64_t)l * list_stride] = Task{0u, n, 32u, 0u};
 }
 
 // One workgroup: chunk counts of the level's big segments, their exclusive
@@ -214,12 +215,13 @@ __global__ __launch_bounds__(kAuxBlock) void msb_hist_kernel(const Ctl *ctl, con
 // is the scratch copy.  Two walks: count and reserve, then write.
 __device__ void plan_subsegments(Ctl *ctl, int cur, const uint32_t *st, const uint32_t *tot, uint32_t seg_start,
                                  uint32_t seg_len, int shift, uint32_t dst, Seg *next, Task *tasks,
-                                 uint32_t &base_big, uint32_t &base_task) {
+                                 uint32_t list_stride, uint32_t &base_big, uint32_t *base_task) {
     for (int write = 0; write < 2; ++write) {
-        uint32_t nbig = 0, ntask = 0;
+        uint32_t nbig = 0, ntask[2] = {0u, 0u};
         auto emit_task = [&](uint32_t a, uint32_t len, uint32_t bits) {
-            if (write) tasks[base_task + ntask] = Task{a, len, bits, dst};
-            ++ntask;
+            const int l = task_list(len, bits);
+            if (write) tasks[(int64_t)l * list_stride + base_task[l] + ntask[l]] = Task{a, len, bits, dst};
+            ++ntask[l];
         };
         if (shift == 0) {
             if (dst != 1u) emit_task(seg_start, seg_len, 0u);
@@ -251,7 +253,7 @@ __device__ void plan_subsegments(Ctl *ctl, int cur, const uint32_t *st, const ui
         }
         if (!write) {
             base_big = nbig ? atomicAdd(&ctl->n_big[cur ^ 1], nbig) : 0u;
-            base_task = ntask ? atomicAdd(&ctl->n_tasks, ntask) : 0u;
+            for (int l = 0; l < 2; ++l) base_task[l] = ntask[l] ? atomicAdd(&ctl->n_tasks[l], ntask[l]) : 0u;
         }
     }
 }
@@ -260,9 +262,9 @@ __device__ void plan_subsegments(Ctl *ctl, int cur, const uint32_t *st, const ui
 // its partition offsets (part[d], part[256] = n) become the first level's
 // sub-segments.  One workgroup of 256 threads; also resets the counters.
 __global__ __launch_bounds__(kAuxBlock) void msb_level0_kernel(Ctl *ctl, const uint32_t *part, uint32_t n,
-                                                               Seg *next, Task *tasks) {
+                                                               Seg *next, Task *tasks, uint32_t list_stride) {
     __shared__ uint32_t st[kBinsM], tot[kBinsM];
-    __shared__ uint32_t base_big, base_task;
+    __shared__ uint32_t base_big, base_task[2];
     const int d = threadIdx.x;
     st[d] = part[d];
     tot[d] = part[d + 1] - part[d];
@@ -270,11 +272,11 @@ __global__ __launch_bounds__(kAuxBlock) void msb_level0_kernel(Ctl *ctl, const u
         ctl->n_big[0] = 0;
         ctl->n_big[1] = 0;
         ctl->n_chunks = 0;
-        ctl->n_tasks = 0;
+        ctl->n_tasks[0] = ctl->n_tasks[1] = 0;
     }
     __syncthreads();
     // big sub-segments go to list 1, which level 1 reads
-    if (d == 0) plan_subsegments(ctl, 0, st, tot, 0u, n, 24, 1u, next, tasks, base_big, base_task);
+    if (d == 0) plan_subsegments(ctl, 0, st, tot, 0u, n, 24, 1u, next, tasks, list_stride, base_big, base_task);
 }
 
 // One workgroup per big segment (thread d = digit d): the chunks' counts
@@ -283,10 +285,10 @@ __global__ __launch_bounds__(kAuxBlock) void msb_level0_kernel(Ctl *ctl, const u
 // output, 2 the scratch copy).
 __global__ __launch_bounds__(kAuxBlock) void msb_scan_kernel(Ctl *ctl, const Seg *big, int cur,
                                                              uint32_t *__restrict__ hist, Seg *next, Task *tasks,
-                                                             int shift, uint32_t dst) {
+                                                             uint32_t list_stride, int shift, uint32_t dst) {
     __shared__ uint32_t tmp[kAuxBlock / kWave];
     __shared__ uint32_t st[kBinsM], tot[kBinsM];
-    __shared__ uint32_t base_big, base_task;
+    __shared__ uint32_t base_big, base_task[2];
     const int d = threadIdx.x;
     const uint32_t nb = ctl->n_big[cur];
     for (uint32_t i = blockIdx.x; i < nb; i += gridDim.x) {
@@ -305,7 +307,9 @@ __global__ __launch_bounds__(kAuxBlock) void msb_scan_kernel(Ctl *ctl, const Seg
         st[d] = at;
         tot[d] = run;
         __syncthreads();
-        if (d == 0) plan_subsegments(ctl, cur, st, tot, s.start, s.len, shift, dst, next, tasks, base_big, base_task);
+        if (d == 0)
+            plan_subsegments(ctl, cur, st, tot, s.start, s.len, shift, dst, next, tasks, list_stride, base_big,
+                             base_task);
         __syncthreads();
     }
 }
@@ -436,18 +440,18 @@ __global__ __launch_bounds__(kPartBlock) void msb_shuffle_kernel(const Ctl *ctl,
 
 // ------------------------------------------------------------ local sort --
 // One task at a time per workgroup: its pairs in registers (the tile layout
-// above), sorted by `bits` low key bits with stable 8-bit passes in LDS, then
-// written to the output.
-template <bool VALS>
-__global__ __launch_bounds__(kLocBlock, 4) void msb_local_kernel(const Ctl *ctl, const Task *tasks,
-                                                              const uint32_t *__restrict__ in_k,
-                                                              const uint32_t *__restrict__ in_v,
-                                                              uint32_t *__restrict__ out_k, uint32_t *__restrict__ out_v,
-                                                              const uint32_t *__restrict__ tmp_k,
-                                                              const uint32_t *__restrict__ tmp_v) {
-    constexpr int W = kLocBlock / kWave;
-    constexpr int ITEMS = kLocBlock * kLocIpt;
-    static_assert(ITEMS == (int)kLocalMax, "a task fits one workgroup");
+// above), sorted by `bits` low key bits with stable 8-bit passes in LDS,
+// then written out from LDS.  Two shapes: BLOCK x IPT holds the task list's
+// largest task; the small shape fits four workgroups per CU.
+template <bool VALS, int BLOCK, int IPT>
+__global__ __launch_bounds__(BLOCK, 4) void msb_local_kernel(const Ctl *ctl, int list, const Task *tasks,
+                                                          const uint32_t *__restrict__ in_k,
+                                                          const uint32_t *__restrict__ in_v,
+                                                          uint32_t *__restrict__ out_k, uint32_t *__restrict__ out_v,
+                                                          const uint32_t *__restrict__ tmp_k,
+                                                          const uint32_t *__restrict__ tmp_v) {
+    constexpr int W = BLOCK / kWave;
+    constexpr int ITEMS = BLOCK * IPT;
     extern __shared__ uint32_t lds[];
     uint32_t *s_keys = lds;
     uint32_t *s_vals = lds + ITEMS;
@@ -456,96 +460,102 @@ __global__ __launch_bounds__(kLocBlock, 4) void msb_local_kernel(const Ctl *ctl,
     const int tid = threadIdx.x;
     const int w = tid / kWave;
     uint32_t *my_wc = s_wc + w * kBinsM;
-    const int off0 = w * (kWave * kLocIpt) + (int)lane_id();
-    const uint32_t nt = ctl->n_tasks;
+    const int wave0 = w * (kWave * IPT);
+    const int off0 = wave0 + (int)lane_id();
+    const uint32_t nt = ctl->n_tasks[list];
+    auto src_k = [&](const Task &t) { return t.src == 0 ? in_k : t.src == 1 ? (const uint32_t *)out_k : tmp_k; };
+    auto src_v = [&](const Task &t) { return t.src == 0 ? in_v : t.src == 1 ? (const uint32_t *)out_v : tmp_v; };
+    uint32_t key[IPT], val[IPT];
+    auto load = [&](const Task &t) {
+        typedef const __attribute__((address_space(1))) uint32_t *gptr;
+        gptr kb = (gptr)(src_k(t) + t.start);
+        gptr vb = VALS ? (gptr)(src_v(t) + t.start) : nullptr;
+        const int len = (int)t.len;
+#pragma unroll
+        for (int k = 0; k < IPT; ++k) {
+            const int i = off0 + k * kWave;
+            key[k] = i < len ? kb[i] : 0u;
+            if (VALS) val[k] = i < len ? vb[i] : 0u;
+        }
+    };
 
     for (uint32_t t = blockIdx.x; t < nt; t += gridDim.x) {
         const Task task = tasks[t];
-        const uint32_t *sk = task.src == 0 ? in_k : task.src == 1 ? out_k : tmp_k;
-        const uint32_t *sv = task.src == 0 ? in_v : task.src == 1 ? out_v : tmp_v;
+        const int len = (int)task.len;
+        if (task.bits) load(task);
         if (task.bits == 0) {
             // already in order: copy unless it is in the output already
-            if (task.src != 1)
-                for (uint32_t i = tid; i < task.len; i += kLocBlock) {
+            if (task.src != 1) {
+                const uint32_t *sk = src_k(task), *sv = src_v(task);
+                for (uint32_t i = tid; i < task.len; i += BLOCK) {
                     out_k[task.start + i] = sk[task.start + i];
                     if (VALS) out_v[task.start + i] = sv[task.start + i];
                 }
-            continue;
-        }
-        const int len = (int)task.len;
-        uint32_t key[kLocIpt], val[kLocIpt];
-        {
-            typedef const __attribute__((address_space(1))) uint32_t *gptr;
-            gptr kb = (gptr)(sk + task.start);
-            gptr vb = VALS ? (gptr)(sv + task.start) : nullptr;
-#pragma unroll
-            for (int k = 0; k < kLocIpt; ++k) {
-                const int i = off0 + k * kWave;
-                key[k] = i < len ? kb[i] : 0u;
-                if (VALS) val[k] = i < len ? vb[i] : 0u;
             }
-        }
-        for (uint32_t sh = 0; sh < task.bits; sh += 8) {
-            const uint32_t left = task.bits - sh;
-            const uint32_t mask = left >= 8 ? 0xFFu : (1u << left) - 1u;
-            if (tid < kBinsM) {
+        } else {
+            for (uint32_t sh = 0; sh < task.bits; sh += 8) {
+                const uint32_t left = task.bits - sh;
+                const uint32_t mask = left >= 8 ? 0xFFu : (1u << left) - 1u;
+                if (tid < kBinsM) {
 #pragma unroll
-                for (int i = 0; i < W; ++i) s_wc[i * kBinsM + tid] = 0u;
-            }
-            __syncthreads();
-            uint32_t rank[kLocIpt];
-            // slots whose 64 pairs all lie past the task's end are skipped
-            // (the test is uniform across the wave)
-            const int wave0 = w * (kWave * kLocIpt);
+                    for (int i = 0; i < W; ++i) s_wc[i * kBinsM + tid] = 0u;
+                }
+                __syncthreads();
+                uint32_t rank[IPT];
+                // slots whose 64 pairs all lie past the task's end are skipped
+                // (the test is uniform across the wave)
 #pragma unroll
-            for (int k = 0; k < kLocIpt; ++k) {
-                rank[k] = 0;
-                if (wave0 + k * kWave < len) rank[k] = stable_rank((key[k] >> sh) & mask, off0 + k * kWave < len, my_wc);
-                __builtin_amdgcn_sched_barrier(0);
-            }
-            __syncthreads();
-            uint32_t cnt = 0;
-            if (tid < kBinsM) {
+                for (int k = 0; k < IPT; ++k) {
+                    rank[k] = 0;
+                    if (wave0 + k * kWave < len)
+                        rank[k] = stable_rank((key[k] >> sh) & mask, off0 + k * kWave < len, my_wc);
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+                __syncthreads();
+                uint32_t cnt = 0;
+                if (tid < kBinsM) {
 #pragma unroll
-                for (int i = 0; i < W; ++i) {
-                    const uint32_t v = s_wc[i * kBinsM + tid];
-                    s_wc[i * kBinsM + tid] = cnt;
-                    cnt += v;
+                    for (int i = 0; i < W; ++i) {
+                        const uint32_t v = s_wc[i * kBinsM + tid];
+                        s_wc[i * kBinsM + tid] = cnt;
+                        cnt += v;
+                    }
+                }
+                uint32_t unused;
+                const uint32_t dstart = block_scan_excl<BLOCK>(cnt, s_tmp, unused);
+                if (tid < kBinsM) {
+#pragma unroll
+                    for (int i = 0; i < W; ++i) s_wc[i * kBinsM + tid] += dstart;
+                }
+                __syncthreads();
+#pragma unroll
+                for (int k = 0; k < IPT; ++k) {
+                    if (off0 + k * kWave < len) {
+                        const uint32_t p = my_wc[(key[k] >> sh) & mask] + rank[k];
+                        s_keys[p] = key[k];
+                        if (VALS) s_vals[p] = val[k];
+                    }
+                }
+                __syncthreads();
+                if (sh + 8 < task.bits) {
+#pragma unroll
+                    for (int k = 0; k < IPT; ++k) {
+                        const int i = off0 + k * kWave;
+                        if (i < len) {
+                            key[k] = s_keys[i];
+                            if (VALS) val[k] = s_vals[i];
+                        }
+                    }
+                    __syncthreads();
                 }
             }
-            uint32_t unused;
-            const uint32_t dstart = block_scan_excl<kLocBlock>(cnt, s_tmp, unused);
-            if (tid < kBinsM) {
-#pragma unroll
-                for (int i = 0; i < W; ++i) s_wc[i * kBinsM + tid] += dstart;
-            }
-            __syncthreads();
-#pragma unroll
-            for (int k = 0; k < kLocIpt; ++k) {
-                if (off0 + k * kWave < len) {
-                    const uint32_t p = my_wc[(key[k] >> sh) & mask] + rank[k];
-                    s_keys[p] = key[k];
-                    if (VALS) s_vals[p] = val[k];
-                }
-            }
-            __syncthreads();
-#pragma unroll
-            for (int k = 0; k < kLocIpt; ++k) {
-                const int i = off0 + k * kWave;
-                if (i < len) {
-                    key[k] = s_keys[i];
-                    if (VALS) val[k] = s_vals[i];
-                }
-            }
-            __syncthreads();
         }
-#pragma unroll
-        for (int k = 0; k < kLocIpt; ++k) {
-            const int i = off0 + k * kWave;
-            if (i < len) {
-                out_k[task.start + i] = key[k];
-                if (VALS) out_v[task.start + i] = val[k];
+        if (task.bits) {
+            for (int i = tid; i < len; i += BLOCK) {
+                out_k[task.start + i] = s_keys[i];
+                if (VALS) out_v[task.start + i] = s_vals[i];
             }
+            __syncthreads();  // the LDS is the next task's
         }
     }
 }
@@ -554,8 +564,8 @@ constexpr size_t shuffle_lds(bool vals) {
     return ((size_t)(vals ? 2 : 1) * kPartBlock * kPartIpt + (kPartBlock / kWave) * kBinsM + 2 * kBinsM +
             kPartBlock / kWave) * 4;
 }
-constexpr size_t local_lds(bool vals) {
-    return ((size_t)(vals ? 2 : 1) * kLocBlock * kLocIpt + (kLocBlock / kWave) * kBinsM + kLocBlock / kWave) * 4;
+constexpr size_t local_lds(bool vals, int block, int ipt) {
+    return ((size_t)(vals ? 2 : 1) * block * ipt + (block / kWave) * kBinsM + block / kWave) * 4;
 }
 
 int64_t r256(int64_t b) { return (b + 255) / 256 * 256; }
@@ -590,8 +600,8 @@ MsbLayout msb_layout(int64_t n, bool vals) {
     at += r256(L.max_chunks * (int64_t)sizeof(ChunkD));
     L.hist = at;
     at += r256(L.max_chunks * kBinsM * 4);
-    L.tasks = at;
-    at += r256(L.max_tasks * (int64_t)sizeof(Task));
+    L.tasks = at;  // two lists of max_tasks entries
+    at += r256(2 * L.max_tasks * (int64_t)sizeof(Task));
     L.ctl = at;
     at += 256;
     L.part = at;
@@ -615,34 +625,43 @@ hipError_t msb_run(const uint32_t *keys, const uint32_t *vals, int64_t n, uint32
     Task *tasks = (Task *)(base + L.tasks);
     Ctl *ctl = (Ctl *)(base + L.ctl);
 
+    const uint32_t stride = (uint32_t)L.max_tasks;
+    auto large = msb_local_kernel<VALS, kLocBlock, kLocIpt>;
+    auto small = msb_local_kernel<VALS, kSmlBlock, kSmlIpt>;
+    const size_t large_lds = local_lds(VALS, kLocBlock, kLocIpt), small_lds = local_lds(VALS, kSmlBlock, kSmlIpt);
     static bool attrs = false;
     if (!attrs) {
         hipError_t e = hipFuncSetAttribute((const void *)msb_shuffle_kernel<VALS>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)shuffle_lds(VALS));
         if (e == hipSuccess)
-            e = hipFuncSetAttribute((const void *)msb_local_kernel<VALS>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)local_lds(VALS));
+            e = hipFuncSetAttribute((const void *)large, hipFuncAttributeMaxDynamicSharedMemorySize, (int)large_lds);
         if (e != hipSuccess) return e;
         attrs = true;
     }
     const int64_t cus = device_cu_count();
-    int64_t part_per_cu = 0, loc_per_cu = 0;
+    int64_t part_per_cu = 0, large_per_cu = 0, small_per_cu = 0;
     hipError_t e = resident_per_cu((const void *)msb_shuffle_kernel<VALS>, kPartBlock, (int64_t)shuffle_lds(VALS),
                                    part_per_cu);
-    if (e != hipSuccess) return e;
-    e = resident_per_cu((const void *)msb_local_kernel<VALS>, kLocBlock, (int64_t)local_lds(VALS), loc_per_cu);
+    if (e == hipSuccess) e = resident_per_cu((const void *)large, kLocBlock, (int64_t)large_lds, large_per_cu);
+    if (e == hipSuccess) e = resident_per_cu((const void *)small, kSmlBlock, (int64_t)small_lds, small_per_cu);
     if (e != hipSuccess) return e;
     if (part_per_cu < 1) part_per_cu = 1;
-    if (loc_per_cu < 1) loc_per_cu = 1;
+    if (large_per_cu < 1) large_per_cu = 1;
+    if (small_per_cu < 1) small_per_cu = 1;
     const dim3 aux_grid((unsigned)(cus * 8)), aux(kAuxBlock);
+    auto local_sorts = [&](int64_t large_grid, int64_t small_grid) {
+        hipLaunchKernelGGL(small, dim3((unsigned)small_grid), dim3(kSmlBlock), small_lds, s, ctl, 0, tasks, keys,
+                           vals, ok, ov, tk, tv);
+        hipLaunchKernelGGL(large, dim3((unsigned)large_grid), dim3(kLocBlock), large_lds, s, ctl, 1,
+                           tasks + stride, keys, vals, ok, ov, tk, tv);
+        return hipGetLastError();
+    };
 
     if (n <= (int64_t)kLocalMax) {
         // one task: the whole input, sorted in LDS
-        hipLaunchKernelGGL(msb_init_kernel, dim3(1), dim3(64), 0, s, ctl, big[0], tasks, (uint32_t)n);
+        hipLaunchKernelGGL(msb_init_kernel, dim3(1), dim3(64), 0, s, ctl, tasks, stride, (uint32_t)n);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        hipLaunchKernelGGL(msb_local_kernel<VALS>, dim3(1), dim3(kLocBlock), local_lds(VALS), s, ctl, tasks, keys,
-                           vals, ok, ov, tk, tv);
-        return hipGetLastError();
+        return local_sorts(1, 1);
     }
     // level 0: the whole input is one segment, so the plain stable partition
     // pass on the top byte does it (input -> output), and its partition
@@ -652,7 +671,7 @@ hipError_t msb_run(const uint32_t *keys, const uint32_t *vals, int64_t n, uint32
                                s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(msb_level0_kernel, dim3(1), dim3(kAuxBlock), 0, s, ctl, (const uint32_t *)(base + L.part),
-                       (uint32_t)n, big[1], tasks);
+                       (uint32_t)n, big[1], tasks, stride);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     for (int level = 1; level < 4; ++level) {
         const int shift = 24 - 8 * level, cur = level & 1;
@@ -665,14 +684,12 @@ hipError_t msb_run(const uint32_t *keys, const uint32_t *vals, int64_t n, uint32
         hipLaunchKernelGGL(msb_chunk_fill_kernel, aux_grid, aux, 0, s, ctl, big[cur], cur, chunks);
         hipLaunchKernelGGL(msb_hist_kernel, aux_grid, aux, 0, s, ctl, chunks, sk, shift, hist);
         hipLaunchKernelGGL(msb_scan_kernel, aux_grid, aux, 0, s, ctl, big[cur], cur, hist, big[cur ^ 1], tasks,
-                           shift, dst);
+                           stride, shift, dst);
         hipLaunchKernelGGL(msb_shuffle_kernel<VALS>, dim3((unsigned)(cus * part_per_cu)), dim3(kPartBlock),
                            shuffle_lds(VALS), s, ctl, chunks, hist, sk, sv, dk, dv, shift);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(msb_local_kernel<VALS>, dim3((unsigned)(cus * loc_per_cu)), dim3(kLocBlock), local_lds(VALS),
-                       s, ctl, tasks, keys, vals, ok, ov, tk, tv);
-    return hipGetLastError();
+    return local_sorts(cus * large_per_cu, cus * small_per_cu);
 }
 
 }  // namespace
