@@ -15,10 +15,12 @@
 //   shuffle   one workgroup per chunk writes its pairs to their offsets, a
 //             tile at a time, ranking equal digits stably with ballots (the
 //             tile is sorted by digit in LDS, then written in that order).
-// A final launch sorts every task in LDS by its remaining low bits (stable
-// 8-bit passes from the low digit up) and writes it to the output.  Levels
-// alternate between the output and a scratch copy; a task reads whichever
-// holds its segment.  Uniform keys need two partition levels (256, then
+// Two final launches sort every task in LDS by its remaining low bits
+// (stable 8-bit passes from the low digit up), one workgroup per task, and
+// write it to the output: tasks of at most kSmallMax pairs in a small shape
+// (four workgroups per CU), the others in a large one.  Levels alternate
+// between the output and a scratch copy; a task reads whichever holds its
+// segment.  Uniform keys need two partition levels (256, then
 // 65,536 segments of about 4,096 pairs) and the local pass; skewed keys
 // simply keep more segments big for more levels.
 //
@@ -40,6 +42,7 @@ constexpr int kPartBlock = 1024, kPartIpt = 16;
 constexpr int kLocBlock = 512, kLocIpt = 16;  // tasks up to kLocalMax pairs
 constexpr int kSmlBlock = 256, kSmlIpt = 17;  // tasks up to kSmallMax pairs, four workgroups per CU
 constexpr uint32_t kSmallMax = kSmlBlock * kSmlIpt;
+static_assert(kLocBlock * kLocIpt >= (int)kLocalMax, "the large shape holds every sorted task");
 constexpr int kAuxBlock = 256;
 
 struct Seg {
@@ -211,8 +214,8 @@ __global__ __launch_bounds__(kAuxBlock) void msb_hist_kernel(const Ctl *ctl, con
 // more are tasks of their own, sorted by the `shift` bits below their digit;
 // shorter neighbours are grouped into tasks of at most kLocalMax pairs,
 // sorted by their digit too.  At the last digit every sub-segment is final
-// where the level wrote it: one copy task for the whole segment when that
-// is the scratch copy.  Two walks: count and reserve, then write.
+// where the level wrote it: copy tasks of at most kChunk pairs when that is
+// the scratch copy.  Two walks: count and reserve, then write.
 __device__ void plan_subsegments(Ctl *ctl, int cur, const uint32_t *st, const uint32_t *tot, uint32_t seg_start,
                                  uint32_t seg_len, int shift, uint32_t dst, Seg *next, Task *tasks,
                                  uint32_t list_stride, uint32_t &base_big, uint32_t *base_task) {
@@ -224,7 +227,11 @@ __device__ void plan_subsegments(Ctl *ctl, int cur, const uint32_t *st, const ui
             ++ntask[l];
         };
         if (shift == 0) {
-            if (dst != 1u) emit_task(seg_start, seg_len, 0u);
+            // copies in pieces of kChunk pairs, so that a long run of one key
+            // is copied by many workgroups
+            if (dst != 1u)
+                for (uint64_t a = 0; a < seg_len; a += kChunk)
+                    emit_task(seg_start + (uint32_t)a, seg_len - a < kChunk ? (uint32_t)(seg_len - a) : kChunk, 0u);
         } else {
             uint32_t g_start = 0, g_len = 0, g_digits = 0;
             auto flush = [&]() {
@@ -584,9 +591,11 @@ MsbLayout msb_layout(int64_t n, bool vals) {
     // ones; a group closes above kLocalMax - kSmallSeg pairs, before a longer
     // or a big sub-segment, or at its parent's end, so there are at most
     // n / (kLocalMax - kSmallSeg) + n / kSmallSeg + (big segments of this and
-    // the next level) of them.  Then the last level's copies (one per big
-    // segment) and the single task of a short input.
-    L.max_tasks = 3 * (2 * (n / kSmallSeg) + n / (kLocalMax - kSmallSeg) + 2 * L.max_big + 2) + L.max_big + 8;
+    // the next level) of them.  Then the last level's copies (pieces of at
+    // most kChunk pairs of the big segments) and the single task of a short
+    // input.
+    L.max_tasks = 3 * (2 * (n / kSmallSeg) + n / (kLocalMax - kSmallSeg) + 2 * L.max_big + 2) + n / kChunk +
+                  L.max_big + 8;
     int64_t at = 0;
     L.tmp_k = at;
     at += r256(n * 4);

@@ -218,6 +218,21 @@ def test_msb_sort_degenerate_inputs(case):
     assert np.array_equal(u32(ov, n), wv)
 
 
+def test_msb_sort_long_equal_runs_are_copied_in_pieces():
+    """Three million pairs of two keys: both runs stay one segment down to the
+    last digit and are then copied to the output in pieces, by many
+    workgroups."""
+    announce("msb sort equal runs")
+    n = 3_000_017
+    rng = np.random.default_rng(41)
+    k = np.where(rng.random(n) < 0.3, 0x0A0B0C0D, 0xF0F0F0F0).astype(np.uint32)
+    v = np.arange(n, dtype=np.uint32)
+    ok, ov = cx.sort_pairs(dev(k.view(np.int32)), dev(v.view(np.int32)), msb=True)
+    wk, wv = oracle.sort_pairs(k, v)
+    assert np.array_equal(u32(ok, n), wk)
+    assert np.array_equal(u32(ov, n), wv)
+
+
 def test_msb_sort_keys_only_equals_lsb_sort():
     announce("msb sort keys only")
     n = 2_000_003
