@@ -1,5 +1,6 @@
-"""Narrow (frame-of-reference uint8 / uint16) fact columns in the fused star
-kernel, against the oracle on the same values as int32."""
+"""Compressed fact columns in the fused star kernel: narrow (frame-of-reference
+uint8 / uint16) and bit-packed (1-16 bits per value, frame of reference)
+columns, against the oracle on the same values as int32."""
 import numpy as np
 import pytest
 import torch

@@ -1,6 +1,8 @@
-"""GPU parity of radix histogram, radix partition and the radix sort
-(section 4.4) against the CPU oracle, through the C ABI.  The partition is
-stable, so its output is unique and compared element by element."""
+"""GPU parity of radix histogram, radix partition and the radix sorts (least
+and most significant digit first; section 4.4) against the CPU oracle,
+through the C ABI.  The stable partition and both sorts have a unique
+output, compared element by element; the unstable partition is compared
+per partition as a multiset."""
 import numpy as np
 import pytest
 import torch
