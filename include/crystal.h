@@ -201,9 +201,11 @@ crystal_status crystal_ht_build_batch(const crystal_ht_build_item *items, int32_
  * To start, clear both sets with a call that has no items.
  * Errors (CRYSTAL_EINVAL, nothing launched): n_items or n_clear outside
  * 0..CRYSTAL_MAX_BUILD_BATCH, an invalid descriptor, zero_n < 0, zero NULL
- * or not 8-byte aligned with zero_n > 0, or any two of the items' tables, the cleared tables and
- * the zeroed range sharing memory.  `clear` and the descriptors are host
- * memory; table memory, columns, `zero` and `status` are device memory. */
+ * or not 8-byte aligned with zero_n > 0, or any two of the items' tables,
+ * the cleared tables and the zeroed range sharing memory.  `clear` and the
+ * descriptors are host memory; table memory, columns, `zero` and `status`
+ * are device memory; device errors of the builds go to *status as in
+ * crystal_ht_build. */
 crystal_status crystal_ht_build_batch_fused(const crystal_ht_build_item *items, int32_t n_items,
                                             const crystal_ht *const *clear, int32_t n_clear, int64_t *zero,
                                             int64_t zero_n, int32_t *status, void *stream);
