@@ -437,7 +437,8 @@ def serve(args, torch, cx, datagen, queries):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1 (the path would shard "
+                                   "by fact row ranges, one share per GPU)",
                           "requested_gpus": args.gpus}))
         sys.exit(2)
     import torch
