@@ -68,6 +68,8 @@ def parse():
     p.add_argument("--serve-rows", type=int, default=0, help="serve: fact rows (default 600M)")
     p.add_argument("--serve-pass-reps", type=int, default=20, help="serve: timed shared-scan passes per template")
     p.add_argument("--no-serve", action="store_true", help="star: skip the served-mix measurement")
+    p.add_argument("--settle", type=float, default=0.25,
+                   help="star, q11: seconds of untimed steps before the warmup steps (0: none)")
     return p.parse_args()
 
 
@@ -143,6 +145,26 @@ def measured_traffic(order, n, packed=False):
     if rec.get("fact_rows", n) != n or rec.get("join_order", list(order)) != list(order):
         return None
     return rec.get("traffic_bytes")
+
+
+def settle(fn, torch, seconds, chunk=50):
+    """Call ``fn`` untimed, ``chunk`` calls between synchronizations, until ``seconds`` have passed.
+
+    After idle the GPU's clocks take tens of milliseconds of work to reach their steady state, so a
+    timed region of a few milliseconds right after start-up would measure that ramp and not the
+    kernels.  Returns the number of calls made (0 when ``seconds`` is 0)."""
+    n, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        for _ in range(chunk):
+            fn()
+        torch.cuda.synchronize()
+        n += chunk
+    return n
+
+
+def settle_record(n, seconds):
+    return {"steps": n, "seconds": seconds,
+            "note": "untimed steps before the warmup steps, so that the timed ones run at steady GPU clocks"}
 
 
 class Timer:
@@ -535,6 +557,7 @@ def main():
                 else:
                     run_step(p)
 
+            n_settle = settle(step, torch, args.settle)
             for _ in range(W):
                 step()
             torch.cuda.synchronize()
@@ -571,6 +594,7 @@ def main():
                               "launch": "one hip graph per step" if use_graph else "eager",
                               "columns": ("fk0 12-bit date codes, fk1 16-bit, bit-packed; others int32" if args.narrow
                                           else "int32")})
+        result["settle"] = settle_record(n_settle, args.settle)
         roof.update(kernel="crystal::star_kernel", achieved=alg_bytes / (kern_ms * 1e-3) / 1e9,
                     algorithmic_bytes=alg_bytes, bytes_per_row=alg_bytes / n, kernel_ms=kern_ms,
                     kernel_rows_per_s=n / (kern_ms * 1e-3), algorithmic_bytes_c64=alg_bytes_c64,
@@ -622,6 +646,7 @@ def main():
         plan = queries.Q11Plan(*cols)
         out = torch.empty(1, dtype=torch.int64, device="cuda")
         status = cx.new_status()
+        n_settle = settle(lambda: plan.run(out=out, status=status), torch, args.settle)
         for _ in range(W):
             plan.run(out=out, status=status)
         torch.cuda.synchronize()
@@ -643,6 +668,7 @@ def main():
                       unit="rows/s", ms_per_step=elapsed / K * 1e3, dtype="int32",
                       config={"workload": "Q1.1 shape: 6M rows, 3 range predicates, SUM(price*disc)",
                               "fact_rows": n})
+        result["settle"] = settle_record(n_settle, args.settle)
         roof.update(kernel="crystal::star_kernel", achieved=b / (kern_ms * 1e-3) / 1e9, algorithmic_bytes=b,
                     kernel_ms=kern_ms)
 
