@@ -69,7 +69,7 @@ def parse():
     p.add_argument("--serve-pass-reps", type=int, default=20, help="serve: timed shared-scan passes per template")
     p.add_argument("--no-serve", action="store_true", help="star: skip the served-mix measurement")
     p.add_argument("--settle", type=float, default=0.25,
-                   help="star, q11: seconds of untimed steps before the warmup steps (0: none)")
+                   help="star, q11, select: seconds of untimed steps before the warmup steps (0: none)")
     return p.parse_args()
 
 
@@ -679,6 +679,7 @@ def main():
         lo, hi = datagen.select_threshold_range(args.sigma)
         outb = torch.empty(n, dtype=torch.int32, device="cuda")
         cnt = torch.empty(1, dtype=torch.int64, device="cuda")
+        n_settle = settle(lambda: cx.select(x, lo, hi, out=outb, count=cnt), torch, args.settle)
         for _ in range(W):
             cx.select(x, lo, hi, out=outb, count=cnt)
         torch.cuda.synchronize()
@@ -711,6 +712,7 @@ def main():
                       ms_per_step=elapsed / K * 1e3, dtype="int32",
                       config={"workload": f"select y < v on 2^29 int32, sigma={args.sigma}", "rows": n,
                               "matches": c, "tile": list(cx.tune_get(cx.K_SELECT, n))})
+        result["settle"] = settle_record(n_settle, args.settle)
         if sweep:
             result["sigma_sweep"] = sweep
         roof.update(kernel="crystal::select_kernel", achieved=b / (kern_ms * 1e-3) / 1e9, algorithmic_bytes=b,
