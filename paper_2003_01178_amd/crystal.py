@@ -363,26 +363,46 @@ def build_tables(items, status=None, stream=None):
     return status
 
 
+class BuildBatch:
+    """The arguments of one fused build launch, marshalled once.
+
+    items: (HashTable, keys, payload or None, filter_col or None, (lo, hi))
+    per table to build, into tables that are already clear; clear: HashTables
+    to clear in the same launch; zero: an int64 tensor to zero (or None).
+    ``launch()`` repeats the call (crystal_ht_build_batch_fused) with these
+    arguments, so a loop that runs the same builds every step spends no host
+    time rebuilding them.  The tensors and tables are referenced, not copied."""
+
+    def __init__(self, items, clear=(), zero=None, status=None):
+        if len(clear) > MAX_BUILD_BATCH:
+            raise ValueError("at most 8 tables to clear")
+        if zero is not None and zero.dtype != torch.int64:
+            raise ValueError("zero must be an int64 tensor")
+        self.arr = _build_items(items)
+        self.n_items = len(items)
+        self.carr = (ctypes.POINTER(HT) * max(1, len(clear)))()
+        for i, ht in enumerate(clear):
+            self.carr[i] = ctypes.pointer(ht.desc)
+        self.n_clear = len(clear)
+        if status is None:
+            dev = items[0][1].device if items else (zero.device if zero is not None else clear[0].mem.device)
+            status = new_status(dev)
+        self.status = status
+        self.zero_ptr = _ptr(zero) if zero is not None else None
+        self.zero_n = zero.numel() if zero is not None else 0
+        self._keep = (list(items), list(clear), zero)
+
+    def launch(self, stream=None):
+        _check(load().crystal_ht_build_batch_fused(self.arr, self.n_items, self.carr, self.n_clear, self.zero_ptr,
+                                                   self.zero_n, _ptr(self.status), _stream(stream)),
+               "crystal_ht_build_batch_fused")
+        return self.status
+
+
 def build_tables_fused(items, clear=(), zero=None, status=None, stream=None):
     """One launch: build `items` into tables that are already clear, clear the
     HashTables in `clear`, and zero the int64 tensor `zero` (if given)."""
-    lib = load()
-    if len(clear) > MAX_BUILD_BATCH:
-        raise ValueError("at most 8 tables to clear")
-    arr = _build_items(items)
-    carr = (ctypes.POINTER(HT) * max(1, len(clear)))()
-    for i, ht in enumerate(clear):
-        carr[i] = ctypes.pointer(ht.desc)
-    if zero is not None and zero.dtype != torch.int64:
-        raise ValueError("zero must be an int64 tensor")
-    if status is None:
-        dev = items[0][1].device if items else (zero.device if zero is not None else clear[0].mem.device)
-        status = new_status(dev)
-    _check(lib.crystal_ht_build_batch_fused(arr, len(items), carr, len(clear),
-                                            _ptr(zero) if zero is not None else None,
-                                            zero.numel() if zero is not None else 0, _ptr(status),
-                                            _stream(stream)), "crystal_ht_build_batch_fused")
-    return status
+    return BuildBatch(items, clear=clear, zero=zero, status=status).launch(stream)
 
 
 def groupby_agg(group, value, n_groups, out=None, status=None, stream=None):

@@ -189,6 +189,43 @@ def test_star_fused_builds_graph_replays(star_small):
     cx.check_status(s.status)
 
 
+def test_star_prepared_build_batches(star_small):
+    """BuildBatch: each table set's fused build marshalled once and launched
+    every other step, eagerly on one stream without synchronising between
+    steps (the benchmark's loop): after an odd and an even number of steps
+    the group array holds the oracle's answer, and the set not in use is
+    clear."""
+    t, s = star_small
+    want, _ = star_oracle(t)
+    sets = [s.new_tables(), s.new_tables()]
+    plans = [s.plan(tables=tb) for tb in sets]
+    status = cx.new_status()
+    s.status.zero_()
+    out = torch.full((STAR_GROUPS,), 7, dtype=torch.int64, device="cuda")
+    for tb in sets:
+        for ht in tb:
+            ht.mem.fill_(0xA5)
+    builds = [cx.BuildBatch(s.build_items(tables=sets[p]), clear=sets[1 - p], zero=out, status=s.status)
+              for p in (0, 1)]
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        cx.build_tables_fused([], clear=sets[0] + sets[1], status=s.status, stream=stream)
+        k = 0
+        for steps in (5, 8):
+            announce("prepared builds, steps", steps)
+            for _ in range(steps):
+                builds[k % 2].launch(stream)
+                plans[k % 2].run(out=out, status=status, stream=stream, accumulate=True)
+                k += 1
+            stream.synchronize()
+            assert np.array_equal(out.cpu().numpy(), want), k
+            for ht in sets[k % 2]:
+                assert int(ht.mem[:_bitmap_bytes(ht)].count_nonzero()) == 0
+    cx.check_status(status)
+    cx.check_status(s.status)
+
+
 @pytest.mark.parametrize("block,ipt,gpc", [(64, 4, 0), (128, 16, 0), (256, 8, 3), (1024, 16, 1)])
 def test_star_tile_shapes(star_small, block, ipt, gpc):
     announce("star shape", block, ipt, gpc)
