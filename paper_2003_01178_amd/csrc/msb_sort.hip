@@ -362,6 +362,9 @@ __global__ __launch_bounds__(kPartBlock) void msb_shuffle_kernel(const Ctl *ctl,
             // is one scalar base plus one lane offset (global address space:
             // a generic pointer would give flat loads)
             typedef const __attribute__((address_space(1))) uint32_t *gptr;
+            // base is uniform; readfirstlane states it for the scalar constraint below
+            base = ((int64_t)__builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)base >> 32)) << 32) |
+                   (int64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)base);
             gptr kb = (gptr)(ik + base);
             gptr vb = VALS ? (gptr)(iv + base) : nullptr;
             asm volatile("" : "+s"(kb));
@@ -384,6 +387,11 @@ __global__ __launch_bounds__(kPartBlock) void msb_shuffle_kernel(const Ctl *ctl,
         load(ch.start);
         for (int64_t base = ch.start; base < (int64_t)ch.end; base += ITEMS) {
             const int rem = (int)((int64_t)ch.end - base < ITEMS ? (int64_t)ch.end - base : ITEMS);
+            // the wave clears its own counter row: the previous tile last read it
+            // in this wave and in the digit scan before its scatter barrier, so
+            // the write-out needs no barrier after it
+#pragma unroll
+            for (int q = 0; q < kBinsM / kWave; ++q) my_wc[q * kWave + (int)lane_id()] = 0u;
             uint32_t rank[kPartIpt];
 #pragma unroll
             for (int k = 0; k < kPartIpt; ++k) {
@@ -423,10 +431,6 @@ __global__ __launch_bounds__(kPartBlock) void msb_shuffle_kernel(const Ctl *ctl,
             __syncthreads();
             // the next tile's loads go out while this one is written
             if (base + ITEMS < (int64_t)ch.end) load(base + ITEMS);
-            if (tid < kBinsM) {
-#pragma unroll
-                for (int i = 0; i < W; ++i) s_wc[i * kBinsM + tid] = 0u;
-            }
             int tidv = tid;  // opaque: keeps the write-out's per-item offsets out of registers
             asm volatile("" : "+v"(tidv));
 #pragma unroll
@@ -440,7 +444,9 @@ __global__ __launch_bounds__(kPartBlock) void msb_shuffle_kernel(const Ctl *ctl,
                 }
                 if (j % 4 == 3) __builtin_amdgcn_sched_barrier(0);
             }
-            __syncthreads();
+            // no barrier: the next tile writes s_gbase, s_run, s_tmp and the LDS
+            // tile only after its ranking barrier, and the next chunk's set-up
+            // ends with one
         }
     }
 }

@@ -219,6 +219,10 @@ __device__ __forceinline__ void load_tile(const uint32_t *__restrict__ keys, con
                                           int64_t base, int rem, int off0, uint32_t (&key)[IPT],
                                           uint32_t (&val)[IPT]) {
     using RT = RadixTile<BLOCK, IPT>;
+    // base is uniform; readfirstlane states it, so that the scalar constraint
+    // below holds wherever the compiler places this call
+    base = ((int64_t)__builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)base >> 32)) << 32) |
+           (int64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)base);
     const uint32_t *kb = keys + base;
     const uint32_t *vb = VALS ? vals + base : nullptr;
     asm volatile("" : "+s"(kb));
@@ -274,8 +278,6 @@ __global__ __launch_bounds__(BLOCK) void radix_shuffle_kernel(
             s_run[tid] = dstart + counts[(int64_t)tid * cols + (int64_t)blockIdx.x * sub];
             if (blockIdx.x == 0 && part_offsets) part_offsets[tid] = dstart;
         }
-#pragma unroll
-        for (int i = 0; i < RT::W; ++i) s_wc[i * kBins + tid] = 0u;
     }
     if (blockIdx.x == 0 && part_offsets && tid == 0) part_offsets[mask + 1] = (uint32_t)n;
     __syncthreads();
@@ -295,7 +297,13 @@ __global__ __launch_bounds__(BLOCK) void radix_shuffle_kernel(
         const int rem = items_from(base);  // items in this tile
         int tidv = tid;                    // opaque: keeps per-item offsets out of registers
         asm volatile("" : "+v"(tidv));
-        // 1. rank every item among the wave's earlier items of its digit
+        // 1. rank every item among the wave's earlier items of its digit.  The
+        //    wave clears its own counter row first: the previous tile last read
+        //    it in this wave (step 3) and in the digit scan before that tile's
+        //    scatter barrier, so no barrier is needed after the write-out, and a
+        //    wave done writing ranks the next tile while others still write.
+#pragma unroll
+        for (int q = 0; q < kBins / kWave; ++q) my_wc[q * kWave + (int)lane_id()] = 0u;
         uint32_t rank[IPT];
         if constexpr (!STABLE) {
 #pragma unroll
@@ -364,10 +372,6 @@ __global__ __launch_bounds__(BLOCK) void radix_shuffle_kernel(
         // 4. next tile's loads go out while this one is written
         if (t + 1 < t1)
             load_tile<BLOCK, IPT, VALS>(keys, vals, base + RT::ITEMS, items_from(base + RT::ITEMS), off0, key, val);
-        if (tid < kBins) {
-#pragma unroll
-            for (int i = 0; i < RT::W; ++i) s_wc[i * kBins + tid] = 0u;
-        }
 #pragma unroll
         for (int j = 0; j < IPT; ++j) {
             const int p = j * BLOCK + tidv;
@@ -379,7 +383,9 @@ __global__ __launch_bounds__(BLOCK) void radix_shuffle_kernel(
             }
             if (j % 4 == 3) __builtin_amdgcn_sched_barrier(0);
         }
-        __syncthreads();
+        // no barrier: the next tile writes s_gbase, s_run, s_tmp and the LDS
+        // tile only after its ranking barrier, which every wave reaches after
+        // finishing this write-out
     }
 }
 
