@@ -70,7 +70,7 @@ def parse():
     p.add_argument("--serve-pass-reps", type=int, default=20, help="serve: timed shared-scan passes per template")
     p.add_argument("--no-serve", action="store_true", help="star: skip the served-mix measurement")
     p.add_argument("--settle", type=float, default=0.25,
-                   help="star, q11, select: seconds of untimed steps before the warmup steps (0: none)")
+                   help="seconds of untimed steps before the warmup steps (0: none)")
     return p.parse_args()
 
 
@@ -488,6 +488,7 @@ def main():
     roof = {"bound": "hbm", "peak": HBM_PEAK_GBS, "unit": "GB/s", "traffic": None,
             "fetch_bytes_model": FETCH_BYTES}
     cpu = None
+    n_settle = None
 
     if args.workload == "star":
         n = args.rows or 120_000_000
@@ -744,6 +745,7 @@ def main():
         x1h, x2h = datagen.project_columns(n)
         x1, x2 = queries.to_dev(x1h), queries.to_dev(x2h)
         outp = torch.empty(n, dtype=torch.float32, device="cuda")
+        n_settle = settle(lambda: cx.project(x1, x2, 2.0, 3.0, out=outp), torch, args.settle)
         for _ in range(W):
             cx.project(x1, x2, 2.0, 3.0, out=outp)
         torch.cuda.synchronize()
@@ -771,6 +773,7 @@ def main():
         keys, vals, fk = queries.to_dev(jt.dim_key), queries.to_dev(jt.dim_val), queries.to_dev(jt.fk)
         st = ht.build(keys, vals)
         res = torch.empty(2, dtype=torch.int64, device="cuda")
+        n_settle = settle(lambda: ht.probe(fk, out=res), torch, args.settle)
         for _ in range(W):
             ht.probe(fk, out=res)
         torch.cuda.synchronize()
@@ -854,6 +857,7 @@ def main():
         v = queries.to_dev(rng.integers(1, 1_000_001, size=n, dtype=np.int32))
         o = torch.empty(7000, dtype=torch.int64, device="cuda")
         st = cx.new_status()
+        n_settle = settle(lambda: cx.groupby_agg(g, v, 7000, out=o, status=st), torch, args.settle)
         for _ in range(W):
             cx.groupby_agg(g, v, 7000, out=o, status=st)
         torch.cuda.synchronize()
@@ -896,6 +900,7 @@ def main():
                                   device="cuda")
             call = lambda: cx.sort_pairs(keys, vals, out_keys=ok, out_vals=ov, scratch=scratch)
             passes = 4
+        n_settle = settle(call, torch, args.settle, chunk=2)
         for _ in range(W):
             call()
         torch.cuda.synchronize()
@@ -933,6 +938,8 @@ def main():
 
     roof["frac"] = roof["achieved"] / roof["peak"]
     result["roofline"] = roof
+    if n_settle is not None and "settle" not in result:
+        result["settle"] = settle_record(n_settle, args.settle)
     if cpu is not None:
         result["cpu_baseline"] = cpu
     order = ["metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better",
