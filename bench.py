@@ -672,13 +672,30 @@ def main():
         for _ in range(W):
             plan.run(out=out, status=status)
         torch.cuda.synchronize()
-        timer = Timer(torch)
         t0 = time.perf_counter()
         for _ in range(K):
-            timer.run(lambda: plan.run(out=out, status=status))
+            plan.run(out=out, status=status)
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
-        kern_ms = timer.mean_ms()
+        # the kernels' own time per query (the fused kernel and its finalize): a HIP graph of G
+        # back-to-back launches, replayed, with events around the replays on the graph's stream.
+        # A step here is shorter than the host's launch call, so events around single launches
+        # would measure the host's latency instead.
+        G = 50
+        reps = max(1, K // G)
+        gstream = torch.cuda.Stream()
+        with torch.cuda.stream(gstream):
+            with cx.Graph.capture(gstream) as graph:
+                for _ in range(G):
+                    plan.run(out=out, status=status, stream=gstream)
+            for _ in range(2):
+                graph.launch(gstream)
+            gstream.synchronize()
+            timer = Timer(torch)
+            timer.run(lambda: [graph.launch(gstream) for _ in range(reps)], gstream)
+        torch.cuda.synchronize()
+        cx.check_status(status)
+        kern_ms = timer.mean_ms() / (reps * G)
         lo, hi = datagen.q11_year_range(1994)
         m = (f.datekey >= lo) & (f.datekey <= hi)
         b = lines_touched(np.ones(n, bool)) * FETCH_BYTES + lines_touched(m) * FETCH_BYTES
@@ -692,7 +709,8 @@ def main():
                               "fact_rows": n})
         result["settle"] = settle_record(n_settle, args.settle)
         roof.update(kernel="crystal::star_kernel", achieved=b / (kern_ms * 1e-3) / 1e9, algorithmic_bytes=b,
-                    kernel_ms=kern_ms)
+                    kernel_ms=kern_ms, kernel_ms_covers="the fused kernel and its scalar finalize kernel, "
+                                                        "per query, from graph replays of 50 queries")
 
     elif args.workload == "select":
         n = args.rows or (1 << 29)
