@@ -111,6 +111,21 @@ def test_partition_tile_shapes(block, ipt, gpc):
         check_partition(k, v, 0, 8, with_vals=True)
 
 
+def test_partition_tuned_shape_several_tiles_per_workgroup():
+    """The tuned 1024 x 16 tile with one workgroup per CU: every workgroup
+    walks three or four tiles of its chunk, so each wave clears and reuses
+    its digit counters, and ranks a tile while other waves may still write
+    out the previous one.  Element by element against the oracle, for a
+    uniform and a two-digit key distribution."""
+    cx.tune_set(cx.K_RADIX, 1024, 16, 1)
+    n = 3 * 256 * 1024 * 16 + 5
+    k, v = pairs(n, 850)
+    announce("radix partition several tiles per workgroup", n)
+    check_partition(k, v, 8, 8, with_vals=True)
+    k2 = np.where(np.random.default_rng(851).random(n) < 0.5, 0x00000500, 0x0000FA00).astype(np.uint32)
+    check_partition(k2, v, 8, 8, with_vals=True)
+
+
 def test_partition_errors():
     announce("radix partition errors")
     k = dev(np.arange(1000, dtype=np.int32))
