@@ -606,6 +606,44 @@ __global__ __launch_bounds__(BLOCK) void shared_scan_kernel(const BatchDev batch
                                 j.g_stride;
                 }
             }
+            if (p.scalar) {
+                // The chunk's (row, query) pairs as one mask, 16 bits per row: the
+                // lanes walk their own pairs together, so the wave loops as often
+                // as its busiest lane has pairs in the chunk, not once per row for
+                // each row's busiest lane.
+                static_assert(T::VEC * 16 <= 64, "a chunk's query masks fit 64 bits");
+                uint64_t pend = 0, vals[T::VEC];
+#pragma unroll
+                for (int e = 0; e < T::VEC; ++e) {
+                    const int k = ch * T::VEC + e;
+                    const uint32_t mk = qm[k] & 0xffffu;
+                    uint64_t val = 0;
+                    if (mk) {  // only survivors' measures were loaded
+                        val = 1;
+                        if (p.agg == CRYSTAL_AGG_SUM)
+                            val = (uint64_t)(int64_t)a[k];
+                        else if (p.agg == CRYSTAL_AGG_SUM_PRODUCT)
+                            val = (uint64_t)((int64_t)a[k] * (int64_t)c[k]);
+                        else if (p.agg == CRYSTAL_AGG_SUM_DIFF)
+                            val = (uint64_t)((int64_t)a[k] - (int64_t)c[k]);
+                    }
+                    vals[e] = val;
+                    pend |= (uint64_t)mk << (16 * e);
+                }
+                while (pend) {
+                    const uint32_t bit = (uint32_t)__builtin_ctzll(pend);
+                    pend &= pend - 1u;
+                    const uint32_t e = bit >> 4, q = bit & 15u;
+                    uint64_t val = vals[0];
+#pragma unroll
+                    for (int i = 1; i < T::VEC; ++i) val = e == (uint32_t)i ? vals[i] : val;
+                    // the lane's slot: an LDS add without return
+                    __hip_atomic_fetch_add((__attribute__((address_space(3))) uint64_t *)&acc[q][lane], val,
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+                continue;
+            }
 #pragma unroll
             for (int e = 0; e < T::VEC; ++e) {
                 const int k = ch * T::VEC + e;
