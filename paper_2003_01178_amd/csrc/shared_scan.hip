@@ -607,12 +607,16 @@ __global__ __launch_bounds__(BLOCK) void shared_scan_kernel(const BatchDev batch
                 }
             }
             if (p.scalar) {
-                // The chunk's (row, query) pairs as one mask, 16 bits per row: the
-                // lanes walk their own pairs together, so the wave loops as often
-                // as its busiest lane has pairs in the chunk, not once per row for
-                // each row's busiest lane.
-                static_assert(T::VEC * 16 <= 64, "a chunk's query masks fit 64 bits");
-                uint64_t pend = 0, vals[T::VEC];
+                // The (row, query) pairs of each two rows of the chunk as one
+                // 32-bit mask, 16 bits per row: the lanes walk their own pairs
+                // together, so the wave loops as often as its busiest lane has
+                // pairs in the two rows, not once per row for each row's busiest
+                // lane, and each trip picks its row's value with one compare.
+                constexpr int HALVES = (T::VEC + 1) / 2;
+                uint64_t vals[T::VEC];
+                uint32_t pend[HALVES];
+#pragma unroll
+                for (int h = 0; h < HALVES; ++h) pend[h] = 0;
 #pragma unroll
                 for (int e = 0; e < T::VEC; ++e) {
                     const int k = ch * T::VEC + e;
@@ -628,18 +632,19 @@ __global__ __launch_bounds__(BLOCK) void shared_scan_kernel(const BatchDev batch
                             val = (uint64_t)((int64_t)a[k] - (int64_t)c[k]);
                     }
                     vals[e] = val;
-                    pend |= (uint64_t)mk << (16 * e);
+                    pend[e / 2] |= mk << (16 * (e & 1));
                 }
-                while (pend) {
-                    const uint32_t bit = (uint32_t)__builtin_ctzll(pend);
-                    pend &= pend - 1u;
-                    const uint32_t e = bit >> 4, q = bit & 15u;
-                    uint64_t val = vals[0];
 #pragma unroll
-                    for (int i = 1; i < T::VEC; ++i) val = e == (uint32_t)i ? vals[i] : val;
-                    // the lane's slot: an LDS add without return
-                    __hip_atomic_fetch_add((__attribute__((address_space(3))) uint64_t *)&acc[q][lane], val,
-                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                for (int h = 0; h < HALVES; ++h) {
+                    uint32_t pm = pend[h];
+                    const uint64_t v0 = vals[2 * h], v1 = vals[2 * h + 1 < T::VEC ? 2 * h + 1 : 2 * h];  // no bit of a missing row is set
+                    while (pm) {
+                        const uint32_t bit = (uint32_t)__builtin_ctz(pm);
+                        pm &= pm - 1u;
+                        const uint64_t val = bit >= 16u ? v1 : v0;
+                        __hip_atomic_fetch_add((__attribute__((address_space(3))) uint64_t *)&acc[bit & 15u][lane], val,
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    }
                 }
                 __builtin_amdgcn_sched_barrier(0);
                 continue;
