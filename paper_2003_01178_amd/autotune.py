@@ -2,10 +2,12 @@
 
 For each kernel, every compiled (BLOCK, IPT) variant is timed at several
 workgroups-per-CU settings on the workload it serves, with HIP events on the
-launch stream; variants whose result differs from the first variant's are
-discarded.  The winner for each workload size is written into the library's
-tuning table for the size buckets nearest to that size, and the table is
-saved as a text cache (``tune/gfx950.txt``) that ``crystal.load()`` reads.
+launch stream (around replays of a graph of calls, for the calls shorter
+than their own host-side set-up); variants whose result differs from the
+first variant's are discarded.  The winner for each workload size is
+written into the library's tuning table for the size buckets nearest to
+that size, and the table is saved as a text cache (``tune/gfx950.txt``)
+that ``crystal.load()`` reads.
 
 Usage: ``python -m paper_2003_01178_amd.autotune [--kernels star,select,...]
 [--out PATH] [--quick]``.  Prints a JSON report.  Entries of kernels that
@@ -44,12 +46,44 @@ def time_ms(fn, reps=10, warmup=2):
     return float(np.median([s.elapsed_time(e) for s, e in ev]))
 
 
+def time_graph_ms(launch, reps=10, per_graph=10):
+    """Time of one `launch(stream)` call, from replays of a HIP graph of
+    `per_graph` calls with events around each replay.  The host's work per
+    call (argument marshalling, launch latency) stays outside the events,
+    which matters when a call is shorter than that work.  The graph is
+    captured afresh, so it holds the current tuning."""
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        launch(s)
+        with cx.Graph.capture(s) as g:
+            for _ in range(per_graph):
+                launch(s)
+        g.launch(s)
+        s.synchronize()
+        ev = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(s)
+            g.launch(s)
+            b.record(s)
+            ev.append((a, b))
+    torch.cuda.synchronize()
+    g.close()
+    return float(np.median([a.elapsed_time(b) for a, b in ev])) / per_graph
+
+
 def bucket(n):
     return max(0, int(n).bit_length() - 1)
 
 
-def sweep(kernel, n, call, result_of, candidates=None, gpcs=GPCS, reps=10, log=None):
-    """Time every (block, ipt, grid_per_cu); return sorted [(ms, b, i, g)]."""
+def sweep(kernel, n, call, result_of, candidates=None, gpcs=GPCS, reps=10, log=None, launch=None):
+    """Time every (block, ipt, grid_per_cu); return sorted [(ms, b, i, g)].
+
+    call() runs the workload once for the result check; with `launch`
+    (launch(stream): the same work on the given stream, allocating nothing)
+    the timing comes from graph replays, otherwise from events around
+    single calls."""
     b0 = bucket(n)
     rows, ref = [], None
     for b, i in candidates or cx.tune_variants(kernel):
@@ -64,7 +98,7 @@ def sweep(kernel, n, call, result_of, candidates=None, gpcs=GPCS, reps=10, log=N
                 if log:
                     log(f"  discard {b}x{i} g{g}: result differs")
                 continue
-            ms = time_ms(call, reps=reps)
+            ms = time_graph_ms(launch, reps=reps) if launch else time_ms(call, reps=reps)
             rows.append((ms, b, i, g))
             if log:
                 log(f"  {kernel} n={n} {b}x{i} g{g}: {ms * 1e3:.1f} us")
@@ -110,7 +144,8 @@ def main(argv=None):
         out = torch.empty(queries.STAR_GROUPS, dtype=torch.int64, device="cuda")
         st = cx.new_status()
         rows = sweep(cx.K_STAR, n, lambda: plan.run(out=out, status=st), lambda: out.cpu().numpy(),
-                     candidates=quick_vec if args.quick else None, reps=args.reps, log=log)
+                     candidates=quick_vec if args.quick else None, reps=args.reps, log=log,
+                     launch=lambda strm: plan.run(out=out, status=st, stream=strm))
         star_results.append((n, rows[0][1:]))
         report["star_120M"] = rows[:8]
         del s, t
@@ -122,7 +157,8 @@ def main(argv=None):
         out = torch.empty(1, dtype=torch.int64, device="cuda")
         st = cx.new_status()
         rows = sweep(cx.K_STAR, n, lambda: plan.run(out=out, status=st), lambda: out.cpu().numpy(),
-                     candidates=quick_vec if args.quick else None, reps=args.reps, log=log)
+                     candidates=quick_vec if args.quick else None, reps=args.reps, log=log,
+                     launch=lambda strm: plan.run(out=out, status=st, stream=strm))
         star_results.append((n, rows[0][1:]))
         report["q11_6M"] = rows[:8]
     if star_results:
@@ -191,6 +227,7 @@ def main(argv=None):
         sv.build_q11_masks([datagen.random_q11_constants(rng) for _ in range(16)])
         outs_s = [torch.zeros(queries.STAR_GROUPS, dtype=torch.int64, device="cuda") for _ in range(16)]
         outs_q = [torch.zeros(1, dtype=torch.int64, device="cuda") for _ in range(16)]
+        st_s, st_q = cx.new_status(), cx.new_status()
 
         # grouped templates (the star template) and scalar ones (Q1.1) are
         # tuned separately: their passes differ in registers and LDS
@@ -204,12 +241,17 @@ def main(argv=None):
                 o.zero_()
             sv.q11_scan.run([[] for _ in outs_q], outs_q, 0, n)
 
+        # timed passes accumulate without the clears: each holds 16 queries' marshalling
         rows = sweep(cx.K_SHARED_SCAN, n, star_pass, lambda: np.concatenate([o.cpu().numpy() for o in outs_s]),
-                     candidates=quick_vec if args.quick else None, gpcs=(0, 1, 2, 4), reps=args.reps, log=log)
+                     candidates=quick_vec if args.quick else None, gpcs=(0, 1, 2, 4), reps=args.reps, log=log,
+                     launch=lambda strm: sv.star_scan.run([[] for _ in outs_s], outs_s, 0, n, status=st_s,
+                                                          stream=strm))
         assign(cx.K_SHARED_SCAN, [(n, rows[0][1:])])
         report["shared_star_75M_16"] = rows[:8]
         rows = sweep(cx.K_SHARED_SCAN_SCALAR, n, q11_pass, lambda: np.concatenate([o.cpu().numpy() for o in outs_q]),
-                     candidates=quick_vec if args.quick else None, gpcs=(0, 1, 2, 4), reps=args.reps, log=log)
+                     candidates=quick_vec if args.quick else None, gpcs=(0, 1, 2, 4), reps=args.reps, log=log,
+                     launch=lambda strm: sv.q11_scan.run([[] for _ in outs_q], outs_q, 0, n, status=st_q,
+                                                         stream=strm))
         assign(cx.K_SHARED_SCAN_SCALAR, [(n, rows[0][1:])])
         report["shared_q11_75M_16"] = rows[:8]
         del sv
