@@ -1,6 +1,7 @@
 """HIP-graph capture of a whole star-query step (four filtered builds plus the
-fused kernel): every replay, with eager work in between, equals the eager
-result and the oracle."""
+fused kernel) and of a scalar query: every replay, with eager work in
+between, equals the eager result and the oracle.  Also the autotuner's
+graph-replay timing of a short query."""
 import numpy as np
 import pytest
 import torch
@@ -65,3 +66,24 @@ def test_graph_replays_scalar_query():
         stream.synchronize()
         assert int(out.item()) == eager, rep
     g.close()
+
+
+def test_autotuner_graph_timing_of_a_short_query():
+    """The autotuner's graph-replay timing (a graph of ten launches of a
+    6M-row Q1.1-shaped query, re-captured per call): a positive time per
+    query well under a millisecond, the result of the replays equal to the
+    eager one, and the same candidate timed twice within a factor of two."""
+    from paper_2003_01178_amd import autotune
+    announce("autotune graph timing")
+    f = datagen.q11_fact(6_000_000, workload=54)
+    plan = queries.Q11Plan(*[queries.to_dev(c) for c in (f.datekey, f.discount, f.quantity, f.price)])
+    out = torch.zeros(1, dtype=torch.int64, device="cuda")
+    st = cx.new_status()
+    plan.run(out=out, status=st)
+    torch.cuda.synchronize()
+    eager = int(out.item())
+    times = [autotune.time_graph_ms(lambda s: plan.run(out=out, status=st, stream=s), reps=5) for _ in range(2)]
+    assert all(0.0 < t < 1.0 for t in times), times
+    assert max(times) < 2 * min(times), times
+    assert int(out.item()) == eager
+    cx.check_status(st)
